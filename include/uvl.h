@@ -1,0 +1,215 @@
+/*
+ * uvl.h - C ABI of libuvl.so: thematic layers stored as 2D texture atlases
+ * indexed by a mesh's texture coordinates, edited and queried on an AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: "An Efficient GPU Approach for Designing 3D Cultural Heritage
+ * Information Systems" (arXiv 2501.14807).  The paper keeps every layer as a
+ * data texture on the GPU (§4.2), indexes it with the mesh's texture
+ * coordinates (§4.1), and edits it with the Texture Editing Algorithm
+ * (§4.3.1): depth test against a depth texture, projective mapping of the
+ * tool through the camera, shape masking, and a write of the chosen value.
+ *
+ * Conventions shared by every call:
+ *  - Every call returns a uvl_status.  Arguments are validated on the host
+ *    before anything is enqueued; on error nothing is enqueued.  A failing
+ *    HIP launch returns UVL_E_DEVICE.  Nothing aborts the process.
+ *  - Device pointers are borrowed: the caller allocates and frees all device
+ *    memory and keeps it alive until the work on `stream` has completed.
+ *    The library never allocates device memory.
+ *  - Host arrays (centre, matrix, polygon) are read during the call and may
+ *    be freed on return.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls are asynchronous on it unless stated otherwise.
+ *  - Texel (i, j) of a W x H atlas is element j*W + i; row j holds texture
+ *    coordinate v in [j/H, (j+1)/H) and its sample is the texel centre.
+ *  - Two calls on different streams that write the same layer race; the
+ *    caller orders them.
+ */
+#ifndef UVL_H
+#define UVL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    UVL_OK = 0,
+    UVL_E_INVAL = -1,        /* null pointer, bad size, value out of range    */
+    UVL_E_SHAPE = -2,        /* layer / geometry image sizes do not match     */
+    UVL_E_DTYPE = -3,        /* unknown layer dtype or label does not fit     */
+    UVL_E_NOMEM = -4,        /* workspace too small                           */
+    UVL_E_DEVICE = -5,       /* a HIP call or kernel launch failed            */
+    UVL_E_UNSUPPORTED = -6   /* the current device is not gfx950              */
+} uvl_status;
+
+/* Layer data types (§4.2: the data texture holds 8/16/32-bit integers or
+ * 16/32-bit floats; database layers hold unsigned primary keys).  This
+ * library implements the unsigned 8- and 16-bit label layers; value 0 is
+ * the null key ("no data"), standing in for the layer's mask texture. */
+typedef enum { UVL_U8 = 1, UVL_U16 = 2 } uvl_dtype;
+
+/* Layer operations (§3.4.2: layer systems combine layers with logic
+ * operations).  See uvl_layer_op. */
+typedef enum { UVL_AND = 0, UVL_OR = 1, UVL_XOR = 2, UVL_REMAP = 3 } uvl_op;
+
+/* A triangle mesh in device memory (§4.3.1 lists vertices, normals and
+ * texture coordinates as inputs of the editing algorithm).
+ *   pos [nv][3] fp32, nrm [nv][3] fp32 (NULL: face normals are used),
+ *   uv  [nv][2] fp32 with every coordinate in [-4, 4],
+ *   tri [nt][3] int32 vertex indices in [0, nv). */
+typedef struct {
+    const float *pos;
+    const float *nrm;
+    const float *uv;
+    const int32_t *tri;
+    int64_t nv;
+    int64_t nt;
+} uvl_mesh;
+
+/* Geometry image: the mesh rendered into texture space once per model and
+ * atlas size, so that each edit reads per-texel surface data instead of
+ * re-rasterising the mesh (§4.3.1 renders the mesh with its texture
+ * coordinates as vertex positions on every edit).  Structure of arrays, one
+ * plane of N = width*height elements each, every plane pointer 16-byte
+ * aligned, all in device memory and owned by the caller:
+ *   tri_id        owning triangle, -1 where no triangle covers the centre
+ *   pos_x/y/z     surface position (fp32 of an fp64 interpolation), NaN
+ *                 where uncovered
+ *   nrm_x/y/z     unit normal, 0 where uncovered (all three NULL: skipped)
+ *   bary1/2       barycentrics of vertices 1 and 2 (both NULL: skipped)
+ *   area_w        surface area of the texel in units of area_scale, 0 where
+ *                 uncovered (uint32 fixed point)
+ * area_scale and area_abs_err are written by uvl_build_geometry_image: a
+ * texel's area is area_w * area_scale, off from the exact fp64 weight by at
+ * most area_abs_err = area_scale / 2, so a label's area over k texels is
+ * within k * area_abs_err. */
+typedef struct {
+    int32_t width, height;
+    int32_t *tri_id;
+    float *pos_x, *pos_y, *pos_z;
+    float *nrm_x, *nrm_y, *nrm_z;
+    float *bary1, *bary2;
+    uint32_t *area_w;
+    double area_scale;      /* out: texel area = area_w * area_scale            */
+    double area_abs_err;    /* out: bound on the rounding of one texel's area   */
+} uvl_geom;
+
+/* A layer's data texture: width*height values of `dtype`, device memory,
+ * 16-byte aligned, row-major as above (§4.2 "data texture"). */
+typedef struct {
+    void *data;
+    int32_t width, height;
+    int32_t dtype;          /* uvl_dtype */
+} uvl_layer;
+
+/* Text for a status code (static storage). */
+const char *uvl_status_str(int32_t status);
+
+/* Returns UVL_OK if the current HIP device is a gfx950, else
+ * UVL_E_UNSUPPORTED (or UVL_E_DEVICE if HIP fails). */
+int32_t uvl_device_check(void);
+
+/* Workspace bytes uvl_build_geometry_image needs for a mesh of nt
+ * triangles. */
+size_t uvl_build_workspace_bytes(int64_t nt);
+
+/* Render the mesh into texture space (§4.3.1, the texture-space render with
+ * texture coordinates as positions; §4.1, texture coordinates index the
+ * layer).  For each texel centre: the covering triangle (coordinates snapped
+ * to 1/256 texel, round half to even; a centre on an edge belongs to the
+ * triangle whose counter-clockwise edge s->t has t.y < s.y, or t.y == s.y and
+ * t.x > s.x; the lowest triangle index wins where triangles overlap;
+ * zero-area triangles cover nothing), its barycentrics b_k = e_k/|E| from the
+ * exact integer edge functions, position b0 P0 + b1 P1 + b2 P2 summed left to
+ * right in fp64 and rounded to fp32, unit normal, and area weight
+ * 131072 * A3 / |E| (A3 the triangle's 3D area) quantised to uint32 with a
+ * power-of-two scale.
+ * ws: device workspace of uvl_build_workspace_bytes(nt) bytes.
+ * SYNCHRONOUS: waits for `stream` to read back area_scale.
+ * mesh->tri may be NULL when nt == 0 (every texel is then uncovered).
+ * Errors: UVL_E_INVAL for null planes, width/height outside [1, 32768],
+ * a texture coordinate outside [-4, 4] or a vertex index outside [0, nv)
+ * (the planes are then undefined); UVL_E_NOMEM if ws_bytes is too small. */
+int32_t uvl_build_geometry_image(const uvl_mesh *mesh, uvl_geom *geom, void *ws, size_t ws_bytes,
+                                 void *stream);
+
+/* Validate a layer descriptor and fill its data with 0 (the null key). */
+int32_t uvl_create_layer(const uvl_layer *layer, void *stream);
+
+/* Workspace bytes uvl_render_depth needs for a mesh of nt triangles. */
+size_t uvl_depth_workspace_bytes(int64_t nt);
+
+/* Depth texture of the scene from a camera (§4.3.1: scene depth from the
+ * current viewpoint, rebuilt when the viewpoint changes).  view_proj: host
+ * fp32 row-major 4x4 with clip = M [x y z 1]^T.  depth: device fp32 [dh][dw],
+ * row 0 at NDC y = -1, window depth 0.5 z_ndc + 0.5, cleared to 1.0; each
+ * pixel keeps the nearest sample of the triangles whose three vertices have
+ * clip w > 0 and |x_ndc|, |y_ndc| <= 16, rasterised with the rule of
+ * uvl_build_geometry_image on screen positions fmaf(ndc, .5, .5) * size and
+ * interpolated in fp64; samples outside [0, 1] are dropped.
+ * Errors: UVL_E_INVAL for null pointers or dw/dh outside [1, 16384];
+ * UVL_E_NOMEM if ws_bytes is too small. */
+int32_t uvl_render_depth(const uvl_mesh *mesh, const float view_proj[16], float *depth, int32_t dw,
+                         int32_t dh, void *ws, size_t ws_bytes, void *stream);
+
+/* Surface brush (§4.3.1 selects part of the surface and stores the chosen
+ * value in the selected texels; here the tool is a 3D ball).  Every texel
+ * whose position p satisfies, in fp32,
+ *   fmaf(dz, dz, fmaf(dy, dy, dx*dx)) <= r*r,   d = p - centre,
+ * gets `label` (uncovered texels hold NaN and never match).  center: host
+ * float[3].  Errors: UVL_E_INVAL (null, radius negative or not finite),
+ * UVL_E_SHAPE (layer size != geometry size), UVL_E_DTYPE (label too wide). */
+int32_t uvl_edit_brush(const uvl_geom *geom, const uvl_layer *layer, const float center[3],
+                       float radius, uint32_t label, void *stream);
+
+/* Lasso (§4.3.1: depth test with a small bias, projective mapping through
+ * the camera with coordinates outside the unit range discarded, then the
+ * tool shape mask).  Per texel, in fp32 with fmaf and IEEE division:
+ *   clip = M p (fmaf chains); require clip.w > 0 and x, y, z_ndc in [-1, 1];
+ *   ix = min(floor(fmaf(x_ndc, .5, .5) * dw), dw-1), iy likewise;
+ *   require fmaf(z_ndc, .5, .5) <= depth[iy*dw + ix] + bias;
+ *   require (x_ndc, y_ndc) inside the polygon by the even-odd crossing rule
+ *   (an edge counts when exactly one end is above y_ndc and the crossing lies
+ *   to the right of x_ndc);
+ * then writes `label`.  poly_xy: host float[n][2] in NDC, 3 <= n <= 64.
+ * depth: device map from uvl_render_depth with the same matrix.
+ * Errors: UVL_E_INVAL (null, n out of range, bias not finite, dw/dh < 1),
+ * UVL_E_SHAPE, UVL_E_DTYPE as for uvl_edit_brush. */
+int32_t uvl_edit_lasso(const uvl_geom *geom, const uvl_layer *layer, const float view_proj[16],
+                       const float *poly_xy, int32_t n, const float *depth, int32_t dw, int32_t dh,
+                       float bias, uint32_t label, void *stream);
+
+/* Layer algebra (§3.4.2: logic operations between layers; §4.2: database
+ * layers hold unsigned keys).  Operand predicate P_X = (sel_X == 0 ?
+ * X != 0 : X == sel_X).  AND / OR / XOR: dst = (P_a op P_b) ? out_label : 0.
+ * REMAP: dst = a ? lut[a] : 0, lut a DEVICE array of 256 (a is u8) or 65536
+ * (a is u16) uint16 entries, each of which must fit dst's dtype (wider
+ * entries are truncated to dst's width); b, sel_a, sel_b, out_label are
+ * ignored.  dst may alias a or b; all three must have the same size; their
+ * dtypes may differ.  Errors: UVL_E_INVAL, UVL_E_SHAPE, UVL_E_DTYPE
+ * (out_label does not fit dst). */
+int32_t uvl_layer_op(int32_t op, const uvl_layer *dst, const uvl_layer *a, const uvl_layer *b,
+                     uint32_t sel_a, uint32_t sel_b, uint32_t out_label, const uint16_t *lut,
+                     void *stream);
+
+/* Per-label surface area (Table 1 reports the surface area one texel
+ * represents; summed over the texels holding a label it gives the labelled
+ * area).  For each of nlayers layers (1..32, same size as geom): bins[l] =
+ * sum of area_w over covered texels with value l, exact uint64; layer k's
+ * 256 (u8) or 65536 (u16) bins follow layer k-1's in bins_dev (device).
+ * If areas_host is non-NULL the call is SYNCHRONOUS and writes
+ * areas_host[b] = bins[b] * area_scale (fp64, same layout); otherwise it is
+ * asynchronous and the bins stay on the device.
+ * Errors: UVL_E_INVAL, UVL_E_SHAPE, UVL_E_DTYPE. */
+int32_t uvl_area_query(const uvl_geom *geom, const uvl_layer *layers, int32_t nlayers,
+                       uint64_t *bins_dev, double *areas_host, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UVL_H */

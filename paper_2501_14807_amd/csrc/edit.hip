@@ -1,0 +1,195 @@
+// Plain edit path of libuvl: one launch per brush or lasso edit.
+//
+// The paper's per-edit pass touches every texel of the layer (§4.3.1, and
+// §5: the edit time does not depend on the tool size).  Here each edit is one
+// streaming pass over the geometry image's position planes: 12 bytes read per
+// texel, one label store per selected texel, no read of the layer.
+//
+// Tiling: a 256-thread workgroup owns 4096 consecutive texels as 4 chunks of
+// 1024; lane l of chunk c reads texels [c*1024 + 4l, c*1024 + 4l + 4) of each
+// plane as one 16-byte load, so a wave's loads are 1 KiB contiguous per
+// plane.  All 12 loads of a thread are issued before any predicate.
+#include <math.h>
+
+#include "edit_texel.h"
+#include "uvl_internal.h"
+
+namespace uvl {
+namespace {
+
+constexpr int kChunk = kBlock * 4;        // texels per chunk
+constexpr int kTile = 4 * kChunk;         // texels per workgroup
+
+template <typename T>
+__device__ __forceinline__ void store4(T *__restrict__ L, int64_t t, bool s0, bool s1, bool s2, bool s3, T label);
+
+template <>
+__device__ __forceinline__ void store4<uint8_t>(uint8_t *__restrict__ L, int64_t t, bool s0, bool s1, bool s2,
+                                                bool s3, uint8_t label) {
+    if (s0 && s1 && s2 && s3) {
+        *reinterpret_cast<uint32_t *>(L + t) = 0x01010101u * label;
+    } else {
+        if (s0) L[t] = label;
+        if (s1) L[t + 1] = label;
+        if (s2) L[t + 2] = label;
+        if (s3) L[t + 3] = label;
+    }
+}
+
+template <>
+__device__ __forceinline__ void store4<uint16_t>(uint16_t *__restrict__ L, int64_t t, bool s0, bool s1, bool s2,
+                                                 bool s3, uint16_t label) {
+    if (s0 && s1 && s2 && s3) {
+        const uint32_t v = 0x00010001u * label;
+        *reinterpret_cast<uint2 *>(L + t) = make_uint2(v, v);
+    } else {
+        if (s0) L[t] = label;
+        if (s1) L[t + 1] = label;
+        if (s2) L[t + 2] = label;
+        if (s3) L[t + 3] = label;
+    }
+}
+
+struct BrushOp {
+    BrushParams p;
+    __device__ __forceinline__ bool operator()(float x, float y, float z) const { return brush_texel(p, x, y, z); }
+};
+
+struct LassoOp {
+    const LassoParams *p;
+    const float *depth;
+    __device__ __forceinline__ bool operator()(float x, float y, float z) const {
+        return lasso_texel(*p, depth, x, y, z);
+    }
+};
+
+template <typename T, typename Op>
+__device__ __forceinline__ void edit_tile(const float *__restrict__ px, const float *__restrict__ py,
+                                          const float *__restrict__ pz, T *__restrict__ L, int64_t n, Op op,
+                                          T label) {
+    const int64_t base = (int64_t)blockIdx.x * kTile + threadIdx.x * 4;
+    if (base + 3 * kChunk + 4 <= n) {
+        float4 X[4], Y[4], Z[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            X[c] = *reinterpret_cast<const float4 *>(px + base + c * kChunk);
+            Y[c] = *reinterpret_cast<const float4 *>(py + base + c * kChunk);
+            Z[c] = *reinterpret_cast<const float4 *>(pz + base + c * kChunk);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const bool s0 = op(X[c].x, Y[c].x, Z[c].x);
+            const bool s1 = op(X[c].y, Y[c].y, Z[c].y);
+            const bool s2 = op(X[c].z, Y[c].z, Z[c].z);
+            const bool s3 = op(X[c].w, Y[c].w, Z[c].w);
+            store4<T>(L, base + c * kChunk, s0, s1, s2, s3, label);
+        }
+    } else {
+        for (int c = 0; c < 4; ++c)
+            for (int k = 0; k < 4; ++k) {
+                const int64_t t = base + c * kChunk + k;
+                if (t < n && op(px[t], py[t], pz[t])) L[t] = label;
+            }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_brush(const float *__restrict__ px, const float *__restrict__ py,
+                                                  const float *__restrict__ pz, T *__restrict__ L, int64_t n,
+                                                  BrushParams p, uint32_t label) {
+    edit_tile<T>(px, py, pz, L, n, BrushOp{p}, (T)label);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lasso(const float *__restrict__ px, const float *__restrict__ py,
+                                                  const float *__restrict__ pz, T *__restrict__ L, int64_t n,
+                                                  LassoParams p, const float *__restrict__ depth,
+                                                  uint32_t label) {
+    edit_tile<T>(px, py, pz, L, n, LassoOp{&p, depth}, (T)label);
+}
+
+int32_t check_edit(const uvl_geom *g, const uvl_layer *l, uint32_t label) {
+    if (!geom_pos_ok(g) || !layer_ok(l)) return UVL_E_INVAL;
+    if (!dtype_ok(l->dtype)) return UVL_E_DTYPE;
+    if (label > dtype_max(l->dtype)) return UVL_E_DTYPE;
+    if (l->width != g->width || l->height != g->height) return UVL_E_SHAPE;
+    return device_ok();
+}
+
+}  // namespace
+
+// Host-side preparation of a lasso's kernel parameters; also used by the
+// batched wave path.  Returns false for an invalid polygon.
+bool make_lasso_params(const float view_proj[16], const float *poly, int32_t n, int32_t dw, int32_t dh,
+                       float bias, LassoParams &p) {
+    if (n < 3 || n > kMaxPoly || !poly || !view_proj || dw < 1 || dh < 1 || !std::isfinite(bias)) return false;
+    for (int k = 0; k < 16; ++k) p.M[k] = view_proj[k];
+    p.bias = bias;
+    p.dw = dw;
+    p.dh = dh;
+    p.n = n;
+    float ylo = INFINITY, yhi = -INFINITY, xhi = -INFINITY;
+    for (int k = 0; k < n; ++k) {
+        const float x0 = poly[2 * k], y0 = poly[2 * k + 1];
+        const float x1 = poly[2 * ((k + 1) % n)], y1 = poly[2 * ((k + 1) % n) + 1];
+        if (!std::isfinite(x0) || !std::isfinite(y0)) return false;
+        const float dx = x1 - x0, dy = y1 - y0;
+        const bool up = y1 > y0;
+        p.x0[k] = x0;
+        p.y0[k] = y0;
+        p.y1[k] = y1;
+        p.sdx[k] = up ? dx : -dx;
+        p.sdy[k] = up ? dy : -dy;
+        ylo = fminf(ylo, y0);
+        yhi = fmaxf(yhi, y0);
+        xhi = fmaxf(xhi, x0);
+    }
+    for (int k = n; k < kMaxPoly; ++k) p.x0[k] = p.y0[k] = p.y1[k] = p.sdx[k] = p.sdy[k] = 0.0f;
+    p.ylo = ylo;
+    p.yhi = yhi;
+    p.xhi = xhi;
+    return true;
+}
+
+}  // namespace uvl
+
+using namespace uvl;
+
+extern "C" int32_t uvl_edit_brush(const uvl_geom *geom, const uvl_layer *layer, const float center[3],
+                                  float radius, uint32_t label, void *stream) {
+    if (!center || !(radius >= 0.0f) || !std::isfinite(radius)) return UVL_E_INVAL;
+    if (!std::isfinite(center[0]) || !std::isfinite(center[1]) || !std::isfinite(center[2])) return UVL_E_INVAL;
+    if (int32_t s = check_edit(geom, layer, label)) return s;
+    const int64_t n = (int64_t)geom->width * geom->height;
+    BrushParams p{center[0], center[1], center[2], radius * radius};
+    const dim3 grid((unsigned)ceil_div(n, kTile));
+    hipStream_t s = as_stream(stream);
+    if (layer->dtype == UVL_U8)
+        hipLaunchKernelGGL(k_brush<uint8_t>, grid, dim3(kBlock), 0, s, geom->pos_x, geom->pos_y, geom->pos_z,
+                           static_cast<uint8_t *>(layer->data), n, p, label);
+    else
+        hipLaunchKernelGGL(k_brush<uint16_t>, grid, dim3(kBlock), 0, s, geom->pos_x, geom->pos_y, geom->pos_z,
+                           static_cast<uint16_t *>(layer->data), n, p, label);
+    return launch_status();
+}
+
+extern "C" int32_t uvl_edit_lasso(const uvl_geom *geom, const uvl_layer *layer, const float view_proj[16],
+                                  const float *poly_xy, int32_t n, const float *depth, int32_t dw, int32_t dh,
+                                  float bias, uint32_t label, void *stream) {
+    if (!depth || dw > kMaxDepthSide || dh > kMaxDepthSide) return UVL_E_INVAL;
+    LassoParams p;
+    if (!make_lasso_params(view_proj, poly_xy, n, dw, dh, bias, p)) return UVL_E_INVAL;
+    for (int k = 0; k < 16; ++k)
+        if (!std::isfinite(view_proj[k])) return UVL_E_INVAL;
+    if (int32_t s = check_edit(geom, layer, label)) return s;
+    const int64_t N = (int64_t)geom->width * geom->height;
+    const dim3 grid((unsigned)ceil_div(N, kTile));
+    hipStream_t s = as_stream(stream);
+    if (layer->dtype == UVL_U8)
+        hipLaunchKernelGGL(k_lasso<uint8_t>, grid, dim3(kBlock), 0, s, geom->pos_x, geom->pos_y, geom->pos_z,
+                           static_cast<uint8_t *>(layer->data), N, p, depth, label);
+    else
+        hipLaunchKernelGGL(k_lasso<uint16_t>, grid, dim3(kBlock), 0, s, geom->pos_x, geom->pos_y, geom->pos_z,
+                           static_cast<uint16_t *>(layer->data), N, p, depth, label);
+    return launch_status();
+}

@@ -1,0 +1,50 @@
+// Internal helpers shared by the libuvl translation units (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "uvl.h"
+
+namespace uvl {
+
+constexpr int kBlock = 256;                 // threads per workgroup (4 waves of 64)
+constexpr int32_t kMaxSide = 32768;         // atlas side limit (2^30 texels, int32-safe products)
+constexpr int32_t kMaxDepthSide = 16384;    // depth map side limit
+constexpr int32_t kEmptyOwner = 0x7fffffff; // tri_id value before ownership resolves
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Cached gfx950 check of the current device.
+int32_t device_ok();
+
+// Status after a batch of launches: UVL_E_DEVICE if the last launch failed.
+inline int32_t launch_status() {
+    return hipGetLastError() == hipSuccess ? UVL_OK : UVL_E_DEVICE;
+}
+
+inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline bool dtype_ok(int32_t dt) { return dt == UVL_U8 || dt == UVL_U16; }
+
+inline uint32_t dtype_max(int32_t dt) { return dt == UVL_U8 ? 0xffu : 0xffffu; }
+
+inline bool layer_ok(const uvl_layer *l) {
+    return l && l->data && l->width >= 1 && l->height >= 1 && l->width <= kMaxSide &&
+           l->height <= kMaxSide && aligned16(l->data);
+}
+
+// The position planes every edit reads.
+inline bool geom_pos_ok(const uvl_geom *g) {
+    return g && g->width >= 1 && g->height >= 1 && g->width <= kMaxSide && g->height <= kMaxSide &&
+           g->pos_x && g->pos_y && g->pos_z && aligned16(g->pos_x) && aligned16(g->pos_y) &&
+           aligned16(g->pos_z);
+}
+
+// Fills (device kernels in fill.hip); safe inside graph capture.
+void fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+void fill_bytes(void *p, int64_t nbytes, hipStream_t s);   // zero
+
+}  // namespace uvl

@@ -1,0 +1,112 @@
+"""A model resident on the device: mesh, geometry image, layers, depth maps.
+
+This is the plain path (one launch per edit), driving the C entry points in
+the order the paper's system uses them (§4: structures live on the GPU; the
+host only issues commands): build the geometry image once, then for each edit
+render the depth texture if the camera changed (§4.3.1) and launch the edit;
+layer operations and per-label areas run on the same stream.
+
+Edits are duck-typed: ``kind`` ('brush' | 'lasso'), ``layer``, ``label``,
+and ``centre``/``radius`` (brush) or ``camera``/``poly`` (lasso).
+"""
+
+from __future__ import annotations
+
+from collections import OrderedDict
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import uvl
+
+
+class Model:
+    def __init__(self, mesh, width: int, height: int, layer_dtypes: Sequence[int], depth_w: int = 256,
+                 depth_h: int = 256, bias: float = 1e-4, normals: bool = True, bary: bool = True,
+                 device="cuda", depth_cache: int = 2):
+        self.mesh = uvl.DeviceMesh.from_mesh(mesh, device=device)
+        self.geom = uvl.GeometryImage(width, height, normals=normals, bary=bary, device=device)
+        self.layers: List[uvl.Layer] = [uvl.Layer(width, height, dt, device=device) for dt in layer_dtypes]
+        self.depth_w, self.depth_h, self.bias = int(depth_w), int(depth_h), float(bias)
+        self.device = device
+        self.build_ws = torch.empty(uvl.lib().uvl_build_workspace_bytes(self.mesh.nt), dtype=torch.uint8,
+                                    device=device)
+        self.depth_ws = uvl.depth_workspace(self.mesh)
+        self._depth: "OrderedDict[int, torch.Tensor]" = OrderedDict()
+        self._depth_cap = max(1, depth_cache)
+        self._luts = {}
+        self.bins = torch.empty(uvl.nbins(self.layers), dtype=torch.int64, device=device)
+
+    @classmethod
+    def from_workload(cls, wl, **kw):
+        return cls(wl.mesh, wl.W, wl.H, wl.layer_dtypes, wl.depth_w, wl.depth_h, wl.bias, **kw)
+
+    # -- set-up -----------------------------------------------------------
+    def build(self):
+        uvl.build_geometry_image(self.mesh, self.geom, self.build_ws)
+        self.clear_layers()
+        return self
+
+    def clear_layers(self):
+        for l in self.layers:
+            uvl.create_layer(l)
+        self._depth.clear()
+
+    # -- depth textures -----------------------------------------------------
+    def depth_for(self, cam_id: int, view_proj) -> torch.Tensor:
+        d = self._depth.get(cam_id)
+        if d is not None:
+            self._depth.move_to_end(cam_id)
+            return d
+        if len(self._depth) >= self._depth_cap:
+            _, d = self._depth.popitem(last=False)
+        else:
+            d = torch.empty((self.depth_h, self.depth_w), dtype=torch.float32, device=self.device)
+        uvl.render_depth(self.mesh, view_proj, d, self.depth_ws)
+        self._depth[cam_id] = d
+        return d
+
+    # -- edits ----------------------------------------------------------------
+    def apply(self, e, cameras):
+        layer = self.layers[e.layer]
+        if e.kind == "brush":
+            uvl.edit_brush(self.geom, layer, e.centre, e.radius, e.label)
+        else:
+            M = cameras[e.camera]
+            d = self.depth_for(e.camera, M)
+            uvl.edit_lasso(self.geom, layer, M, e.poly, d, self.bias, e.label)
+
+    def apply_all(self, edits, cameras):
+        for e in edits:
+            self.apply(e, cameras)
+
+    # -- layer algebra ---------------------------------------------------------
+    def upload_luts(self, ops):
+        for o in ops:
+            if o.lut is not None and id(o) not in self._luts:
+                self._luts[id(o)] = torch.from_numpy(np.ascontiguousarray(o.lut, dtype=np.uint16)).to(
+                    self.device)
+
+    def apply_op(self, o):
+        lut = None
+        if o.lut is not None:
+            if id(o) not in self._luts:
+                self.upload_luts([o])
+            lut = self._luts[id(o)]
+        b = None if o.op == uvl.REMAP else self.layers[o.b]
+        uvl.layer_op(o.op, self.layers[o.dst], self.layers[o.a], b, o.sel_a, o.sel_b, o.out_label, lut)
+
+    # -- queries -------------------------------------------------------------
+    def areas(self, sync: bool = True, layers: Optional[Sequence[int]] = None):
+        ls = self.layers if layers is None else [self.layers[k] for k in layers]
+        bins = self.bins if layers is None else None
+        return uvl.area_query(self.geom, ls, bins=bins, sync=sync)
+
+    def run(self, wl):
+        """One full pass of a workload: geometry image, edits, operations, areas."""
+        self.build()
+        self.apply_all(wl.edits, wl.cameras)
+        for o in wl.ops:
+            self.apply_op(o)
+        return self.areas()

@@ -1,0 +1,319 @@
+"""Python binding of libuvl.so (argument marshalling only).
+
+Every step of the layer method runs in the HIP kernels behind the C ABI
+declared in include/uvl.h; this module passes torch device pointers, host
+parameter arrays and the current HIP stream through ctypes, and turns status
+codes into exceptions.  PyTorch provides device memory and streams only.
+There is no CPU fallback: if libuvl.so is missing the import fails.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libuvl.so")
+
+U8, U16 = 1, 2
+AND, OR, XOR, REMAP = 0, 1, 2, 3
+
+STATUS = {0: "UVL_OK", -1: "UVL_E_INVAL", -2: "UVL_E_SHAPE", -3: "UVL_E_DTYPE",
+          -4: "UVL_E_NOMEM", -5: "UVL_E_DEVICE", -6: "UVL_E_UNSUPPORTED"}
+
+
+class UvlError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {STATUS.get(code, code)} ({_lib().uvl_status_str(code).decode()})")
+
+
+class CMesh(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("nrm", ctypes.c_void_p), ("uv", ctypes.c_void_p),
+                ("tri", ctypes.c_void_p), ("nv", ctypes.c_int64), ("nt", ctypes.c_int64)]
+
+
+class CGeom(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("tri_id", ctypes.c_void_p),
+                ("pos_x", ctypes.c_void_p), ("pos_y", ctypes.c_void_p), ("pos_z", ctypes.c_void_p),
+                ("nrm_x", ctypes.c_void_p), ("nrm_y", ctypes.c_void_p), ("nrm_z", ctypes.c_void_p),
+                ("bary1", ctypes.c_void_p), ("bary2", ctypes.c_void_p),
+                ("area_w", ctypes.c_void_p),
+                ("area_scale", ctypes.c_double), ("area_abs_err", ctypes.c_double)]
+
+
+class CLayer(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("dtype", ctypes.c_int32)]
+
+
+_L = None
+
+# exported names and ctypes signatures; the CPU tests check that include/uvl.h
+# declares exactly these
+_P, _I32, _I64, _U32, _F32, _SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                   ctypes.c_float, ctypes.c_size_t)
+SIGNATURES = {
+    "uvl_status_str": ([_I32], ctypes.c_char_p),
+    "uvl_device_check": ([], _I32),
+    "uvl_build_workspace_bytes": ([_I64], _SZ),
+    "uvl_build_geometry_image": ([_P, _P, _P, _SZ, _P], _I32),
+    "uvl_create_layer": ([_P, _P], _I32),
+    "uvl_depth_workspace_bytes": ([_I64], _SZ),
+    "uvl_render_depth": ([_P, _P, _P, _I32, _I32, _P, _SZ, _P], _I32),
+    "uvl_edit_brush": ([_P, _P, _P, _F32, _U32, _P], _I32),
+    "uvl_edit_lasso": ([_P, _P, _P, _P, _I32, _P, _I32, _I32, _F32, _U32, _P], _I32),
+    "uvl_layer_op": ([_I32, _P, _P, _P, _U32, _U32, _U32, _P, _P], _I32),
+    "uvl_area_query": ([_P, _P, _I32, _P, _P, _P], _I32),
+}
+
+
+def _lib():
+    global _L
+    if _L is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2501_14807_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _L = L
+    return _L
+
+
+def lib():
+    """The loaded libuvl.so (ctypes.CDLL)."""
+    return _lib()
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise UvlError(code, where)
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _f32(a, n=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} floats, got {a.size}")
+    return a
+
+
+def _pad(n: int, q: int = 64) -> int:
+    return (n + q - 1) // q * q
+
+
+def device_check():
+    _check(_lib().uvl_device_check(), "uvl_device_check")
+
+
+# ---------------------------------------------------------------------------
+# device objects
+
+
+class DeviceMesh:
+    """A triangle mesh resident in device memory (fp32 pos/nrm/uv, int32 tri)."""
+
+    def __init__(self, pos, uv, tri, nrm=None, device="cuda"):
+        def dev(a, dt):
+            if isinstance(a, torch.Tensor):
+                return a.to(device=device, dtype=dt).contiguous()
+            return torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt).contiguous()
+        self.pos = dev(pos, torch.float32).reshape(-1, 3)
+        self.uv = dev(uv, torch.float32).reshape(-1, 2)
+        self.tri = dev(tri, torch.int32).reshape(-1, 3)
+        self.nrm = None if nrm is None else dev(nrm, torch.float32).reshape(-1, 3)
+        self.c = CMesh(self.pos.data_ptr(), None if self.nrm is None else self.nrm.data_ptr(),
+                       self.uv.data_ptr(), self.tri.data_ptr(), self.pos.shape[0], self.tri.shape[0])
+
+    @classmethod
+    def from_mesh(cls, m, device="cuda", normals=True):
+        return cls(m.pos, m.uv, m.tri, m.nrm if normals else None, device)
+
+    @property
+    def nt(self) -> int:
+        return int(self.tri.shape[0])
+
+
+class GeometryImage:
+    """Per-texel triangle id, position, normal, barycentrics and area weight.
+
+    Planes are rows of padded tensors so that each starts 16-byte aligned.
+    """
+
+    def __init__(self, width: int, height: int, normals: bool = True, bary: bool = True,
+                 device="cuda"):
+        self.width, self.height = int(width), int(height)
+        n = self.width * self.height
+        self.n = n
+        p = _pad(n)
+        self.tri_id = torch.empty(p, dtype=torch.int32, device=device)
+        self.pos = torch.empty((3, p), dtype=torch.float32, device=device)
+        self.nrm = torch.empty((3, p), dtype=torch.float32, device=device) if normals else None
+        self.bary = torch.empty((2, p), dtype=torch.float32, device=device) if bary else None
+        self.area_w = torch.empty(p, dtype=torch.int32, device=device)   # uint32 bits
+        self.c = CGeom()
+        self.c.width, self.c.height = self.width, self.height
+        self.c.tri_id = self.tri_id.data_ptr()
+        self.c.pos_x, self.c.pos_y, self.c.pos_z = (self.pos[k].data_ptr() for k in range(3))
+        if normals:
+            self.c.nrm_x, self.c.nrm_y, self.c.nrm_z = (self.nrm[k].data_ptr() for k in range(3))
+        if bary:
+            self.c.bary1, self.c.bary2 = self.bary[0].data_ptr(), self.bary[1].data_ptr()
+        self.c.area_w = self.area_w.data_ptr()
+        self.c.area_scale = 0.0
+        self.c.area_abs_err = 0.0
+
+    @property
+    def area_scale(self) -> float:
+        return float(self.c.area_scale)
+
+    @property
+    def area_abs_err(self) -> float:
+        return float(self.c.area_abs_err)
+
+    def nbytes(self) -> int:
+        ts = [self.tri_id, self.pos, self.nrm, self.bary, self.area_w]
+        return sum(t.numel() * t.element_size() for t in ts if t is not None)
+
+    # host copies of the first n elements of each plane
+    def host(self):
+        n = self.n
+        out = {"tri_id": self.tri_id[:n].cpu().numpy(), "pos": self.pos[:, :n].cpu().numpy(),
+               "area_w": self.area_w[:n].cpu().numpy().view(np.uint32)}
+        if self.nrm is not None:
+            out["nrm"] = self.nrm[:, :n].cpu().numpy()
+        if self.bary is not None:
+            out["bary"] = self.bary[:, :n].cpu().numpy()
+        return out
+
+
+class Layer:
+    """A layer's data texture: width*height uint8 or uint16 labels on the device."""
+
+    def __init__(self, width: int, height: int, dtype: int = U8, device="cuda", data=None):
+        self.width, self.height, self.dtype = int(width), int(height), int(dtype)
+        n = self.width * self.height
+        if data is None:
+            tdt = torch.uint8 if dtype == U8 else torch.uint16
+            data = torch.empty(_pad(n), dtype=tdt, device=device)
+        self.data = data
+        self.c = CLayer(data.data_ptr(), self.width, self.height, self.dtype)
+
+    @property
+    def n(self) -> int:
+        return self.width * self.height
+
+    def numpy(self) -> np.ndarray:
+        return self.data[:self.n].cpu().numpy()
+
+    def copy_from(self, arr: np.ndarray):
+        t = torch.from_numpy(np.ascontiguousarray(arr))
+        self.data[:self.n].copy_(t.to(self.data.dtype))
+
+
+# ---------------------------------------------------------------------------
+# the C entry points, one function each
+
+
+def build_geometry_image(mesh: DeviceMesh, geom: GeometryImage, workspace: Optional[torch.Tensor] = None,
+                         stream=None) -> GeometryImage:
+    L = _lib()
+    need = L.uvl_build_workspace_bytes(mesh.nt)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=mesh.pos.device)
+    _check(L.uvl_build_geometry_image(ctypes.byref(mesh.c), ctypes.byref(geom.c), _ptr(workspace),
+                                      workspace.numel(), _stream(stream)), "uvl_build_geometry_image")
+    return geom
+
+
+def create_layer(layer: Layer, stream=None) -> Layer:
+    _check(_lib().uvl_create_layer(ctypes.byref(layer.c), _stream(stream)), "uvl_create_layer")
+    return layer
+
+
+def depth_workspace(mesh: DeviceMesh) -> torch.Tensor:
+    return torch.empty(_lib().uvl_depth_workspace_bytes(mesh.nt), dtype=torch.uint8, device=mesh.pos.device)
+
+
+def render_depth(mesh: DeviceMesh, view_proj, depth: torch.Tensor, workspace: Optional[torch.Tensor] = None,
+                 stream=None) -> torch.Tensor:
+    M = _f32(view_proj, 16)
+    dh, dw = depth.shape
+    if workspace is None:
+        workspace = depth_workspace(mesh)
+    _check(_lib().uvl_render_depth(ctypes.byref(mesh.c), M.ctypes.data_as(ctypes.c_void_p), _ptr(depth),
+                                   dw, dh, _ptr(workspace), workspace.numel(), _stream(stream)),
+           "uvl_render_depth")
+    return depth
+
+
+def edit_brush(geom: GeometryImage, layer: Layer, center, radius: float, label: int, stream=None):
+    c = _f32(center, 3)
+    _check(_lib().uvl_edit_brush(ctypes.byref(geom.c), ctypes.byref(layer.c), c.ctypes.data_as(ctypes.c_void_p),
+                                 float(np.float32(radius)), int(label), _stream(stream)), "uvl_edit_brush")
+
+
+def edit_lasso(geom: GeometryImage, layer: Layer, view_proj, poly, depth: torch.Tensor, bias: float, label: int,
+               stream=None):
+    M = _f32(view_proj, 16)
+    P = _f32(poly).reshape(-1)
+    dh, dw = depth.shape
+    _check(_lib().uvl_edit_lasso(ctypes.byref(geom.c), ctypes.byref(layer.c), M.ctypes.data_as(ctypes.c_void_p),
+                                 P.ctypes.data_as(ctypes.c_void_p), P.size // 2, _ptr(depth), dw, dh,
+                                 float(np.float32(bias)), int(label), _stream(stream)), "uvl_edit_lasso")
+
+
+def layer_op(op: int, dst: Layer, a: Layer, b: Optional[Layer] = None, sel_a: int = 0, sel_b: int = 0,
+             out_label: int = 0, lut: Optional[torch.Tensor] = None, stream=None):
+    """lut: device uint16 tensor of 256 / 65536 entries (REMAP only)."""
+    if op == REMAP:
+        need = 256 if a.dtype == U8 else 65536
+        if lut is None or lut.dtype != torch.uint16 or not lut.is_cuda or lut.numel() < need:
+            raise ValueError(f"REMAP needs a device uint16 lut of {need} entries")
+    _check(_lib().uvl_layer_op(int(op), ctypes.byref(dst.c), ctypes.byref(a.c),
+                               None if b is None else ctypes.byref(b.c), int(sel_a), int(sel_b),
+                               int(out_label), _ptr(lut), _stream(stream)), "uvl_layer_op")
+
+
+def nbins(layers: Sequence[Layer]) -> int:
+    return sum(256 if l.dtype == U8 else 65536 for l in layers)
+
+
+def area_query(geom: GeometryImage, layers: Sequence[Layer], bins: Optional[torch.Tensor] = None,
+               sync: bool = True, stream=None):
+    """Per-label areas of each layer.
+
+    sync=True: returns a list of fp64 numpy arrays (256 or 65536 bins each).
+    sync=False: returns the device uint64 bins tensor (asynchronous).
+    """
+    arr = (CLayer * len(layers))(*[l.c for l in layers])
+    nb = nbins(layers)
+    if bins is None:
+        bins = torch.empty(nb, dtype=torch.int64, device=layers[0].data.device)
+    host = np.empty(nb, np.float64) if sync else None
+    _check(_lib().uvl_area_query(ctypes.byref(geom.c), arr, len(layers), _ptr(bins),
+                                 None if host is None else host.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
+           "uvl_area_query")
+    if not sync:
+        return bins
+    out, off = [], 0
+    for l in layers:
+        k = 256 if l.dtype == U8 else 65536
+        out.append(host[off:off + k])
+        off += k
+    return out

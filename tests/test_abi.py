@@ -1,0 +1,146 @@
+"""The C ABI loads and exports every symbol include/uvl.h declares (no GPU).
+
+Only validation paths that return before any HIP call are exercised here:
+null pointers, sizes out of range, dtype and shape mismatches.  Fake device
+addresses are never dereferenced on these paths.
+"""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "uvl.h")
+
+
+def _declared():
+    hdr = open(HEADER).read()
+    return re.findall(r"^\w[\w\s\*]*?\b(uvl_\w+)\s*\(", hdr, re.M)
+
+
+@pytest.fixture(scope="module")
+def uvl():
+    from paper_2501_14807_amd import uvl as U
+    if not os.path.exists(U.LIB_PATH):
+        from paper_2501_14807_amd import build
+        build.build()
+    return U
+
+
+def test_header_and_binding_agree(uvl):
+    assert sorted(_declared()) == sorted(uvl.SIGNATURES)
+
+
+def test_library_exports_every_declared_symbol(uvl):
+    L = uvl.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    # and with C linkage (plain names in the dynamic symbol table)
+    out = os.popen(f"nm -D --defined-only {uvl.LIB_PATH}").read()
+    for name in _declared():
+        assert re.search(rf"\bT {name}$", out, re.M), name
+
+
+def test_status_strings(uvl):
+    L = uvl.lib()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert L.uvl_status_str(code)
+    assert L.uvl_status_str(-99) == b"unknown status"
+
+
+FAKE = 0x100000        # a 16-byte aligned address that is never dereferenced
+
+
+def _geom(uvl, w=64, h=32):
+    g = uvl.CGeom()
+    g.width, g.height = w, h
+    g.tri_id = g.area_w = FAKE
+    g.pos_x = g.pos_y = g.pos_z = FAKE
+    return g
+
+
+def _layer(uvl, w=64, h=32, dt=1):
+    return uvl.CLayer(FAKE, w, h, dt)
+
+
+def test_brush_validation(uvl):
+    L = uvl.lib()
+    g, l = _geom(uvl), _layer(uvl)
+    c = (ctypes.c_float * 3)(0, 0, 0)
+    s = None
+    assert L.uvl_edit_brush(None, ctypes.byref(l), c, 1.0, 1, s) == -1
+    assert L.uvl_edit_brush(ctypes.byref(g), ctypes.byref(l), None, 1.0, 1, s) == -1
+    assert L.uvl_edit_brush(ctypes.byref(g), ctypes.byref(l), c, -1.0, 1, s) == -1
+    assert L.uvl_edit_brush(ctypes.byref(g), ctypes.byref(l), c, float("nan"), 1, s) == -1
+    assert L.uvl_edit_brush(ctypes.byref(g), ctypes.byref(l), c, float("inf"), 1, s) == -1
+    assert L.uvl_edit_brush(ctypes.byref(g), ctypes.byref(l), c, 1.0, 256, s) == -3
+    l16 = _layer(uvl, dt=2)
+    assert L.uvl_edit_brush(ctypes.byref(g), ctypes.byref(l16), c, 1.0, 65536, s) == -3
+    lbad = _layer(uvl, dt=7)
+    assert L.uvl_edit_brush(ctypes.byref(g), ctypes.byref(lbad), c, 1.0, 1, s) == -3
+    lsz = _layer(uvl, w=63)
+    assert L.uvl_edit_brush(ctypes.byref(g), ctypes.byref(lsz), c, 1.0, 1, s) == -2
+    unaligned = uvl.CLayer(FAKE + 4, 64, 32, 1)
+    assert L.uvl_edit_brush(ctypes.byref(g), ctypes.byref(unaligned), c, 1.0, 1, s) == -1
+    g.pos_y = FAKE + 8
+    assert L.uvl_edit_brush(ctypes.byref(g), ctypes.byref(l), c, 1.0, 1, s) == -1
+
+
+def test_lasso_validation(uvl):
+    L = uvl.lib()
+    g, l = _geom(uvl), _layer(uvl)
+    M = (ctypes.c_float * 16)(*([1.0] * 16))
+    poly = (ctypes.c_float * 200)(*([0.5] * 200))
+    s = None
+    call = lambda n, dw=32, dh=32, bias=1e-4, depth=FAKE, label=1: L.uvl_edit_lasso(
+        ctypes.byref(g), ctypes.byref(l), M, poly, n, depth, dw, dh, bias, label, s)
+    assert call(2) == -1
+    assert call(65) == -1
+    assert call(8, depth=None) == -1
+    assert call(8, dw=0) == -1
+    assert call(8, dh=20000) == -1
+    assert call(8, bias=float("nan")) == -1
+    assert call(8, label=300) == -3
+    poly[3] = float("nan")
+    assert call(8) == -1
+
+
+def test_layer_op_and_area_validation(uvl):
+    L = uvl.lib()
+    a, b = _layer(uvl), _layer(uvl)
+    d16 = _layer(uvl, dt=2)
+    s = None
+    assert L.uvl_layer_op(9, ctypes.byref(a), ctypes.byref(a), ctypes.byref(b), 0, 0, 1, None, s) == -1
+    assert L.uvl_layer_op(0, ctypes.byref(a), ctypes.byref(a), None, 0, 0, 1, None, s) == -1
+    assert L.uvl_layer_op(0, ctypes.byref(a), ctypes.byref(a), ctypes.byref(b), 0, 0, 256, None, s) == -3
+    assert L.uvl_layer_op(0, ctypes.byref(d16), ctypes.byref(a), ctypes.byref(_layer(uvl, h=31)), 0, 0, 1, None,
+                          s) == -2
+    assert L.uvl_layer_op(3, ctypes.byref(a), ctypes.byref(a), None, 0, 0, 0, None, s) == -1
+    g = _geom(uvl)
+    arr = (uvl.CLayer * 2)(a, _layer(uvl, w=8))
+    assert L.uvl_area_query(ctypes.byref(g), arr, 2, FAKE, None, s) == -2
+    assert L.uvl_area_query(ctypes.byref(g), arr, 0, FAKE, None, s) == -1
+    assert L.uvl_area_query(ctypes.byref(g), arr, 33, FAKE, None, s) == -1
+    assert L.uvl_area_query(ctypes.byref(g), arr, 1, None, None, s) == -1
+
+
+def test_build_and_depth_validation(uvl):
+    L = uvl.lib()
+    m = uvl.CMesh(FAKE, None, FAKE, FAKE, 10, 4)
+    g = _geom(uvl)
+    ws_need = L.uvl_build_workspace_bytes(4)
+    assert ws_need >= 4 * 12
+    assert L.uvl_build_geometry_image(ctypes.byref(m), ctypes.byref(g), FAKE, ws_need - 1, None) == -4
+    g.width = 40000
+    assert L.uvl_build_geometry_image(ctypes.byref(m), ctypes.byref(g), FAKE, ws_need, None) == -1
+    g.width = 64
+    g.nrm_x = FAKE
+    assert L.uvl_build_geometry_image(ctypes.byref(m), ctypes.byref(g), FAKE, ws_need, None) == -1
+    M = (ctypes.c_float * 16)()
+    dws = L.uvl_depth_workspace_bytes(4)
+    assert L.uvl_render_depth(ctypes.byref(m), M, FAKE, 0, 16, FAKE, dws, None) == -1
+    assert L.uvl_render_depth(ctypes.byref(m), M, FAKE, 16, 16, FAKE, dws - 1, None) == -4
+    assert L.uvl_create_layer(ctypes.byref(_layer(uvl, dt=5)), None) == -3
+    assert L.uvl_create_layer(None, None) == -1

@@ -1,0 +1,425 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars (exact unless stated):
+  * geometry image: triangle ids and fp32 positions bit-exact (both sides
+    round the same fp64 interpolation once); normals within 1e-5; texel
+    areas within the quantisation bound the build reports (+1e-12);
+  * depth maps bit-exact (same fixed-point raster, same fp64 interpolation);
+  * layers after any sequence of brush / lasso edits and layer operations
+    bit-exact;
+  * per-label areas within 1e-6 relative (and within the reported bound).
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_14807_amd import uvl
+    uvl.device_check()
+    return uvl
+
+
+def _geom_gpu(uvl, mesh, W, H, normals=True, bary=True):
+    dm = uvl.DeviceMesh.from_mesh(mesh)
+    g = uvl.GeometryImage(W, H, normals=normals, bary=bary)
+    uvl.build_geometry_image(dm, g)
+    return dm, g
+
+
+def _compare_geom(orc_g, h, area_scale, abs_err, tag=""):
+    tri = h["tri_id"]
+    assert np.array_equal(tri, orc_g.tri_id), tag
+    assert np.array_equal(h["pos"], orc_g.pos32, equal_nan=True), tag
+    cov = tri >= 0
+    if "nrm" in h:
+        assert np.abs(h["nrm"][:, cov] - orc_g.nrm[:, cov]).max(initial=0) <= 1e-5, tag
+        assert not h["nrm"][:, ~cov].any(), tag
+    if "bary" in h:
+        assert np.abs(h["bary"][:, cov] - orc_g.bary[:, cov]).max(initial=0) <= 1e-7, tag
+    a = h["area_w"].astype(np.float64) * area_scale
+    w = orc_g.w
+    pos = w > 0
+    assert (a[~cov] == 0).all(), tag
+    assert abs_err == 0.5 * area_scale, tag
+    if pos.any():
+        # one rounding of the fp64 weight to the power-of-two grid (the
+        # weights themselves agree to a few ulps)
+        assert (np.abs(a - w) <= abs_err + 1e-12 * w).all(), tag
+        # the grid is fine enough for 1e-6 relative on any texel weighing
+        # at least 2^-10 of the largest
+        assert abs_err <= 1e-6 * 2.0 ** -10 * w.max(), tag
+
+
+# ---------------------------------------------------------------------------
+# geometry image
+
+
+def test_geometry_image_vessel(gpu, orc):
+    wl = synth.tiny_workload()
+    dm, g = _geom_gpu(gpu, wl.mesh, wl.W, wl.H)
+    og = orc.geometry_image(wl.mesh, wl.W, wl.H)
+    _compare_geom(og, g.host(), g.area_scale, g.area_abs_err, "vessel")
+
+
+def _edge_meshes():
+    out = []
+    out.append(("vessel-ragged", synth.vessel(), 37, 53))
+    out.append(("vessel-1x1", synth.vessel(), 1, 1))
+    out.append(("vessel-3x1000", synth.vessel(), 3, 1000))
+    out.append(("vessel-1000x3", synth.vessel(), 1000, 3))
+    out.append(("sphere", synth.sphere(1.0, 65, 33), 300, 200))
+    # two triangles over most of the atlas: the large-triangle queue path
+    out.append(("quad-big", synth.plane_grid(2, 2, uv0=(0.01, 0.02), uv1=(0.97, 0.99)), 700, 500))
+    # mirrored (clockwise) chart, overlapping copies (lowest index wins)
+    out.append(("mirror", synth.plane_grid(9, 7, mirror=True), 129, 77))
+    m1 = synth.plane_grid(5, 5, uv0=(0.1, 0.1), uv1=(0.8, 0.9))
+    out.append(("overlap", synth.merge_meshes([m1, synth.plane_grid(4, 4, uv0=(0.3, 0.2), uv1=(0.95, 0.7)), m1]),
+                96, 96))
+    # vertices and edges on texel centres
+    W = 64
+    out.append(("centres", synth.plane_grid(5, 5, uv0=(5.5 / W, 7.5 / W), uv1=(45.5 / W, 39.5 / W)), W, W))
+    # degenerate triangles mixed in
+    m = synth.vessel()
+    tri = m.tri.copy()
+    tri[::7, 2] = tri[::7, 1]
+    out.append(("degenerate", synth.Mesh(m.pos, m.nrm, m.uv, tri), 256, 256))
+    return out
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_geometry_image_edge_cases(gpu, orc, case):
+    name, mesh, W, H = _edge_meshes()[case]
+    for normals in (True, False):
+        mm = mesh if normals else synth.Mesh(mesh.pos, mesh.nrm, mesh.uv, mesh.tri)
+        dm = gpu.DeviceMesh.from_mesh(mm, normals=normals)
+        g = gpu.GeometryImage(W, H)
+        gpu.build_geometry_image(dm, g)
+        og = orc.geometry_image(mm, W, H, normals=normals)
+        _compare_geom(og, g.host(), g.area_scale, g.area_abs_err, f"{name} normals={normals}")
+
+
+def test_geometry_image_without_optional_planes_and_empty_mesh(gpu, orc):
+    wl = synth.tiny_workload()
+    dm, g = _geom_gpu(gpu, wl.mesh, 100, 90, normals=False, bary=False)
+    og = orc.geometry_image(wl.mesh, 100, 90)
+    h = g.host()
+    assert "nrm" not in h and "bary" not in h
+    _compare_geom(og, h, g.area_scale, g.area_abs_err, "no-optional")
+    empty = synth.Mesh(wl.mesh.pos, wl.mesh.nrm, wl.mesh.uv, np.zeros((0, 3), np.int32))
+    dm, g = _geom_gpu(gpu, empty, 64, 64)
+    h = g.host()
+    assert (h["tri_id"] == -1).all() and np.isnan(h["pos"]).all() and not h["area_w"].any()
+
+
+def test_build_rejects_invalid_mesh(gpu):
+    m = synth.vessel()
+    uv = m.uv.copy()
+    uv[5, 0] = 5.0
+    with pytest.raises(gpu.UvlError) as ei:
+        _geom_gpu(gpu, synth.Mesh(m.pos, m.nrm, uv, m.tri), 64, 64)
+    assert ei.value.code == -1
+    tri = m.tri.copy()
+    tri[3, 1] = m.nv
+    with pytest.raises(gpu.UvlError):
+        _geom_gpu(gpu, synth.Mesh(m.pos, m.nrm, m.uv, tri), 64, 64)
+
+
+# ---------------------------------------------------------------------------
+# depth maps
+
+
+def test_depth_maps_bit_exact(gpu, orc):
+    import torch
+    wl = synth.tiny_workload()
+    dm = gpu.DeviceMesh.from_mesh(wl.mesh)
+    for k, M in enumerate(wl.cameras[:12]):
+        for (dw, dh) in ((256, 256), (97, 131)):
+            d = torch.empty((dh, dw), dtype=torch.float32, device="cuda")
+            gpu.render_depth(dm, M, d)
+            od = orc.depth_map(wl.mesh, M, dw, dh)
+            assert np.array_equal(d.cpu().numpy(), od), (k, dw, dh)
+    # a sphere seen from close by (large screen triangles: queue path)
+    sph = synth.sphere(1.0, 17, 9)
+    dms = gpu.DeviceMesh.from_mesh(sph)
+    M = synth.edits.look_at_perspective((0.0, -1.6, 0.3), (0, 0, 0), (0, 0, 1))
+    d = torch.empty((300, 400), dtype=torch.float32, device="cuda")
+    gpu.render_depth(dms, M, d)
+    assert np.array_equal(d.cpu().numpy(), orc.depth_map(sph, M, 400, 300))
+
+
+# ---------------------------------------------------------------------------
+# edits
+
+
+@pytest.fixture(scope="module")
+def tiny_oracle(orc):
+    from oracle import workload
+    wl = synth.tiny_workload()
+    geom, layers, areas = workload.run(wl)
+    return wl, geom, layers, areas
+
+
+def test_tiny_workload_bit_exact(gpu, orc, tiny_oracle):
+    from paper_2501_14807_amd.model import Model
+    wl, og, ol, oa = tiny_oracle
+    m = Model.from_workload(wl).build()
+    # edit by edit against the oracle's sequence
+    from oracle import workload
+    L = workload.new_layers(wl)
+    cache = {}
+    for k, e in enumerate(wl.edits):
+        m.apply(e, wl.cameras)
+        workload.apply_edits(wl, og, L, [e], cache)
+        assert np.array_equal(m.layers[0].numpy(), L[0]), (k, e.kind)
+    assert np.array_equal(m.layers[0].numpy(), ol[0])
+    with open(os.path.join(GOLDEN, "vessel512_oracle.json")) as f:
+        gold = json.load(f)
+    import hashlib
+    assert hashlib.sha256(m.layers[0].numpy().tobytes()).hexdigest() == gold["layer_sha256"]
+    areas = m.areas()[0]
+    nz = oa[0] > 0
+    assert np.allclose(areas[nz], oa[0][nz], rtol=1e-6, atol=0)
+    assert (areas[~nz] == 0).all()
+    assert np.allclose(areas[:8], gold["areas"], rtol=1e-6)
+
+
+def test_edits_ragged_sizes_and_u16(gpu, orc):
+    import torch
+    wl = synth.tiny_workload()
+    rng = np.random.default_rng(9)
+    for (W, H) in ((37, 53), (1, 1), (4099, 3), (70, 70)):
+        dm = gpu.DeviceMesh.from_mesh(wl.mesh)
+        g = gpu.GeometryImage(W, H)
+        gpu.build_geometry_image(dm, g)
+        og = orc.geometry_image(wl.mesh, W, H)
+        for dt, npdt in ((gpu.U8, np.uint8), (gpu.U16, np.uint16)):
+            lay = gpu.create_layer(gpu.Layer(W, H, dt))
+            ref = np.zeros(W * H, npdt)
+            for k, e in enumerate(wl.edits[:24]):
+                label = int(rng.integers(0, 256 if dt == gpu.U8 else 65536))
+                if e.kind == "brush":
+                    gpu.edit_brush(g, lay, e.centre, e.radius * 2, label)
+                    orc.brush(og.pos32, ref, e.centre, np.float32(e.radius * 2), label)
+                else:
+                    M = wl.cameras[e.camera]
+                    d = torch.empty((64, 48), dtype=torch.float32, device="cuda")
+                    gpu.render_depth(dm, M, d)
+                    gpu.edit_lasso(g, lay, M, e.poly, d, 1e-3, label)
+                    orc.lasso(og.pos32, ref, M, e.poly, orc.depth_map(wl.mesh, M, 48, 64), 1e-3, label)
+            assert np.array_equal(lay.numpy(), ref), (W, H, dt)
+
+
+def test_brush_extremes_gpu(gpu):
+    wl = synth.tiny_workload()
+    dm, g = _geom_gpu(gpu, wl.mesh, 128, 128)
+    lay = gpu.create_layer(gpu.Layer(128, 128, gpu.U16))
+    gpu.edit_brush(g, lay, (0.0, 0.0, 1.5), 1e30, 65535)
+    tri = g.host()["tri_id"]
+    assert np.array_equal(lay.numpy() == 65535, tri >= 0)
+    gpu.edit_brush(g, lay, (0.0, 0.0, 1.5), 1e30, 0)
+    assert not lay.numpy().any()
+    gpu.edit_brush(g, lay, (0.0, 0.0, 1.5), 0.0, 9)
+    assert not lay.numpy().any()
+
+
+def test_lasso_large_polygon_and_idempotence(gpu, orc):
+    import torch
+    wl = synth.tiny_workload()
+    dm, g = _geom_gpu(gpu, wl.mesh, 300, 300)
+    og = orc.geometry_image(wl.mesh, 300, 300)
+    rng = np.random.default_rng(4)
+    poly = synth.star_polygon(rng, 64)
+    M = wl.cameras[3]
+    d = torch.empty((256, 256), dtype=torch.float32, device="cuda")
+    gpu.render_depth(dm, M, d)
+    lay = gpu.create_layer(gpu.Layer(300, 300, gpu.U8))
+    gpu.edit_lasso(g, lay, M, poly, d, 1e-4, 200)
+    first = lay.numpy().copy()
+    gpu.edit_lasso(g, lay, M, poly, d, 1e-4, 200)
+    assert np.array_equal(lay.numpy(), first)
+    ref = np.zeros(300 * 300, np.uint8)
+    orc.lasso(og.pos32, ref, M, poly, orc.depth_map(wl.mesh, M, 256, 256), 1e-4, 200)
+    assert np.array_equal(first, ref)
+    assert (first == 200).sum() > 100
+
+
+# ---------------------------------------------------------------------------
+# layer algebra
+
+
+def _dev_layer(gpu, arr, W, H, dt):
+    lay = gpu.Layer(W, H, dt)
+    lay.copy_from(arr)
+    return lay
+
+
+def test_layer_ops_exhaustive_u8(gpu, orc):
+    W = H = 256
+    a = np.repeat(np.arange(256, dtype=np.uint8), 256)
+    b = np.tile(np.arange(256, dtype=np.uint8), 256)
+    A, B = _dev_layer(gpu, a, W, H, gpu.U8), _dev_layer(gpu, b, W, H, gpu.U8)
+    D = gpu.Layer(W, H, gpu.U8)
+    for op in (gpu.AND, gpu.OR, gpu.XOR):
+        for sa, sb in ((0, 0), (7, 0), (0, 200), (255, 1)):
+            gpu.layer_op(op, D, A, B, sa, sb, 42)
+            ref = np.empty_like(a)
+            orc.layer_op(op, ref, a, b, sa, sb, 42)
+            assert np.array_equal(D.numpy(), ref), (op, sa, sb)
+
+
+def test_layer_ops_mixed_dtypes_ragged_alias(gpu, orc):
+    import torch
+    rng = np.random.default_rng(12)
+    for (W, H) in ((1000, 7), (1, 1), (33, 33)):
+        n = W * H
+        vals = {gpu.U8: rng.integers(0, 5, n).astype(np.uint8) * 50,
+                gpu.U16: (rng.integers(0, 5, n) * 13000).astype(np.uint16)}
+        for da in (gpu.U8, gpu.U16):
+            for db in (gpu.U8, gpu.U16):
+                for dd in (gpu.U8, gpu.U16):
+                    for op in (gpu.AND, gpu.OR, gpu.XOR):
+                        a, b = vals[da], vals[db]
+                        A, B = _dev_layer(gpu, a, W, H, da), _dev_layer(gpu, b, W, H, db)
+                        D = gpu.Layer(W, H, dd)
+                        sa = 0 if op != gpu.AND else int(a.max())
+                        gpu.layer_op(op, D, A, B, sa, 0, 250)
+                        ref = np.zeros(n, np.uint8 if dd == gpu.U8 else np.uint16)
+                        orc.layer_op(op, ref, a, b, sa, 0, 250)
+                        assert np.array_equal(D.numpy(), ref), (W, H, da, db, dd, op)
+        # aliasing: dst is b
+        a, b = vals[gpu.U8], vals[gpu.U16].copy()
+        A, B = _dev_layer(gpu, a, W, H, gpu.U8), _dev_layer(gpu, b, W, H, gpu.U16)
+        gpu.layer_op(gpu.XOR, B, A, B, 0, 0, 60000)
+        ref = b.copy()
+        orc.layer_op(orc.XOR, ref, a, ref, 0, 0, 60000)
+        assert np.array_equal(B.numpy(), ref)
+        # remap, both widths, into both widths
+        for da in (gpu.U8, gpu.U16):
+            na = 256 if da == gpu.U8 else 65536
+            for dd in (gpu.U8, gpu.U16):
+                top = 256 if dd == gpu.U8 else 65536
+                lut = rng.integers(1, top, na).astype(np.uint16)
+                lut[0] = 0
+                A = _dev_layer(gpu, vals[da], W, H, da)
+                D = gpu.Layer(W, H, dd)
+                gpu.layer_op(gpu.REMAP, D, A, None, lut=torch.from_numpy(lut).cuda())
+                ref = np.zeros(n, np.uint8 if dd == gpu.U8 else np.uint16)
+                orc.layer_op(orc.REMAP, ref, vals[da], None, lut=lut)
+                assert np.array_equal(D.numpy(), ref), (W, H, da, dd)
+
+
+# ---------------------------------------------------------------------------
+# area
+
+
+def test_area_fused_layers_and_exact_additivity(gpu, orc):
+    import torch
+    wl = synth.tiny_workload()
+    W = H = 384
+    dm, g = _geom_gpu(gpu, wl.mesh, W, H)
+    og = orc.geometry_image(wl.mesh, W, H)
+    rng = np.random.default_rng(2)
+    arrs = []
+    for k in range(10):
+        dt = gpu.U8 if k % 3 else gpu.U16
+        top = 8 if k < 5 else (256 if dt == gpu.U8 else 65536)
+        # blocky labels (runs) plus scattered ones
+        base = rng.integers(0, top, (W * H) // 64 + 1).repeat(64)[:W * H]
+        noise = rng.integers(0, top, W * H)
+        v = np.where(rng.uniform(size=W * H) < 0.1, noise, base)
+        arrs.append((v.astype(np.uint8 if dt == gpu.U8 else np.uint16), dt))
+    layers = [_dev_layer(gpu, a, W, H, dt) for a, dt in arrs]
+    fused = gpu.area_query(g, layers)
+    for (a, dt), got in zip(arrs, fused):
+        ref = orc.area(og, a)
+        nz = ref > 0
+        assert np.allclose(got[nz], ref[nz], rtol=1e-6, atol=0)
+        assert (got[~nz] == 0).all()
+        single = gpu.area_query(g, [_dev_layer(gpu, a, W, H, dt)])[0]
+        assert np.array_equal(single, got)
+    # exact integer additivity of the bins: |A or B| = |A| + |B| - |A and B|
+    A, B = layers[1], layers[2]
+    U, I = gpu.Layer(W, H, gpu.U8), gpu.Layer(W, H, gpu.U8)
+    gpu.layer_op(gpu.OR, U, A, B, 0, 0, 1)
+    gpu.layer_op(gpu.AND, I, A, B, 0, 0, 1)
+    bins = [gpu.area_query(g, [L], sync=False).cpu().numpy() for L in (A, B, U, I)]
+    sa, sb = bins[0][1:].sum(), bins[1][1:].sum()
+    assert bins[2][1] == sa + sb - bins[3][1]
+    total = gpu.area_query(g, [gpu.create_layer(gpu.Layer(W, H, gpu.U8))], sync=False).cpu().numpy()
+    assert total[0] == sum(b.sum() for b in bins[:1])
+
+
+def test_determinism(gpu):
+    from paper_2501_14807_amd.model import Model
+    wl = synth.tiny_workload()
+    outs = []
+    for _ in range(2):
+        m = Model.from_workload(wl).build()
+        m.apply_all(wl.edits, wl.cameras)
+        outs.append((m.layers[0].numpy().copy(), m.areas(sync=False).cpu().numpy().copy(),
+                     m.geom.host()["pos"].copy()))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert np.array_equal(outs[0][2], outs[1][2], equal_nan=True)
+
+
+# ---------------------------------------------------------------------------
+# scan-scale workloads
+
+
+def _scan_small():
+    return synth.scan_workload(n_brush=40, n_lasso=40, n_ops=32, W=1024, n_charts=4, nx=64, ny=32, depth=512)
+
+
+def test_scan_small_full_parity(gpu, orc):
+    from oracle import workload
+    from paper_2501_14807_amd.model import Model
+    wl = _scan_small()
+    og, ol, oa = workload.run(wl)
+    m = Model.from_workload(wl)
+    areas = m.run(wl)
+    _compare_geom(og, m.geom.host(), m.geom.area_scale, m.geom.area_abs_err, "scan-small")
+    for k, (L, ref) in enumerate(zip(m.layers, ol)):
+        assert np.array_equal(L.numpy(), ref), k
+    for got, ref in zip(areas, oa):
+        nz = ref > 0
+        assert np.allclose(got[nz], ref[nz], rtol=1e-6, atol=0)
+
+
+def test_scan_full_size_sampled_rows(gpu, orc):
+    """The 8192^2, 4,145,280-triangle model in the benchmark's launch
+    configuration, checked on sampled atlas rows the oracle computes one band
+    at a time, for the first 160 edits of its stream."""
+    from oracle import workload
+    from paper_2501_14807_amd.model import Model
+    wl = synth.scan_workload()
+    m = Model.from_workload(wl).build()
+    edits = wl.edits[:160]
+    m.apply_all(edits, wl.cameras)
+    rng = np.random.default_rng(77)
+    rows = sorted(rng.choice(wl.H, size=6, replace=False).tolist())
+    cache = {}
+    for r in rows:
+        og = orc.geometry_image(wl.mesh, wl.W, wl.H, rows=(r, r + 1))
+        sl = slice(r * wl.W, (r + 1) * wl.W)
+        assert np.array_equal(m.geom.tri_id[sl].cpu().numpy(), og.tri_id), r
+        assert np.array_equal(m.geom.pos[:, sl].cpu().numpy(), og.pos32, equal_nan=True), r
+        L = workload.new_layers(wl, wl.W)
+        workload.apply_edits(wl, og, L, edits, cache)
+        for k, lay in enumerate(m.layers):
+            assert np.array_equal(lay.data[sl].cpu().numpy(), L[k]), (r, k)
