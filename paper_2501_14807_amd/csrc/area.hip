@@ -7,12 +7,19 @@
 // integers: independent of summation order, deterministic run to run, and
 // exactly additive (area(A or B) = area(A) + area(B) - area(A and B)).
 //
-// One pass reads each area weight once for up to kGroup layers.  A thread
-// takes 16 consecutive texels (4 x 16-byte weight loads, one 16-byte u8 label
-// load); a run of equal labels collapses to one (label, sum) pair; pairs of a
-// wave with the same label are summed across lanes before one atomic add.
-// u8 layers accumulate in LDS bins (256 x u64 per layer) flushed once per
-// workgroup; u16 layers (65536 bins) add straight into the global bins.
+// One pass reads each area weight once for up to kGroup layers.  The atlas is
+// cut into bands of 4096 columns; a workgroup owns one band over a range of
+// rows and walks it row by row; lane l takes columns [16 l, 16 l + 16) of the
+// band in every row (4 x 16-byte weight loads, one 16-byte u8 or two u16
+// label loads per layer when the width is a multiple of 16).  Every lane
+// keeps, per layer, its current label and the uint64 weight sum of its run of
+// that label, carried down the rows: labelled regions are spatially coherent,
+// so a run usually spans many rows and is added to a bin only when the lane's
+// label changes.  u8 layers add into 256 LDS bins (native LDS atomics);
+// u16 layers (65536 bins) add into an LDS hash table keyed by (layer,
+// label), open addressing with linear probing, falling back to the global
+// bin only if 16 probes find no slot.  Both are flushed to the global bins
+// once per workgroup, so global atomics stay few and spread out.
 #include "uvl_internal.h"
 
 namespace uvl {
@@ -21,6 +28,41 @@ namespace {
 constexpr int kPer = 16;
 constexpr int kGroup = 8;                 // layers per launch
 constexpr int kTexPerIter = kBlock * kPer;
+constexpr int kHashBits = 11;
+constexpr int kHash = 1 << kHashBits;     // LDS hash slots for u16 labels
+constexpr uint32_t kEmptyKey = 0xffffffffu;
+
+struct U16Table {
+    uint32_t *key;                 // LDS [kHash]
+    unsigned long long *val;       // LDS [kHash]
+    unsigned long long *const *bins;   // global bins per layer (fallback)
+};
+
+// Add `sum` to label `label` of group layer `l` in the LDS hash table.
+__device__ __forceinline__ void table_add(const U16Table &T, int l, uint32_t label, unsigned long long sum) {
+    const uint32_t key = ((uint32_t)l << 16) | label;
+    uint32_t h = (key * 2654435761u) >> (32 - kHashBits);
+    for (int probe = 0; probe < 16; ++probe) {
+        const uint32_t prev = atomicCAS(T.key + h, kEmptyKey, key);
+        if (prev == kEmptyKey || prev == key) {
+            atomicAdd(T.val + h, sum);
+            return;
+        }
+        h = (h + 1) & (kHash - 1);
+    }
+    atomicAdd(T.bins[l] + label, sum);
+}
+
+// Bin sinks: direct LDS bins for u8 layers, the hash table for u16 layers.
+struct SinkU8 {
+    unsigned long long *bins;
+    __device__ __forceinline__ void add(uint32_t label, unsigned long long s) const { atomicAdd(bins + label, s); }
+};
+struct SinkU16 {
+    const U16Table *T;
+    int l;
+    __device__ __forceinline__ void add(uint32_t label, unsigned long long s) const { table_add(*T, l, label, s); }
+};
 
 struct AreaArgs {
     const void *data[kGroup];
@@ -29,43 +71,14 @@ struct AreaArgs {
     int32_t nl;
 };
 
-__device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    return x;
-}
-
-// Add each pending lane's (label, sum) into bins; lanes with equal labels are
-// combined first.  Must be reached by the whole wave.
-__device__ __forceinline__ void flush(bool pending, uint32_t label, unsigned long long sum,
-                                      unsigned long long *bins) {
-    unsigned long long todo = __ballot(pending);
-    const int lane = threadIdx.x & 63;
-    while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const uint32_t l0 = __shfl(label, leader);
-        const bool mine = pending && label == l0;
-        const unsigned long long m = __ballot(mine);
-        const unsigned long long s = wave_sum(mine ? sum : 0ull);
-        if (lane == leader) atomicAdd(bins + l0, s);
-        pending = pending && !mine;
-        todo &= ~m;
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void load_labels(const T *p, uint32_t v[kPer]);
-
-template <>
-__device__ __forceinline__ void load_labels<uint8_t>(const uint8_t *p, uint32_t v[kPer]) {
+__device__ __forceinline__ void label16_u8(const uint8_t *p, uint32_t v[kPer]) {
     const uint4 q = *reinterpret_cast<const uint4 *>(p);
     const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
     for (int k = 0; k < kPer; ++k) v[k] = (w[k >> 2] >> (8 * (k & 3))) & 0xffu;
 }
 
-template <>
-__device__ __forceinline__ void load_labels<uint16_t>(const uint16_t *p, uint32_t v[kPer]) {
+__device__ __forceinline__ void label16_u16(const uint16_t *p, uint32_t v[kPer]) {
     const uint4 q0 = reinterpret_cast<const uint4 *>(p)[0];
     const uint4 q1 = reinterpret_cast<const uint4 *>(p)[1];
     const uint32_t w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
@@ -73,43 +86,62 @@ __device__ __forceinline__ void load_labels<uint16_t>(const uint16_t *p, uint32_
     for (int k = 0; k < kPer; ++k) v[k] = (w[k >> 1] >> (16 * (k & 1))) & 0xffffu;
 }
 
-// Run-length accumulation of 16 (label, weight) pairs of every lane.
-__device__ __forceinline__ void accumulate(const uint32_t lab[kPer], const uint32_t w[kPer], bool valid,
-                                           unsigned long long *bins) {
-    bool uniform = valid;
+// Feed 16 (label, weight) pairs into a lane's run; a finished run goes to
+// the sink.
+template <typename Sink>
+__device__ __forceinline__ void feed(const uint32_t lab[kPer], const uint32_t w[kPer], unsigned long long tot,
+                                     uint32_t &cur, unsigned long long &run, const Sink &bins) {
+    bool uni = true;
 #pragma unroll
-    for (int k = 1; k < kPer; ++k) uniform = uniform && lab[k] == lab[0];
-    unsigned long long total = 0;
+    for (int k = 1; k < kPer; ++k) uni = uni && lab[k] == lab[0];
+    if (uni) {
+        if (lab[0] != cur) {
+            if (run) bins.add(cur, run);
+            cur = lab[0];
+            run = 0;
+        }
+        run += tot;
+    } else {
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) total += w[k];
-    // fast path: all 16 labels equal
-    flush(uniform, lab[0], total, bins);
-    if (__ballot(valid && !uniform) == 0) return;
-    bool slow = valid && !uniform;
-    uint32_t cur = lab[0];
-    unsigned long long run = w[0];
-#pragma unroll
-    for (int k = 1; k < kPer; ++k) {
-        const bool ends = slow && lab[k] != cur;
-        flush(ends, cur, run, bins);
-        if (slow) {
-            run = ends ? (unsigned long long)w[k] : run + w[k];
-            cur = lab[k];
+        for (int k = 0; k < kPer; ++k) {
+            if (lab[k] != cur) {
+                if (run) bins.add(cur, run);
+                cur = lab[k];
+                run = 0;
+            }
+            run += w[k];
         }
     }
-    flush(slow, cur, run, bins);
 }
 
-__global__ __launch_bounds__(kBlock) void k_area(const uint32_t *__restrict__ area_w, int64_t n, AreaArgs A) {
+__global__ __launch_bounds__(kBlock) void k_area(const uint32_t *__restrict__ area_w, int W, int H, int rows_per,
+                                                  AreaArgs A) {
     __shared__ unsigned long long s_bins[kGroup][256];
+    __shared__ uint32_t s_key[kHash];
+    __shared__ unsigned long long s_val[kHash];
     for (int k = threadIdx.x; k < kGroup * 256; k += kBlock) (&s_bins[0][0])[k] = 0ull;
+    for (int k = threadIdx.x; k < kHash; k += kBlock) {
+        s_key[k] = kEmptyKey;
+        s_val[k] = 0ull;
+    }
     __syncthreads();
-    const int64_t iters = ceil_div(n, kTexPerIter);
-    for (int64_t it = blockIdx.x; it < iters; it += gridDim.x) {
-        const int64_t t0 = it * kTexPerIter + (int64_t)threadIdx.x * kPer;
-        const bool full = t0 + kPer <= n;
+    const U16Table table{s_key, s_val, A.bins};
+    uint32_t cur[kGroup];
+    unsigned long long run[kGroup];
+#pragma unroll
+    for (int l = 0; l < kGroup; ++l) {
+        cur[l] = 0;
+        run[l] = 0;
+    }
+    const int col = (int)blockIdx.x * kTexPerIter + (int)threadIdx.x * kPer;   // first column of the lane
+    const int ncol = W - col < kPer ? (W - col > 0 ? W - col : 0) : kPer;       // columns it owns
+    const bool vec = (W % kPer) == 0 && ncol == kPer;                          // aligned 16-wide loads
+    const int r0 = (int)blockIdx.y * rows_per;
+    const int r1 = r0 + rows_per < H ? r0 + rows_per : H;
+    for (int r = r0; r < r1; ++r) {
+        const int64_t t0 = (int64_t)r * W + col;
         uint32_t w[kPer];
-        if (full) {
+        if (vec) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const uint4 v = reinterpret_cast<const uint4 *>(area_w + t0)[q];
@@ -117,25 +149,42 @@ __global__ __launch_bounds__(kBlock) void k_area(const uint32_t *__restrict__ ar
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < kPer; ++k) w[k] = t0 + k < n ? area_w[t0 + k] : 0u;
+            for (int k = 0; k < kPer; ++k) w[k] = k < ncol ? area_w[t0 + k] : 0u;
         }
-        for (int l = 0; l < A.nl; ++l) {
-            uint32_t lab[kPer];
-            const bool u8 = A.dtype[l] == UVL_U8;
-            if (full) {
-                if (u8) load_labels<uint8_t>(static_cast<const uint8_t *>(A.data[l]) + t0, lab);
-                else load_labels<uint16_t>(static_cast<const uint16_t *>(A.data[l]) + t0, lab);
-            } else {
+        unsigned long long tot = 0;
 #pragma unroll
-                for (int k = 0; k < kPer; ++k) {
-                    if (t0 + k < n)
-                        lab[k] = u8 ? static_cast<const uint8_t *>(A.data[l])[t0 + k]
-                                    : static_cast<const uint16_t *>(A.data[l])[t0 + k];
-                    else
-                        lab[k] = k > 0 ? lab[k - 1] : 0u;   // padding carries weight 0
+        for (int k = 0; k < kPer; ++k) tot += w[k];
+#pragma unroll
+        for (int l = 0; l < kGroup; ++l) {
+            if (l >= A.nl) break;
+            uint32_t lab[kPer];
+            if (A.dtype[l] == UVL_U8) {
+                const uint8_t *L = static_cast<const uint8_t *>(A.data[l]);
+                if (vec) {
+                    label16_u8(L + t0, lab);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < kPer; ++k) lab[k] = k < ncol ? L[t0 + k] : cur[l];
                 }
+                feed(lab, w, tot, cur[l], run[l], SinkU8{&s_bins[l][0]});
+            } else {
+                const uint16_t *L = static_cast<const uint16_t *>(A.data[l]);
+                if (vec) {
+                    label16_u16(L + t0, lab);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < kPer; ++k) lab[k] = k < ncol ? L[t0 + k] : cur[l];
+                }
+                feed(lab, w, tot, cur[l], run[l], SinkU16{&table, l});
             }
-            accumulate(lab, w, t0 < n, u8 ? s_bins[l] : A.bins[l]);
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < kGroup; ++l) {
+        if (l >= A.nl) break;
+        if (run[l]) {
+            if (A.dtype[l] == UVL_U8) atomicAdd(&s_bins[l][cur[l]], run[l]);
+            else table_add(table, l, cur[l], run[l]);
         }
     }
     __syncthreads();
@@ -143,6 +192,10 @@ __global__ __launch_bounds__(kBlock) void k_area(const uint32_t *__restrict__ ar
         if (A.dtype[l] != UVL_U8) continue;
         const unsigned long long v = s_bins[l][threadIdx.x];
         if (v) atomicAdd(A.bins[l] + threadIdx.x, v);
+    }
+    for (int k = threadIdx.x; k < kHash; k += kBlock) {
+        const uint32_t key = s_key[k];
+        if (key != kEmptyKey && s_val[k]) atomicAdd(A.bins[key >> 16] + (key & 0xffffu), s_val[k]);
     }
 }
 
@@ -164,10 +217,13 @@ extern "C" int32_t uvl_area_query(const uvl_geom *geom, const uvl_layer *layers,
     }
     if (int32_t s = device_ok()) return s;
     hipStream_t s = as_stream(stream);
-    const int64_t n = (int64_t)geom->width * geom->height;
     fill_bytes(bins_dev, nbins * 8, s);
-    const int64_t iters = ceil_div(n, kTexPerIter);
-    const unsigned grid = (unsigned)(iters < 2048 ? iters : 2048);
+    // grid: column bands x row groups, about 1024 workgroups in all
+    const int bands = (int)ceil_div(geom->width, kTexPerIter);
+    int groups = (int)ceil_div(1024, bands);
+    if (groups > geom->height) groups = geom->height;
+    const int rows_per = (int)ceil_div(geom->height, groups);
+    groups = (int)ceil_div(geom->height, rows_per);
     int64_t off = 0;
     for (int l0 = 0; l0 < nlayers; l0 += kGroup) {
         AreaArgs A{};
@@ -179,7 +235,8 @@ extern "C" int32_t uvl_area_query(const uvl_geom *geom, const uvl_layer *layers,
             A.bins[k] = reinterpret_cast<unsigned long long *>(bins_dev) + off;
             off += L.dtype == UVL_U8 ? 256 : 65536;
         }
-        hipLaunchKernelGGL(k_area, dim3(grid), dim3(kBlock), 0, s, geom->area_w, n, A);
+        hipLaunchKernelGGL(k_area, dim3((unsigned)bands, (unsigned)groups), dim3(kBlock), 0, s, geom->area_w,
+                           geom->width, geom->height, rows_per, A);
     }
     if (launch_status() != UVL_OK) return UVL_E_DEVICE;
     if (!areas_host) return UVL_OK;

@@ -7,8 +7,9 @@
 //
 // Tiling: a 256-thread workgroup owns 4096 consecutive texels as 4 chunks of
 // 1024; lane l of chunk c reads texels [c*1024 + 4l, c*1024 + 4l + 4) of each
-// plane as one 16-byte load, so a wave's loads are 1 KiB contiguous per
-// plane.  All 12 loads of a thread are issued before any predicate.
+// plane as one 16-byte non-temporal load, so a wave's loads are 1 KiB
+// contiguous per plane.  All 12 loads of a thread are issued before any
+// predicate.
 #include <math.h>
 
 #include "edit_texel.h"
@@ -50,54 +51,48 @@ __device__ __forceinline__ void store4<uint16_t>(uint16_t *__restrict__ L, int64
     }
 }
 
-struct BrushOp {
-    BrushParams p;
-    __device__ __forceinline__ bool operator()(float x, float y, float z) const { return brush_texel(p, x, y, z); }
-};
-
-struct LassoOp {
-    const LassoParams *p;
-    const float *depth;
-    __device__ __forceinline__ bool operator()(float x, float y, float z) const {
-        return lasso_texel(*p, depth, x, y, z);
-    }
-};
-
-template <typename T, typename Op>
-__device__ __forceinline__ void edit_tile(const float *__restrict__ px, const float *__restrict__ py,
-                                          const float *__restrict__ pz, T *__restrict__ L, int64_t n, Op op,
-                                          T label) {
+template <typename T>
+__device__ __forceinline__ void edit_tail(const float *__restrict__ px, const float *__restrict__ py,
+                                          const float *__restrict__ pz, T *__restrict__ L, int64_t n,
+                                          const BrushParams *B, const LassoParams *P,
+                                          const float *__restrict__ depth, T label) {
     const int64_t base = (int64_t)blockIdx.x * kTile + threadIdx.x * 4;
-    if (base + 3 * kChunk + 4 <= n) {
-        float4 X[4], Y[4], Z[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            X[c] = *reinterpret_cast<const float4 *>(px + base + c * kChunk);
-            Y[c] = *reinterpret_cast<const float4 *>(py + base + c * kChunk);
-            Z[c] = *reinterpret_cast<const float4 *>(pz + base + c * kChunk);
+    for (int c = 0; c < 4; ++c)
+        for (int k = 0; k < 4; ++k) {
+            const int64_t t = base + c * kChunk + k;
+            if (t >= n) continue;
+            const bool s = B ? brush_texel(*B, px[t], py[t], pz[t]) : lasso_texel(*P, depth, px[t], py[t], pz[t]);
+            if (s) L[t] = label;
         }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const bool s0 = op(X[c].x, Y[c].x, Z[c].x);
-            const bool s1 = op(X[c].y, Y[c].y, Z[c].y);
-            const bool s2 = op(X[c].z, Y[c].z, Z[c].z);
-            const bool s3 = op(X[c].w, Y[c].w, Z[c].w);
-            store4<T>(L, base + c * kChunk, s0, s1, s2, s3, label);
-        }
-    } else {
-        for (int c = 0; c < 4; ++c)
-            for (int k = 0; k < 4; ++k) {
-                const int64_t t = base + c * kChunk + k;
-                if (t < n && op(px[t], py[t], pz[t])) L[t] = label;
-            }
-    }
 }
 
+// One workgroup tile of 4096 texels; the full-tile test is uniform over the
+// workgroup, so whole waves take the same path (the lasso's wave-wide
+// polygon test needs every lane).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_brush(const float *__restrict__ px, const float *__restrict__ py,
                                                   const float *__restrict__ pz, T *__restrict__ L, int64_t n,
                                                   BrushParams p, uint32_t label) {
-    edit_tile<T>(px, py, pz, L, n, BrushOp{p}, (T)label);
+    const int64_t base = (int64_t)blockIdx.x * kTile + threadIdx.x * 4;
+    if ((int64_t)(blockIdx.x + 1) * kTile > n) {
+        edit_tail<T>(px, py, pz, L, n, &p, nullptr, nullptr, (T)label);
+        return;
+    }
+    float4 X[4], Y[4], Z[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        X[c] = load_stream4(px + base + c * kChunk);
+        Y[c] = load_stream4(py + base + c * kChunk);
+        Z[c] = load_stream4(pz + base + c * kChunk);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const bool s0 = brush_texel(p, X[c].x, Y[c].x, Z[c].x);
+        const bool s1 = brush_texel(p, X[c].y, Y[c].y, Z[c].y);
+        const bool s2 = brush_texel(p, X[c].z, Y[c].z, Z[c].z);
+        const bool s3 = brush_texel(p, X[c].w, Y[c].w, Z[c].w);
+        store4<T>(L, base + c * kChunk, s0, s1, s2, s3, (T)label);
+    }
 }
 
 template <typename T>
@@ -105,7 +100,24 @@ __global__ __launch_bounds__(kBlock) void k_lasso(const float *__restrict__ px, 
                                                   const float *__restrict__ pz, T *__restrict__ L, int64_t n,
                                                   LassoParams p, const float *__restrict__ depth,
                                                   uint32_t label) {
-    edit_tile<T>(px, py, pz, L, n, LassoOp{&p, depth}, (T)label);
+    const int64_t base = (int64_t)blockIdx.x * kTile + threadIdx.x * 4;
+    if ((int64_t)(blockIdx.x + 1) * kTile > n) {
+        edit_tail<T>(px, py, pz, L, n, nullptr, &p, depth, (T)label);
+        return;
+    }
+    float4 X[4], Y[4], Z[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        X[c] = load_stream4(px + base + c * kChunk);
+        Y[c] = load_stream4(py + base + c * kChunk);
+        Z[c] = load_stream4(pz + base + c * kChunk);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        bool s[4];
+        lasso_quad(p, depth, X[c], Y[c], Z[c], s);
+        store4<T>(L, base + c * kChunk, s[0], s[1], s[2], s[3], (T)label);
+    }
 }
 
 int32_t check_edit(const uvl_geom *g, const uvl_layer *l, uint32_t label) {
@@ -135,19 +147,38 @@ bool make_lasso_params(const float view_proj[16], const float *poly, int32_t n, 
         if (!std::isfinite(x0) || !std::isfinite(y0)) return false;
         const float dx = x1 - x0, dy = y1 - y0;
         const bool up = y1 > y0;
-        p.x0[k] = x0;
-        p.y0[k] = y0;
-        p.y1[k] = y1;
-        p.sdx[k] = up ? dx : -dx;
-        p.sdy[k] = up ? dy : -dy;
+        p.edge[k] = LassoEdge{x0, y0, y1, up ? dx : -dx, up ? dy : -dy, fmaxf(x0, x1), 0.0f, 0.0f};
         ylo = fminf(ylo, y0);
         yhi = fmaxf(yhi, y0);
         xhi = fmaxf(xhi, x0);
     }
-    for (int k = n; k < kMaxPoly; ++k) p.x0[k] = p.y0[k] = p.y1[k] = p.sdx[k] = p.sdy[k] = 0.0f;
+    for (int k = n; k < kMaxPoly; ++k) p.edge[k] = LassoEdge{};
     p.ylo = ylo;
     p.yhi = yhi;
     p.xhi = xhi;
+    p.ylo_m = ylo - 1e-4f * (1.0f + fabsf(ylo));
+    p.yhi_m = yhi + 1e-4f * (1.0f + fabsf(yhi));
+    p.xhi_m = xhi + 1e-4f * (1.0f + fabsf(xhi));
+    // y-slabs: slab s holds the edges whose y-range meets
+    // [ylo + (s - 1e-3)/inv_h, ylo + (s + 1 + 1e-3)/inv_h]; horizontal edges
+    // never straddle and are left out
+    // (with no usable slab height every texel maps to slab 0, which then
+    // holds every edge)
+    const float hf = (yhi - ylo) / (float)kSlabs;
+    p.inv_h = hf > 0.0f ? 1.0f / hf : 0.0f;
+    if (!std::isfinite(p.inv_h)) p.inv_h = 0.0f;
+    for (int s = 0; s < kSlabs; ++s) {
+        uint64_t m = 0;
+        const double lo = p.inv_h > 0.0f ? (double)ylo + (s - 1e-3) / (double)p.inv_h : -INFINITY;
+        const double hi = p.inv_h > 0.0f ? (double)ylo + (s + 1 + 1e-3) / (double)p.inv_h : INFINITY;
+        for (int k = 0; k < n; ++k) {
+            const LassoEdge &E = p.edge[k];
+            if (E.y0 == E.y1) continue;
+            const double emin = fmin(E.y0, E.y1), emax = fmax(E.y0, E.y1);
+            if (emin <= hi && emax >= lo) m |= 1ull << k;
+        }
+        p.slab_edges[s] = m;
+    }
     return true;
 }
 

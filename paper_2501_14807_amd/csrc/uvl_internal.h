@@ -43,7 +43,15 @@ inline bool geom_pos_ok(const uvl_geom *g) {
            aligned16(g->pos_z);
 }
 
-// Fills (device kernels in fill.hip); safe inside graph capture.
+// 16-byte streaming load that bypasses cache residency (each position is read
+// once per edit; the planes are far larger than the caches).
+typedef float uvl_f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 load_stream4(const float *p) {
+    const uvl_f4v v = __builtin_nontemporal_load(reinterpret_cast<const uvl_f4v *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+// Fills (device kernels in common.hip); safe inside graph capture.
 void fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 void fill_bytes(void *p, int64_t nbytes, hipStream_t s);   // zero
 

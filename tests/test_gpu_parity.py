@@ -258,6 +258,43 @@ def test_lasso_large_polygon_and_idempotence(gpu, orc):
     assert (first == 200).sum() > 100
 
 
+def _adversarial_polygons():
+    rng = np.random.default_rng(21)
+    P = []
+    P.append(np.array([[-0.5, -0.5], [0.5, -0.5], [0.5, 0.5], [-0.5, 0.5]]))          # horizontal edges
+    P.append(np.array([[-0.2, -0.9], [0.3, -0.9], [0.3, -0.1], [0.3, 0.6], [-0.2, 0.6]]))  # collinear
+    P.append(np.array([[0.0, 0.0], [0.0, 0.0], [0.4, 0.1], [0.4, 0.1], [0.1, 0.5]]))     # repeated vertices
+    P.append(np.array([[0.1, 0.2], [0.3, 0.2], [0.5, 0.2]]))                            # zero height
+    P.append(np.array([[0.1, 0.2], [0.1 + 1e-6, 0.2], [0.1, 0.2 + 1e-6]]))              # tiny
+    P.append(np.array([[-3, -3], [3, -3], [3, 3], [-3, 3]]))                            # covers the screen
+    P.append(np.array([[2, 2], [3, 2], [3, 3]]))                                         # off screen
+    k = np.arange(7)
+    P.append(np.stack([np.cos(6 * np.pi * k / 7), np.sin(6 * np.pi * k / 7)], 1) * 0.7)  # self-intersecting
+    P.append(synth.star_polygon(rng, 64))
+    q = np.round(rng.uniform(-1, 1, size=(40, 2)) * 8) / 8                              # grid-snapped zigzag
+    P.append(q)
+    return [np.asarray(p, np.float32) for p in P]
+
+
+def test_lasso_adversarial_polygons(gpu, orc):
+    import torch
+    wl = synth.tiny_workload()
+    W = 512
+    dm, g = _geom_gpu(gpu, wl.mesh, W, W)
+    og = orc.geometry_image(wl.mesh, W, W)
+    d = torch.empty((256, 256), dtype=torch.float32, device="cuda")
+    for ci in (0, 5):
+        M = wl.cameras[ci]
+        gpu.render_depth(dm, M, d)
+        od = orc.depth_map(wl.mesh, M, 256, 256)
+        for k, poly in enumerate(_adversarial_polygons()):
+            lay = gpu.create_layer(gpu.Layer(W, W, gpu.U8))
+            gpu.edit_lasso(g, lay, M, poly, d, 1e-4, 1 + k)
+            ref = np.zeros(W * W, np.uint8)
+            orc.lasso(og.pos32, ref, M, poly, od, 1e-4, 1 + k)
+            assert np.array_equal(lay.numpy(), ref), (ci, k)
+
+
 # ---------------------------------------------------------------------------
 # layer algebra
 
