@@ -208,6 +208,73 @@ int32_t uvl_layer_op(int32_t op, const uvl_layer *dst, const uvl_layer *a, const
 int32_t uvl_area_query(const uvl_geom *geom, const uvl_layer *layers, int32_t nlayers,
                        uint64_t *bins_dev, double *areas_host, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batched edit waves.  The paper applies one edit per rendering pass
+ * (§4.3.1); a wave applies many pending edits -- of many models and layers --
+ * with one persistent-kernel launch.  Each edit's selection depends only on
+ * the texel's stored position, so the result of a wave is bit-identical to
+ * calling uvl_edit_brush / uvl_edit_lasso once per edit in array order.
+ * ------------------------------------------------------------------------ */
+typedef enum { UVL_EDIT_BRUSH = 0, UVL_EDIT_LASSO = 1 } uvl_edit_kind;
+
+/* One edit of a wave.  geom and layer are host pointers to descriptors of
+ * device data (as for the single-edit calls); all edits of one layer must
+ * name the same geometry image.  Brush: center, radius.  Lasso: view_proj
+ * (host float[16]), poly_xy (host float[npoly][2], 3 <= npoly <= 64), depth
+ * (device [dh][dw] map rendered with that matrix), bias. */
+typedef struct {
+    const uvl_geom *geom;
+    const uvl_layer *layer;
+    int32_t kind;           /* uvl_edit_kind */
+    uint32_t label;
+    float center[3];
+    float radius;
+    const float *view_proj;
+    const float *poly_xy;
+    int32_t npoly;
+    int32_t dw, dh;
+    float bias;
+    const float *depth;
+} uvl_edit;
+
+typedef struct uvl_wave uvl_wave;   /* opaque handle */
+
+/* Device workspace bytes for waves of up to max_edits edits, of which up to
+ * max_lassos are lassos. */
+size_t uvl_wave_workspace_bytes(int32_t max_edits, int32_t max_lassos);
+
+/* Create a wave handle over a caller-owned device workspace (256-byte
+ * aligned, uvl_wave_workspace_bytes bytes, kept alive until destroy).  The
+ * handle owns a pinned host staging buffer, a capture stream and the HIP
+ * graph of the launch; it allocates no device memory itself.
+ * Errors: UVL_E_INVAL, UVL_E_NOMEM (workspace too small), UVL_E_DEVICE. */
+int32_t uvl_wave_create(int32_t max_edits, int32_t max_lassos, void *ws, size_t ws_bytes, uvl_wave **out);
+
+/* Apply edits[0..n) on `stream`: the descriptor is copied host->device into
+ * the workspace, then the captured graph (counter reset + persistent kernel)
+ * is replayed.  tile_chunks in 1..8 forces tiles of tile_chunks*1024 texels;
+ * 0 uses the tuned size of each layer's atlas size (4 if not tuned).  Edits
+ * of different layers are independent; edits of one layer apply in order.
+ * The edits array may be freed on return.  Submits on one handle are
+ * serialised; the workspace is reused, so a submit waits until the previous
+ * submit's descriptor copy has completed.
+ * Errors: as the single-edit calls, plus UVL_E_NOMEM if n exceeds the
+ * handle's capacity. */
+int32_t uvl_wave_submit(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t tile_chunks, void *stream);
+
+/* Autotune the tile size per atlas size class (power of two of the texel
+ * count) present in edits: each of 1, 2, 4, 8 chunks is timed on the class's
+ * edits (applying a wave again leaves the layers unchanged, so the layers
+ * end as after one submit).  SYNCHRONOUS. */
+int32_t uvl_wave_tune(uvl_wave *w, const uvl_edit *edits, int32_t n, void *stream);
+
+/* The tuned tile size (chunks of 1024 texels) for an atlas of `texels`
+ * texels, 0 if that size class is not tuned. */
+int32_t uvl_wave_tuned_chunks(const uvl_wave *w, int64_t texels);
+
+/* Release the handle (waits for its last descriptor copy). */
+int32_t uvl_wave_destroy(uvl_wave *w);
+
 #ifdef __cplusplus
 }
 #endif

@@ -61,8 +61,11 @@ struct LassoParams {
 
 // Everything but the polygon test: true if the texel is a candidate, with
 // its NDC position.
-__device__ __forceinline__ bool lasso_front(const LassoParams &P, const float *__restrict__ depth, float x,
-                                            float y, float z, float &xn, float &yn) {
+// PT is LassoParams, possibly qualified with the constant address space so
+// that a parameter block in global memory is read with scalar loads.
+template <class PT>
+__device__ __forceinline__ bool lasso_front(const PT &P, const float *__restrict__ depth, float x, float y,
+                                            float z, float &xn, float &yn) {
     float c[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
@@ -93,7 +96,8 @@ __device__ __forceinline__ bool lasso_front(const LassoParams &P, const float *_
     return d <= depth[(int64_t)iy * P.dw + ix] + P.bias;
 }
 
-__device__ __forceinline__ int lasso_slab(const LassoParams &P, float yn) {
+template <class PT>
+__device__ __forceinline__ int lasso_slab(const PT &P, float yn) {
     int s = (int)((yn - P.ylo) * P.inv_h);
     s = s < 0 ? 0 : s;
     return s > kSlabs - 1 ? kSlabs - 1 : s;
@@ -109,8 +113,9 @@ __device__ __forceinline__ void lasso_edge(float ex0, float ey0, float ey1, floa
 }
 
 // The whole predicate for one texel (edges of its own slab).
-__device__ __forceinline__ bool lasso_texel(const LassoParams &P, const float *__restrict__ depth, float x,
-                                            float y, float z) {
+template <class PT>
+__device__ __forceinline__ bool lasso_texel(const PT &P, const float *__restrict__ depth, float x, float y,
+                                            float z) {
     float xn, yn;
     if (!lasso_front(P, depth, x, y, z, xn, yn)) return false;
     uint64_t m = P.slab_edges[lasso_slab(P, yn)];
@@ -118,8 +123,7 @@ __device__ __forceinline__ bool lasso_texel(const LassoParams &P, const float *_
     while (m) {
         const int e = __builtin_ctzll(m);
         m &= m - 1;
-        const LassoEdge E = P.edge[e];
-        lasso_edge(E.x0, E.y0, E.y1, E.sdx, E.sdy, xn, yn, inside);
+        lasso_edge(P.edge[e].x0, P.edge[e].y0, P.edge[e].y1, P.edge[e].sdx, P.edge[e].sdy, xn, yn, inside);
     }
     return inside;
 }
@@ -165,7 +169,8 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
 // skipped: for a point right of both ends the crossing test is false even
 // after rounding (the same monotonicity argument as the xhi bound).
 // Must be called by all 64 lanes.
-__device__ __forceinline__ void lasso_quad(const LassoParams &P, const float *__restrict__ depth, const float4 &X,
+template <class PT>
+__device__ __forceinline__ void lasso_quad(const PT &P, const float *__restrict__ depth, const float4 &X,
                                            const float4 &Y, const float4 &Z, bool sel[4]) {
     const float xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w}, zs[4] = {Z.x, Z.y, Z.z, Z.w};
     float xn[4], yn[4];
@@ -193,10 +198,11 @@ __device__ __forceinline__ void lasso_quad(const LassoParams &P, const float *__
         while (m) {
             const int e = __builtin_ctzll(m);
             m &= m - 1;
-            const LassoEdge E = P.edge[e];
-            if (E.xmax < wxmin) continue;
+            const float ex0 = P.edge[e].x0, ey0 = P.edge[e].y0, ey1 = P.edge[e].y1;
+            const float esdx = P.edge[e].sdx, esdy = P.edge[e].sdy, exmax = P.edge[e].xmax;
+            if (exmax < wxmin) continue;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) lasso_edge(E.x0, E.y0, E.y1, E.sdx, E.sdy, xn[k], yn[k], inside[k]);
+            for (int k = 0; k < 4; ++k) lasso_edge(ex0, ey0, ey1, esdx, esdy, xn[k], yn[k], inside[k]);
         }
     }
 #pragma unroll

@@ -81,6 +81,24 @@ class Model:
         for e in edits:
             self.apply(e, cameras)
 
+    def add_to_batch(self, batch: "uvl.EditBatch", edits, cameras):
+        """Append edits to a wave batch.  Each lasso camera's depth map is
+        rendered once into a map owned by the batch (alive until the batch is
+        dropped)."""
+        maps = {}
+        for e in edits:
+            layer = self.layers[e.layer]
+            if e.kind == "brush":
+                batch.brush(self.geom, layer, e.centre, e.radius, e.label)
+            else:
+                M = cameras[e.camera]
+                d = maps.get(e.camera)
+                if d is None:
+                    d = torch.empty((self.depth_h, self.depth_w), dtype=torch.float32, device=self.device)
+                    uvl.render_depth(self.mesh, M, d, self.depth_ws)
+                    maps[e.camera] = d
+                batch.lasso(self.geom, layer, M, e.poly, d, self.bias, e.label)
+
     # -- layer algebra ---------------------------------------------------------
     def upload_luts(self, ops):
         for o in ops:

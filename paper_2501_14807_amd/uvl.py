@@ -70,7 +70,23 @@ SIGNATURES = {
     "uvl_edit_lasso": ([_P, _P, _P, _P, _I32, _P, _I32, _I32, _F32, _U32, _P], _I32),
     "uvl_layer_op": ([_I32, _P, _P, _P, _U32, _U32, _U32, _P, _P], _I32),
     "uvl_area_query": ([_P, _P, _I32, _P, _P, _P], _I32),
+    "uvl_wave_workspace_bytes": ([_I32, _I32], _SZ),
+    "uvl_wave_create": ([_I32, _I32, _P, _SZ, _P], _I32),
+    "uvl_wave_submit": ([_P, _P, _I32, _I32, _P], _I32),
+    "uvl_wave_tune": ([_P, _P, _I32, _P], _I32),
+    "uvl_wave_tuned_chunks": ([_P, _I64], _I32),
+    "uvl_wave_destroy": ([_P], _I32),
 }
+
+EDIT_BRUSH, EDIT_LASSO = 0, 1
+
+
+class CEdit(ctypes.Structure):
+    _fields_ = [("geom", ctypes.c_void_p), ("layer", ctypes.c_void_p), ("kind", ctypes.c_int32),
+                ("label", ctypes.c_uint32), ("center", ctypes.c_float * 3), ("radius", ctypes.c_float),
+                ("view_proj", ctypes.c_void_p), ("poly_xy", ctypes.c_void_p), ("npoly", ctypes.c_int32),
+                ("dw", ctypes.c_int32), ("dh", ctypes.c_int32), ("bias", ctypes.c_float),
+                ("depth", ctypes.c_void_p)]
 
 
 def _lib():
@@ -317,3 +333,89 @@ def area_query(geom: GeometryImage, layers: Sequence[Layer], bins: Optional[torc
         out.append(host[off:off + k])
         off += k
     return out
+
+
+# ---------------------------------------------------------------------------
+# batched edit waves
+
+
+class EditBatch:
+    """A packed array of uvl_edit records plus the host arrays they point to."""
+
+    def __init__(self):
+        self._recs = []
+        self._keep = []
+
+    def brush(self, geom: GeometryImage, layer: Layer, center, radius: float, label: int):
+        c = _f32(center, 3)
+        r = CEdit()
+        r.geom, r.layer = ctypes.addressof(geom.c), ctypes.addressof(layer.c)
+        r.kind, r.label = EDIT_BRUSH, int(label)
+        r.center[0], r.center[1], r.center[2] = float(c[0]), float(c[1]), float(c[2])
+        r.radius = float(np.float32(radius))
+        self._recs.append(r)
+        self._keep.append((geom, layer))
+
+    def lasso(self, geom: GeometryImage, layer: Layer, view_proj, poly, depth: torch.Tensor, bias: float,
+              label: int):
+        M = _f32(view_proj, 16)
+        P = _f32(poly).reshape(-1)
+        r = CEdit()
+        r.geom, r.layer = ctypes.addressof(geom.c), ctypes.addressof(layer.c)
+        r.kind, r.label = EDIT_LASSO, int(label)
+        r.view_proj = M.ctypes.data
+        r.poly_xy = P.ctypes.data
+        r.npoly = P.size // 2
+        r.dh, r.dw = depth.shape
+        r.bias = float(np.float32(bias))
+        r.depth = depth.data_ptr()
+        self._recs.append(r)
+        self._keep.append((geom, layer, M, P, depth))
+
+    def __len__(self):
+        return len(self._recs)
+
+    @property
+    def n_lassos(self) -> int:
+        return sum(1 for r in self._recs if r.kind == EDIT_LASSO)
+
+    def array(self):
+        return (CEdit * len(self._recs))(*self._recs)
+
+
+class Wave:
+    """Handle for batched edit waves (uvl_wave_*), workspace owned here."""
+
+    def __init__(self, max_edits: int, max_lassos: int, device="cuda"):
+        L = _lib()
+        need = L.uvl_wave_workspace_bytes(int(max_edits), int(max_lassos))
+        if need == 0:
+            raise ValueError("bad wave capacity")
+        self.ws = torch.empty(need, dtype=torch.uint8, device=device)
+        self.h = ctypes.c_void_p()
+        _check(L.uvl_wave_create(int(max_edits), int(max_lassos), _ptr(self.ws), need, ctypes.byref(self.h)),
+               "uvl_wave_create")
+        self.max_edits, self.max_lassos = int(max_edits), int(max_lassos)
+
+    def submit(self, batch: EditBatch, tile_chunks: int = 0, stream=None):
+        arr = batch.array()
+        _check(_lib().uvl_wave_submit(self.h, arr, len(batch), int(tile_chunks), _stream(stream)),
+               "uvl_wave_submit")
+
+    def tune(self, batch: EditBatch, stream=None):
+        arr = batch.array()
+        _check(_lib().uvl_wave_tune(self.h, arr, len(batch), _stream(stream)), "uvl_wave_tune")
+
+    def tuned_chunks(self, texels: int) -> int:
+        return int(_lib().uvl_wave_tuned_chunks(self.h, int(texels)))
+
+    def close(self):
+        if self.h:
+            _lib().uvl_wave_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,146 @@
+"""Batched edit waves: one persistent launch == the edits applied one launch
+at a time, bit for bit, for every tile size, across models, layers, dtypes
+and ragged atlases; and against the CPU oracle."""
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_14807_amd import uvl
+    uvl.device_check()
+    return uvl
+
+
+def _models(gpu):
+    from paper_2501_14807_amd.model import Model
+    tiny = synth.tiny_workload()
+    scan = synth.scan_workload(n_brush=30, n_lasso=30, n_ops=0, W=1024, n_charts=4, nx=64, ny=32, depth=512)
+    out = []
+    m = Model.from_workload(tiny).build()
+    out.append((m, tiny, tiny.edits))
+    # the same vessel on a ragged atlas with a u16 layer
+    m2 = Model(tiny.mesh, 37 * 11, 53 * 5, [gpu.U16, gpu.U8], depth_w=128, depth_h=96).build()
+    rng = np.random.default_rng(3)
+    edits2 = []
+    for e in tiny.edits[:40]:
+        e2 = type(e)(**{**e.__dict__})
+        e2.layer = int(rng.integers(0, 2))
+        e2.label = int(rng.integers(0, 65536 if e2.layer == 0 else 256))
+        edits2.append(e2)
+    out.append((m2, tiny, edits2))
+    m3 = Model.from_workload(scan).build()
+    out.append((m3, scan, scan.edits))
+    return out
+
+
+def _plain(gpu, models):
+    """Reference: fresh layers, edits applied one launch each."""
+    res = []
+    for m, wl, edits in models:
+        m.clear_layers()
+        m.apply_all(edits, wl.cameras)
+        res.append([l.numpy().copy() for l in m.layers])
+    return res
+
+
+def test_wave_equals_plain_all_tile_sizes(gpu):
+    models = _models(gpu)
+    ref = _plain(gpu, models)
+    n = sum(len(e) for _, _, e in models)
+    wave = gpu.Wave(max_edits=n, max_lassos=n)
+    for chunks in (1, 2, 4, 8, 0):
+        batch = gpu.EditBatch()
+        for m, wl, edits in models:
+            m.clear_layers()
+            m.add_to_batch(batch, edits, wl.cameras)
+        wave.submit(batch, tile_chunks=chunks)
+        for (m, _, _), r in zip(models, ref):
+            for k, l in enumerate(m.layers):
+                assert np.array_equal(l.numpy(), r[k]), (chunks, k)
+    wave.close()
+
+
+def test_wave_against_oracle_and_interleaving(gpu, orc):
+    from oracle import workload
+    from paper_2501_14807_amd.model import Model
+    wl = synth.tiny_workload()
+    og, ol, _ = workload.run(wl)
+    m = Model.from_workload(wl).build()
+    wave = gpu.Wave(64, 64)
+    # two submits in a row: first half, then second half
+    for part in (wl.edits[:29], wl.edits[29:]):
+        b = gpu.EditBatch()
+        m.add_to_batch(b, part, wl.cameras)
+        wave.submit(b)
+    assert np.array_equal(m.layers[0].numpy(), ol[0])
+    # resubmitting a wave leaves the layers unchanged
+    b = gpu.EditBatch()
+    m.add_to_batch(b, wl.edits, wl.cameras)
+    wave.submit(b)
+    wave.submit(b)
+    assert np.array_equal(m.layers[0].numpy(), ol[0])
+    wave.close()
+
+
+def test_wave_tune_then_submit(gpu):
+    models = _models(gpu)[:2]
+    ref = _plain(gpu, models)
+    n = sum(len(e) for _, _, e in models)
+    wave = gpu.Wave(n, n)
+    batch = gpu.EditBatch()
+    for m, wl, edits in models:
+        m.clear_layers()
+        m.add_to_batch(batch, edits, wl.cameras)
+    wave.tune(batch)
+    for m, _, _ in models:
+        assert wave.tuned_chunks(m.geom.n) in (1, 2, 4, 8)
+    for m, _, _ in models:
+        m.clear_layers()
+    wave.submit(batch)
+    for (m, _, _), r in zip(models, ref):
+        for k, l in enumerate(m.layers):
+            assert np.array_equal(l.numpy(), r[k])
+    wave.close()
+
+
+def test_wave_errors(gpu):
+    from paper_2501_14807_amd.model import Model
+    wl = synth.tiny_workload()
+    m = Model.from_workload(wl).build()
+    wave = gpu.Wave(4, 1)
+    b = gpu.EditBatch()
+    m.add_to_batch(b, wl.edits[:6], wl.cameras)
+    with pytest.raises(gpu.UvlError) as ei:
+        wave.submit(b)
+    assert ei.value.code == -4            # more edits than the handle holds
+    b = gpu.EditBatch()
+    lassos = [e for e in wl.edits if e.kind == "lasso"][:2]
+    m.add_to_batch(b, lassos, wl.cameras)
+    with pytest.raises(gpu.UvlError) as ei:
+        wave.submit(b)
+    assert ei.value.code == -4            # more lassos than the handle holds
+    # one layer edited through two different geometry images
+    g2 = gpu.GeometryImage(wl.W, wl.H)
+    gpu.build_geometry_image(m.mesh, g2)
+    b = gpu.EditBatch()
+    e = [x for x in wl.edits if x.kind == "brush"][0]
+    b.brush(m.geom, m.layers[0], e.centre, e.radius, 1)
+    b.brush(g2, m.layers[0], e.centre, e.radius, 2)
+    with pytest.raises(gpu.UvlError) as ei:
+        wave.submit(b)
+    assert ei.value.code == -1
+    b = gpu.EditBatch()
+    b.brush(m.geom, m.layers[0], e.centre, e.radius, 300)
+    with pytest.raises(gpu.UvlError) as ei:
+        wave.submit(b)
+    assert ei.value.code == -3
+    wave.close()
