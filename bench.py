@@ -47,6 +47,12 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-rows", type=int, default=64, help="atlas rows in the oracle's timed sample")
     p.add_argument("--cpu-edits", type=int, default=200, help="edits in the oracle's timed sample")
+    p.add_argument("--batch-models", type=int, default=256,
+                   help="models in the batched-wave comparison (0: skip it)")
+    p.add_argument("--serve-models", type=int, default=8,
+                   help="small + scan-scale models each in the serving comparison (0: skip it)")
+    p.add_argument("--serve-requests", type=int, default=4000)
+    p.add_argument("--serve-slo-ms", type=float, default=20.0)
     return p.parse_args()
 
 
@@ -116,6 +122,138 @@ def run_step(m, wl, uvl, T):
     with T.span("area_query"):
         bins = m.areas(sync=False)
     return bins
+
+
+def bench_batched(n_models, reps, torch, uvl):
+    """Batched waves against the plain path on many models of uneven size.
+
+    256 models (triangles log-uniform in 1e4..1e6, atlases 1024^2..8192^2,
+    one u8 layer each) with 1..64 pending edits each, half brushes, half
+    lassos (one camera per 8 lassos, 1024^2 depth maps).  Plain: one launch
+    per edit, depth maps rendered as the camera changes.  Batched: the same
+    depth maps, then one wave launch for all edits of all models.  Both start
+    from cleared layers and must end with identical layers.
+    """
+    import synth
+    from paper_2501_14807_amd.model import Model
+    t = time.perf_counter()
+    wls = synth.batch_workload(n_models=n_models)
+    log(f"batch workload generated in {time.perf_counter() - t:.1f} s")
+    models = [Model.from_workload(w, normals=False, bary=False).build() for w in wls]
+    n_edits = sum(len(w.edits) for w in wls)
+    n_lassos = sum(1 for w in wls for e in w.edits if e.kind == "lasso")
+    texels = sum(w.W * w.H for w in wls)
+    batch = uvl.EditBatch()
+    maps = [m.add_to_batch(batch, w.edits, w.cameras, render=False) for m, w in zip(models, wls)]
+    wave = uvl.Wave(max(1, n_edits), max(1, n_lassos))
+    for m, w, mp in zip(models, wls, maps):
+        m.clear_layers()
+        m.render_maps(mp, w.cameras)
+    wave.tune(batch)
+    tuned = {int(side): wave.tuned_chunks(side * side) for side in sorted({w.W for w in wls})}
+    torch.cuda.synchronize()
+
+    def plain():
+        for m, w in zip(models, wls):
+            m.clear_layers()
+            m.apply_all(w.edits, w.cameras)
+
+    def batched():
+        for m, w, mp in zip(models, wls, maps):
+            m.clear_layers()
+            m.render_maps(mp, w.cameras)
+        wave.submit(batch)
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) / 1e3)
+        return best
+
+    t_plain = timed(plain)
+    ref = [m.layers[0].data[:m.layers[0].n].clone() for m in models]
+    t_wave = timed(batched)
+    same = all(torch.equal(m.layers[0].data[:m.layers[0].n], r) for m, r in zip(models, ref))
+    # the wave kernel alone (depth maps already rendered)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    wave.submit(batch)
+    e1.record()
+    torch.cuda.synchronize()
+    t_kernel = e0.elapsed_time(e1) / 1e3
+    wave.close()
+    log(f"batched: plain {t_plain * 1e3:.1f} ms, wave pass {t_wave * 1e3:.1f} ms, identical={same}")
+    return {
+        "workload": f"{n_models} models, triangles log-uniform 1e4-1e6, atlases 1024^2-8192^2 "
+                    f"({texels / 1e9:.2f} G texels), 1-64 edits each, 1024^2 depth maps",
+        "edits": n_edits, "lassos": n_lassos,
+        "plain_edits_per_s": n_edits / t_plain, "batched_edits_per_s": n_edits / t_wave,
+        "speedup": t_plain / t_wave, "plain_ms": t_plain * 1e3, "batched_ms": t_wave * 1e3,
+        "wave_launch_ms": t_kernel * 1e3, "identical_layers": bool(same), "tuned_chunks": tuned,
+    }
+
+
+def bench_serving(n_each, n_requests, slo_ms, torch, uvl):
+    """Continuous batching against plain one-launch-per-request serving.
+
+    n_each vessel-size models (512^2) and n_each scan-scale models (8192^2,
+    4,145,280 triangles), each with a u8 and a u16 layer, all resident
+    (admitted by footprint within 200 GB); Poisson arrivals, 60% brush / 25%
+    lasso / 10% area / 5% layer operation, uniform model choice; a sweep of
+    arrival rates.  For each mode, the highest edits/s reached with p99
+    latency within the SLO.
+    """
+    import synth
+    from paper_2501_14807_amd.model import Model
+    from paper_2501_14807_amd.serve import GpuExecutor, Request, Server
+    t = time.perf_counter()
+    meshes, sizes, depth = [], [], []
+    for k in range(n_each):
+        meshes.append(synth.vessel(seed=100 + k))
+        sizes.append(512)
+        depth.append(256)
+    for k in range(n_each):
+        meshes.append(synth.scan_mesh(seed=1100 + k)[0])
+        sizes.append(8192)
+        depth.append(1024)
+    dtypes = [[uvl.U8, uvl.U16]] * len(meshes)
+    models = [Model(m, s_, s_, dt, depth_w=d, depth_h=d).build() for m, s_, dt, d in zip(meshes, sizes, dtypes, depth)]
+    log(f"serving: {len(models)} models resident after {time.perf_counter() - t:.1f} s")
+    sweep = []
+    for qps in (1000.0, 4000.0, 16000.0, 64000.0):
+        cams, stream = synth.serve_stream(meshes, dtypes, n_requests, qps, seed=int(qps))
+        row = {"qps": qps}
+        for mode in ("plain", "batched"):
+            for m in models:
+                m.clear_layers()
+            ex = GpuExecutor(models, cams, max_wave_edits=8192)
+            srv = Server(ex, len(models), 200 << 30)
+            reqs = [Request(i, d["t"], d["model"], d["kind"], edit=d.get("edit"), op=d.get("op"),
+                            layer=d.get("layer", 0)) for i, d in enumerate(stream)]
+            st = srv.run(reqs, mode)
+            torch.cuda.synchronize()
+            ex.wave.close()
+            row[mode] = st.as_dict()
+            log(f"serving qps {qps:.0f} {mode}: p50 {st.p50_ms:.2f} ms p99 {st.p99_ms:.2f} ms "
+                f"{st.edits_per_s:.0f} edits/s ({st.rounds} rounds)")
+        sweep.append(row)
+
+    def best(mode):
+        ok = [r[mode]["edits_per_s"] for r in sweep if r[mode]["p99_ms"] <= slo_ms]
+        return max(ok) if ok else None
+
+    bp, bb = best("plain"), best("batched")
+    return {"workload": f"{n_each} vessel-size (512^2) + {n_each} scan-scale (8192^2) models, u8+u16 layers, "
+                        f"{n_requests} Poisson requests per rate, 60/25/10/5 brush/lasso/area/op",
+            "sweep": sweep, "slo_p99_ms": slo_ms, "plain_edits_per_s_at_slo": bp,
+            "batched_edits_per_s_at_slo": bb, "ratio_at_slo": (bb / bp) if bp and bb else None}
 
 
 def copy_bandwidth(torch, nbytes=2 << 30, reps=10):
@@ -241,6 +379,15 @@ def main():
         kernels["area_query"]["gbps"] = ab / (stats["area_query"]["avg_us"] * 1e-6) / 1e9
     copy_gbps = copy_bandwidth(torch)
     log(f"device copy bandwidth {copy_gbps:.0f} GB/s")
+    batched = None
+    if args.batch_models > 0:
+        del m
+        torch.cuda.empty_cache()
+        batched = bench_batched(args.batch_models, 2, torch, uvl)
+        torch.cuda.empty_cache()
+    serving = None
+    if args.serve_models > 0:
+        serving = bench_serving(args.serve_models, args.serve_requests, args.serve_slo_ms, torch, uvl)
 
     out = {
         "metric": "edited texels/s (% HBM peak); batched edits/s + p50/p99 latency vs plain",
@@ -264,6 +411,8 @@ def main():
                      "bytes_per_launch": per_launch[kern], "avg_us": stats[kern]["avg_us"]},
         "kernels": kernels,
         "copy_gbps": copy_gbps,
+        "batched": batched,
+        "serving": serving,
     }
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample ...")

@@ -86,7 +86,16 @@ typedef struct {
  * area_scale and area_abs_err are written by uvl_build_geometry_image: a
  * texel's area is area_w * area_scale, off from the exact fp64 weight by at
  * most area_abs_err = area_scale / 2, so a label's area over k texels is
- * within k * area_abs_err. */
+ * within k * area_abs_err.
+ *   tile_box      optional (NULL: skipped): for each tile of UVL_TILE_SIDE x
+ *                 UVL_TILE_SIDE texels (tile (tx, ty) holds texels i in
+ *                 [32 tx, 32 tx + 32), j in [32 ty, 32 ty + 32); tiles are
+ *                 stored row-major, ceil(W/32) per row), the bounds of its
+ *                 covered positions as {min x, min y, min z, max x, max y,
+ *                 max z}; a tile without covered texels holds min = +inf,
+ *                 max = -inf.  ceil(W/32) * ceil(H/32) * 6 floats.  Batched
+ *                 waves use it to skip tiles an edit provably cannot select. */
+#define UVL_TILE_SIDE 32
 typedef struct {
     int32_t width, height;
     int32_t *tri_id;
@@ -96,6 +105,7 @@ typedef struct {
     uint32_t *area_w;
     double area_scale;      /* out: texel area = area_w * area_scale            */
     double area_abs_err;    /* out: bound on the rounding of one texel's area   */
+    float *tile_box;        /* optional per-tile position bounds (see above)    */
 } uvl_geom;
 
 /* A layer's data texture: width*height values of `dtype`, device memory,
@@ -240,24 +250,29 @@ typedef struct {
 typedef struct uvl_wave uvl_wave;   /* opaque handle */
 
 /* Device workspace bytes for waves of up to max_edits edits, of which up to
- * max_lassos are lassos. */
-size_t uvl_wave_workspace_bytes(int32_t max_edits, int32_t max_lassos);
+ * max_lassos are lassos, with room for max_cull_words tile-culling words (a
+ * layer whose geometry image has tile bounds needs ceil(edits / 64) words
+ * per 32 x 32 tile of its atlas; layers whose words do not fit run without
+ * culling, with identical results). */
+size_t uvl_wave_workspace_bytes(int32_t max_edits, int32_t max_lassos, int64_t max_cull_words);
 
 /* Create a wave handle over a caller-owned device workspace (256-byte
  * aligned, uvl_wave_workspace_bytes bytes, kept alive until destroy).  The
  * handle owns a pinned host staging buffer, a capture stream and the HIP
  * graph of the launch; it allocates no device memory itself.
  * Errors: UVL_E_INVAL, UVL_E_NOMEM (workspace too small), UVL_E_DEVICE. */
-int32_t uvl_wave_create(int32_t max_edits, int32_t max_lassos, void *ws, size_t ws_bytes, uvl_wave **out);
+int32_t uvl_wave_create(int32_t max_edits, int32_t max_lassos, int64_t max_cull_words, void *ws, size_t ws_bytes,
+                        uvl_wave **out);
 
 /* Apply edits[0..n) on `stream`: the descriptor is copied host->device into
- * the workspace, then the captured graph (counter reset + persistent kernel)
- * is replayed.  tile_chunks in 1..8 forces tiles of tile_chunks*1024 texels;
+ * the workspace, then the captured graph (counter reset, tile-culling masks,
+ * persistent kernel) is replayed.  tile_chunks in 1..8 forces tiles of tile_chunks*1024 texels;
  * 0 uses the tuned size of each layer's atlas size (4 if not tuned).  Edits
  * of different layers are independent; edits of one layer apply in order.
  * The edits array may be freed on return.  Submits on one handle are
- * serialised; the workspace is reused, so a submit waits until the previous
- * submit's descriptor copy has completed.
+ * serialised and must go to one stream (the device descriptor is reused in
+ * stream order); up to 4 submits may be in flight before a submit waits for
+ * the oldest one's descriptor copy.
  * Errors: as the single-edit calls, plus UVL_E_NOMEM if n exceeds the
  * handle's capacity. */
 int32_t uvl_wave_submit(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t tile_chunks, void *stream);

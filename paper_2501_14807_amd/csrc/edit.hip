@@ -140,7 +140,7 @@ bool make_lasso_params(const float view_proj[16], const float *poly, int32_t n, 
     p.dw = dw;
     p.dh = dh;
     p.n = n;
-    float ylo = INFINITY, yhi = -INFINITY, xhi = -INFINITY;
+    float ylo = INFINITY, yhi = -INFINITY, xhi = -INFINITY, xlo = INFINITY;
     for (int k = 0; k < n; ++k) {
         const float x0 = poly[2 * k], y0 = poly[2 * k + 1];
         const float x1 = poly[2 * ((k + 1) % n)], y1 = poly[2 * ((k + 1) % n) + 1];
@@ -151,14 +151,34 @@ bool make_lasso_params(const float view_proj[16], const float *poly, int32_t n, 
         ylo = fminf(ylo, y0);
         yhi = fmaxf(yhi, y0);
         xhi = fmaxf(xhi, x0);
+        xlo = fminf(xlo, x0);
     }
     for (int k = n; k < kMaxPoly; ++k) p.edge[k] = LassoEdge{};
     p.ylo = ylo;
     p.yhi = yhi;
     p.xhi = xhi;
+    p.xlo = xlo;
     p.ylo_m = ylo - 1e-4f * (1.0f + fabsf(ylo));
     p.yhi_m = yhi + 1e-4f * (1.0f + fabsf(yhi));
     p.xhi_m = xhi + 1e-4f * (1.0f + fabsf(xhi));
+    // tile culling planes (see LassoCull)
+    {
+        const double m = 2e-3;
+        const double rx0 = fmax(-1.0, (double)xlo) - m, rx1 = fmin(1.0, (double)xhi) + m;
+        const double ry0 = fmax(-1.0, (double)ylo) - m, ry1 = fmin(1.0, (double)yhi) + m;
+        double Md[16];
+        for (int k = 0; k < 16; ++k) Md[k] = (double)view_proj[k];
+        for (int j = 0; j < 4; ++j) {
+            p.cull.plane[0][j] = Md[j] - rx0 * Md[12 + j];          // clip_x - rx0 clip_w
+            p.cull.plane[1][j] = rx1 * Md[12 + j] - Md[j];          // rx1 clip_w - clip_x
+            p.cull.plane[2][j] = Md[4 + j] - ry0 * Md[12 + j];      // clip_y - ry0 clip_w
+            p.cull.plane[3][j] = ry1 * Md[12 + j] - Md[4 + j];      // ry1 clip_w - clip_y
+            p.cull.wrow[j] = Md[12 + j];
+            p.cull.ax[j] = fabs(Md[j]);
+            p.cull.ay[j] = fabs(Md[4 + j]);
+            p.cull.aw[j] = fabs(Md[12 + j]);
+        }
+    }
     // y-slabs: slab s holds the edges whose y-range meets
     // [ylo + (s - 1e-3)/inv_h, ylo + (s + 1 + 1e-3)/inv_h]; horizontal edges
     // never straddle and are left out
@@ -178,6 +198,16 @@ bool make_lasso_params(const float view_proj[16], const float *poly, int32_t n, 
             if (emin <= hi && emax >= lo) m |= 1ull << k;
         }
         p.slab_edges[s] = m;
+        float sx0 = INFINITY, sx1 = -INFINITY;
+        for (int k = 0; k < n; ++k)
+            if ((m >> k) & 1) {
+                const float ex1 = p.edge[k].xmax;
+                const float exa = poly[2 * k], exb = poly[2 * ((k + 1) % n)];
+                sx0 = fminf(sx0, fminf(exa, exb));
+                sx1 = fmaxf(sx1, ex1);
+            }
+        p.cull.slab_x0[s] = sx0;
+        p.cull.slab_x1[s] = sx1;
     }
     return true;
 }

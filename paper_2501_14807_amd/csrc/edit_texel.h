@@ -48,15 +48,33 @@ struct alignas(32) LassoEdge {
     float x0, y0, y1, sdx, sdy, xmax, pad0, pad1;   // xmax = max(x0, x1)
 };
 
+// Tile-culling data of a lasso, fp64 (filled on the host): four linear
+// functions L(p) = a . p + b, one per side of the polygon's screen rectangle
+// R = [max(-1, xlo), min(1, xhi)] x [max(-1, ylo), min(1, yhi)] widened by
+// 2e-3, each negative exactly where a point in front of the camera projects
+// beyond that side (e.g. clip_x - r clip_w for the left side); the clip w row;
+// and |M| of the x, y and w rows for the conditioning check.
+struct LassoCull {
+    double plane[4][4];
+    double wrow[4];
+    double ax[4], ay[4], aw[4];
+    // x-range of the edges that can straddle a point of slab s:
+    // [slab_x0[s], slab_x1[s]] (min / max over the edges of slab_edges[s];
+    // empty slab: x0 = +inf, x1 = -inf)
+    float slab_x0[kSlabs], slab_x1[kSlabs];
+};
+
 struct LassoParams {
     float M[16];
     float bias;
     int32_t dw, dh, n;
     float ylo, yhi, xhi;        // polygon bounds: min y, max y, max x
+    float xlo;                  // polygon min x (tile culling only)
     float ylo_m, yhi_m, xhi_m;  // the same widened by 1e-4 (1 + |v|), for the reciprocal pre-test
     float inv_h;                // slabs per unit of y
     uint64_t slab_edges[kSlabs];
     LassoEdge edge[kMaxPoly];
+    LassoCull cull;
 };
 
 // Everything but the polygon test: true if the texel is a candidate, with
@@ -207,6 +225,125 @@ __device__ __forceinline__ void lasso_quad(const PT &P, const float *__restrict_
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) sel[k] = cand[k] && inside[k];
+}
+
+// ---------------------------------------------------------------------------
+// Conservative tile tests.  box = {min x, min y, min z, max x, max y, max z}
+// of the covered positions of a tile (min > max: no covered texel).  A test
+// returns true only if no texel of the tile can be selected by the fp32
+// predicate above, so skipping culled tiles leaves every result unchanged.
+
+// Brush: the fp32 squared distance of the box to the centre, D2, is within
+// 6 ulps of the exact one, and a texel's fp32 d2 within 6 ulps of its exact
+// squared distance, which is >= the box's; D2 > r2 (1 + 1e-5) + 1e-30 then
+// forces d2 > r2 (the 1e-30 covers underflow).
+__device__ __forceinline__ bool brush_culls(const BrushParams &B, const float box[6]) {
+    if (!(box[0] <= box[3])) return true;
+    const float dx = fmaxf(fmaxf(box[0] - B.cx, B.cx - box[3]), 0.0f);
+    const float dy = fmaxf(fmaxf(box[1] - B.cy, B.cy - box[4]), 0.0f);
+    const float dz = fmaxf(fmaxf(box[2] - B.cz, B.cz - box[5]), 0.0f);
+    const float d2 = dx * dx + dy * dy + dz * dz;
+    return d2 > B.r2 * 1.00001f + 1e-30f;
+}
+
+// Lasso: a texel can only be selected if its fp32 NDC position lies in R
+// (outside R it fails the frustum test, the exact y / right-side rejections,
+// or -- left of every vertex by more than 1e-3 -- the crossing test counts
+// every straddling edge and leaves it outside).  The exact NDC position of a
+// point in front of the camera is beyond the widened side k iff L_k(p) < 0,
+// and L_k is linear, so max over the box of L_k < 0 (in fp64) puts every
+// texel of the tile beyond that side; its fp32 NDC position is within 4e-4 of
+// the exact one while clip w >= 1e-3 of the rows' |M| sums over the box
+// (checked first; otherwise nothing is culled), inside the 2e-3 widening.
+__device__ __forceinline__ double box_max(const double a[4], const float box[6]) {
+    double v = a[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) v += a[j] >= 0.0 ? a[j] * (double)box[3 + j] : a[j] * (double)box[j];
+    return v;
+}
+
+__device__ __forceinline__ double box_abs_max(const double a[4], const float box[6]) {
+    double v = a[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) v += a[j] * fmax(fabs((double)box[j]), fabs((double)box[3 + j]));
+    return v;
+}
+
+template <class PT>
+__device__ __forceinline__ bool lasso_culls_slabs(const PT &P, const float box[6]);
+
+template <class PT>
+__device__ __forceinline__ bool lasso_culls(const PT &P, const float box[6]) {
+    const auto &C = P.cull;
+    if (!(box[0] <= box[3] && box[1] <= box[4] && box[2] <= box[5])) return true;
+    double wneg[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) wneg[j] = -C.wrow[j];
+    const double wmin = -box_max(wneg, box);
+    double ax[4], ay[4], aw[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        ax[j] = C.ax[j];
+        ay[j] = C.ay[j];
+        aw[j] = C.aw[j];
+    }
+    const double smax = fmax(box_abs_max(ax, box), box_abs_max(ay, box)) + box_abs_max(aw, box);
+    if (!(wmin >= 1e-3 * smax) || !(wmin > 0.0)) return false;
+#pragma unroll 1
+    for (int k = 0; k < 4; ++k) {
+        double a[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a[j] = C.plane[k][j];
+        if (box_max(a, box) < 0.0) return true;
+    }
+    return lasso_culls_slabs(P, box);
+}
+
+// Tighter lasso test by y-slabs (reached only with the conditioning above
+// satisfied).  With every corner in front of the camera
+// (wmin > 0 above) the box projects into the bounding box of its corners'
+// NDC images (fp64 here, so within 1e-12), and every texel's fp32 NDC
+// position lies within eps = 5e-4 of that box.  A texel whose fp32 y falls in
+// slab s and whose fp32 x exceeds slab_x1[s] is right of every edge that can
+// straddle it (outside exactly), and one with x below slab_x0[s] - 1e-3 is
+// left of all of them by the margin (outside).  The texel slab index is
+// floor((y - ylo) inv_h) of an fp32 y; the slab range of the tile's y-range
+// is taken one slab wider on each side.  If every slab in that range misses
+// the tile's x-range, the tile is culled.
+template <class PT>
+__device__ __forceinline__ bool lasso_culls_slabs(const PT &P, const float box[6]) {
+    if (!(P.inv_h > 0.0f)) return false;
+    
+    double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+#pragma unroll 1
+    for (int k = 0; k < 8; ++k) {
+        const double x = (k & 1) ? box[3] : box[0];
+        const double y = (k & 2) ? box[4] : box[1];
+        const double z = (k & 4) ? box[5] : box[2];
+        double c[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            c[r] = (double)P.M[4 * r] * x + (double)P.M[4 * r + 1] * y + (double)P.M[4 * r + 2] * z + (double)P.M[4 * r + 3];
+        if (!(c[3] > 0.0)) return false;
+        const double xn = c[0] / c[3], yn = c[1] / c[3];
+        x0 = fmin(x0, xn);
+        x1 = fmax(x1, xn);
+        y0 = fmin(y0, yn);
+        y1 = fmax(y1, yn);
+    }
+    const double eps = 5e-4;
+    x0 -= eps;
+    x1 += eps;
+    const double h = 1.0 / (double)P.inv_h;
+    int s0 = (int)floor((y0 - eps - (double)P.ylo) / h) - 1;
+    int s1 = (int)floor((y1 + eps - (double)P.ylo) / h) + 1;
+    s0 = s0 < 0 ? 0 : s0;
+    s1 = s1 > kSlabs - 1 ? kSlabs - 1 : s1;
+    for (int s = s0; s <= s1; ++s) {
+        const double a = (double)P.cull.slab_x0[s] - 1e-3, b = (double)P.cull.slab_x1[s];
+        if (a <= x1 && b >= x0) return false;
+    }
+    return true;
 }
 
 }  // namespace uvl

@@ -382,6 +382,50 @@ __global__ __launch_bounds__(kBlock) void k_depth_big(Mat4 M, const float *__res
     }
 }
 
+// Per-tile bounds of the covered positions: one workgroup per tile of
+// UVL_TILE_SIDE x UVL_TILE_SIDE texels, a min/max over the non-NaN positions.
+__global__ __launch_bounds__(kBlock) void k_tile_box(const float *__restrict__ px, const float *__restrict__ py,
+                                                     const float *__restrict__ pz, int W, int H,
+                                                     float *__restrict__ box) {
+    __shared__ float s_red[6][kBlock / 64];
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const int i0 = (int)blockIdx.x * UVL_TILE_SIDE, j0 = (int)blockIdx.y * UVL_TILE_SIDE;
+    for (int k = threadIdx.x; k < UVL_TILE_SIDE * UVL_TILE_SIDE; k += kBlock) {
+        const int i = i0 + (k % UVL_TILE_SIDE), j = j0 + (k / UVL_TILE_SIDE);
+        if (i >= W || j >= H) continue;
+        const int64_t t = (int64_t)j * W + i;
+        const float v[3] = {px[t], py[t], pz[t]};
+        if (v[0] == v[0]) {     // covered (uncovered texels hold NaN)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                mn[c] = fminf(mn[c], v[c]);
+                mx[c] = fmaxf(mx[c], v[c]);
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            mn[c] = fminf(mn[c], __shfl_xor(mn[c], o));
+            mx[c] = fmaxf(mx[c], __shfl_xor(mx[c], o));
+        }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            s_red[c][wv] = mn[c];
+            s_red[3 + c][wv] = mx[c];
+        }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int c = threadIdx.x;
+        float r = s_red[c][0];
+        for (int w = 1; w < kBlock / 64; ++w) r = c < 3 ? fminf(r, s_red[c][w]) : fmaxf(r, s_red[c][w]);
+        box[6 * ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) + c] = r;
+    }
+}
+
 __global__ void k_counters_reset(Counters *ctr) {
     if (threadIdx.x == 0) {
         ctr->queue_len = 0;
@@ -439,6 +483,9 @@ extern "C" int32_t uvl_build_geometry_image(const uvl_mesh *mesh, uvl_geom *g, v
     hipLaunchKernelGGL(k_geom_attr, dim3(grid), dim3(kBlock), 0, s, mesh->uv, mesh->pos, mesh->nrm, mesh->tri, W,
                        H, gp, w_tri, ctr);
     hipLaunchKernelGGL(k_geom_quant, dim3(grid), dim3(kBlock), 0, s, g->tri_id, w_tri, g->area_w, N, ctr);
+    if (g->tile_box)
+        hipLaunchKernelGGL(k_tile_box, dim3((unsigned)ceil_div(W, UVL_TILE_SIDE), (unsigned)ceil_div(H, UVL_TILE_SIDE)),
+                           dim3(kBlock), 0, s, g->pos_x, g->pos_y, g->pos_z, W, H, g->tile_box);
     if (launch_status() != UVL_OK) return UVL_E_DEVICE;
     Counters host{};
     if (hipMemcpyAsync(&host, ctr, sizeof(Counters), hipMemcpyDeviceToHost, s) != hipSuccess) return UVL_E_DEVICE;

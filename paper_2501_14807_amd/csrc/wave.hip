@@ -9,11 +9,20 @@
 // is bit-identical to applying the edits one launch at a time.
 //
 // Work decomposition: edits are grouped by target layer into streams (each
-// stream keeps its edits' order); a stream is cut into tiles of
-// chunks x 1024 texels (chunks per stream chosen per atlas size by the
-// autotuner); a fixed grid of workgroups takes (stream, tile) items from an
-// atomic counter until none are left.  Every workgroup ends when the counter
-// passes the item count, so the grid always drains.
+// stream keeps its edits' order); a stream's atlas is cut into 32 x 32-texel
+// tiles (row-major), and an item is `chunks` consecutive tiles (chunks per
+// stream chosen per atlas size by the autotuner); a fixed grid of workgroups
+// takes (stream, item) pairs from an atomic counter until none are left.
+// Every workgroup ends when the counter passes the item count, so the grid
+// always drains.  In a tile, lane t covers row t/8 and columns 4(t%8)..+3.
+//
+// Tile culling (when the geometry image has tile bounds): a first kernel
+// gives every (tile, group of 64 edits) one wave, each lane tests one edit
+// against the tile's bounds (exact conservative tests, edit_texel.h), and the
+// ballot -- the mask of edits that may select something there -- is stored in
+// the workspace.  The wave kernel then reads a tile only if some edit is live
+// and evaluates only the live edits.  Streams whose masks do not fit the
+// workspace run without culling.
 //
 // The descriptor (streams, edits, lasso parameters) is copied host->device
 // into the caller's workspace before each launch; the counter reset and the
@@ -35,7 +44,7 @@ bool make_lasso_params(const float view_proj[16], const float *poly, int32_t n, 
 
 namespace {
 
-constexpr int kChunkTexels = kBlock * 4;   // 1024 texels per chunk, 4 per lane
+static_assert(UVL_TILE_SIDE * UVL_TILE_SIDE == kBlock * 4, "a tile is 4 texels per thread");
 constexpr int kMaxChunks = 8;
 constexpr int kWaveGrid = 2048;            // persistent workgroups (256 CUs x 8)
 
@@ -43,12 +52,16 @@ constexpr int kWaveGrid = 2048;            // persistent workgroups (256 CUs x 8
 
 struct WaveStream {
     const float *px, *py, *pz;
+    const float *box;   // per-tile position bounds, or null (no culling)
     void *layer;
-    int64_t n;          // texels
     int64_t item0;      // first item of this stream
+    int64_t mask0;      // first cull-mask word of this stream (running offset)
+    int32_t W, H;       // atlas size
+    int32_t tiles_x, ntiles;
     int32_t dtype;
     int32_t e0, ne;     // edits [e0, e0 + ne)
-    int32_t chunks;     // 1024-texel chunks per tile
+    int32_t chunks;     // tiles per item
+    int32_t cull;       // 1: masks at mask0 (tiles x groups words), 0: no culling
 };
 
 struct WaveEdit {
@@ -64,22 +77,26 @@ struct WaveHeader {
     int32_t nstreams;
     int32_t pad;
     int64_t total_items;
+    int64_t total_words;     // cull-mask words in use
     unsigned int counter;
     unsigned int pad2[3];
 };
 
-// Workspace layout: header | streams | edits | lassos
+// Workspace layout: header | streams | edits | lassos | cull masks
 struct Layout {
-    size_t streams, edits, lassos, total;
+    size_t streams, edits, lassos, masks, total;
+    int64_t max_words;
 };
 
-Layout layout(int32_t max_edits, int32_t max_lassos) {
+Layout layout(int32_t max_edits, int32_t max_lassos, int64_t max_words) {
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     Layout L;
     L.streams = 256;
     L.edits = L.streams + al(sizeof(WaveStream) * (size_t)max_edits);
     L.lassos = L.edits + al(sizeof(WaveEdit) * (size_t)max_edits);
-    L.total = L.lassos + al(sizeof(LassoParams) * (size_t)(max_lassos > 0 ? max_lassos : 1));
+    L.masks = L.lassos + al(sizeof(LassoParams) * (size_t)(max_lassos > 0 ? max_lassos : 1));
+    L.total = L.masks + al(sizeof(uint64_t) * (size_t)(max_words > 0 ? max_words : 1));
+    L.max_words = max_words;
     return L;
 }
 
@@ -88,8 +105,8 @@ __global__ void k_wave_reset(WaveHeader *h) {
 }
 
 template <typename T>
-__device__ __forceinline__ void wave_store(T *L, int64_t t, const uint32_t val[4], const bool wr[4], bool full,
-                                           int64_t n) {
+__device__ __forceinline__ void wave_store(T *L, int64_t t, const uint32_t val[4], const bool wr[4],
+                                           const bool in[4], bool full) {
     if (full && wr[0] && wr[1] && wr[2] && wr[3] && val[0] == val[1] && val[0] == val[2] && val[0] == val[3]) {
         if (sizeof(T) == 1) {
             *reinterpret_cast<uint32_t *>(L + t) = 0x01010101u * (val[0] & 0xffu);
@@ -101,19 +118,65 @@ __device__ __forceinline__ void wave_store(T *L, int64_t t, const uint32_t val[4
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-        if (wr[k] && t + k < n) L[t + k] = (T)val[k];
+        if (wr[k] && in[k]) L[t + k] = (T)val[k];
 }
 
-__global__ __launch_bounds__(kBlock) void k_wave(const char *__restrict__ ws, WaveHeader *__restrict__ hdr,
-                                                  size_t off_streams, size_t off_edits, size_t off_lassos) {
-    // read-only descriptor viewed in the constant address space: uniform
-    // reads become scalar loads
+// Cull masks: one wave per (tile, group of 64 edits) word, grid-striding
+// over the words in use.
+__global__ __launch_bounds__(kBlock) void k_wave_cull(const char *__restrict__ ws, const WaveHeader *__restrict__ hdr,
+                                                       size_t off_streams, size_t off_edits, size_t off_lassos,
+                                                       uint64_t *__restrict__ masks) {
     const UVL_CONST WaveStream *streams = (const UVL_CONST WaveStream *)(ws + off_streams);
     const UVL_CONST WaveEdit *edits = (const UVL_CONST WaveEdit *)(ws + off_edits);
     const UVL_CONST LassoParams *lassos = (const UVL_CONST LassoParams *)(ws + off_lassos);
+    const int32_t nstreams = hdr->nstreams;
+    const int64_t total = hdr->total_words;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t word = wave0; word < total; word += nwaves) {
+        // stream owning the word: the last stream with mask0 <= word (streams
+        // without culling own no words, so this is a culling stream)
+        int lo = 0, hi = nstreams - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (streams[mid].mask0 <= word) lo = mid;
+            else hi = mid - 1;
+        }
+        const UVL_CONST WaveStream &S = streams[lo];
+        const int groups = (S.ne + 63) >> 6;
+        const int64_t rel = word - S.mask0;
+        const int64_t ti = rel / groups;
+        const int g = (int)(rel % groups);
+        float box[6];
+        const UVL_CONST float *bp = (const UVL_CONST float *)(S.box + 6 * ti);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) box[q] = bp[q];
+        const int e = g * 64 + lane;
+        bool alive = false;
+        if (e < S.ne) {
+            const UVL_CONST WaveEdit &E = edits[S.e0 + e];
+            alive = E.kind == UVL_EDIT_BRUSH ? !brush_culls(BrushParams{E.cx, E.cy, E.cz, E.r2}, box)
+                                             : !lasso_culls(lassos[E.lasso], box);
+        }
+        const uint64_t m = __ballot(alive);
+        if (lane == 0) masks[word] = m;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_wave(const char *__restrict__ ws, WaveHeader *__restrict__ hdr,
+                                                  size_t off_streams, size_t off_edits, size_t off_lassos,
+                                                  const uint64_t *__restrict__ masks_in) {
+    // read-only descriptor and masks viewed in the constant address space:
+    // uniform reads become scalar loads
+    const UVL_CONST WaveStream *streams = (const UVL_CONST WaveStream *)(ws + off_streams);
+    const UVL_CONST WaveEdit *edits = (const UVL_CONST WaveEdit *)(ws + off_edits);
+    const UVL_CONST LassoParams *lassos = (const UVL_CONST LassoParams *)(ws + off_lassos);
+    const UVL_CONST uint64_t *masks = (const UVL_CONST uint64_t *)masks_in;
     __shared__ long long s_item;
     const int32_t nstreams = hdr->nstreams;
     const int64_t total = hdr->total_items;
+    const int trow = threadIdx.x >> 3, tcol = (threadIdx.x & 7) * 4;
     for (;;) {
         if (threadIdx.x == 0) s_item = (long long)atomicAdd(&hdr->counter, 1u);
         __syncthreads();
@@ -128,15 +191,28 @@ __global__ __launch_bounds__(kBlock) void k_wave(const char *__restrict__ ws, Wa
             else hi = mid - 1;
         }
         const UVL_CONST WaveStream &S = streams[lo];
-        const int chunks = S.chunks;
-        const int64_t tile0 = (item - S.item0) * (int64_t)chunks * kChunkTexels;
+        const int chunks = S.chunks, W = S.W, H = S.H;
+        const int groups = (S.ne + 63) >> 6;
+        const bool cull = S.cull != 0;
+        const int64_t tile_first = (item - S.item0) * (int64_t)chunks;
         for (int c = 0; c < chunks; ++c) {
-            const int64_t cbase = tile0 + (int64_t)c * kChunkTexels;
-            if (cbase >= S.n) break;
-            const bool full = cbase + kChunkTexels <= S.n;    // uniform over the workgroup
-            const int64_t t = cbase + threadIdx.x * 4;
+            const int64_t ti = tile_first + c;
+            if (ti >= S.ntiles) break;
+            const UVL_CONST uint64_t *tm = masks + (cull ? S.mask0 + ti * groups : 0);
+            if (cull) {
+                uint64_t any = 0;
+                for (int g = 0; g < groups; ++g) any |= tm[g];
+                if (!any) continue;
+            }
+            const int tx = (int)(ti % S.tiles_x), ty = (int)(ti / S.tiles_x);
+            // uniform over the workgroup: whole tile inside, rows 16-byte aligned
+            const bool full = (tx + 1) * UVL_TILE_SIDE <= W && (ty + 1) * UVL_TILE_SIDE <= H && (W & 3) == 0;
+            const int i = tx * UVL_TILE_SIDE + tcol, j = ty * UVL_TILE_SIDE + trow;
+            const int64_t t = (int64_t)j * W + i;
+            bool in[4];
             float4 X, Y, Z;
             if (full) {
+                in[0] = in[1] = in[2] = in[3] = true;
                 X = load_stream4(S.px + t);
                 Y = load_stream4(S.py + t);
                 Z = load_stream4(S.pz + t);
@@ -145,10 +221,10 @@ __global__ __launch_bounds__(kBlock) void k_wave(const char *__restrict__ ws, Wa
                 float xs[4], ys[4], zs[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    const bool in = t + k < S.n;
-                    xs[k] = in ? S.px[t + k] : nan;
-                    ys[k] = in ? S.py[t + k] : nan;
-                    zs[k] = in ? S.pz[t + k] : nan;
+                    in[k] = i + k < W && j < H;
+                    xs[k] = in[k] ? S.px[t + k] : nan;
+                    ys[k] = in[k] ? S.py[t + k] : nan;
+                    zs[k] = in[k] ? S.pz[t + k] : nan;
                 }
                 X = make_float4(xs[0], xs[1], xs[2], xs[3]);
                 Y = make_float4(ys[0], ys[1], ys[2], ys[3]);
@@ -156,26 +232,34 @@ __global__ __launch_bounds__(kBlock) void k_wave(const char *__restrict__ ws, Wa
             }
             uint32_t val[4] = {0, 0, 0, 0};
             bool wr[4] = {false, false, false, false};
-            for (int e = 0; e < S.ne; ++e) {
-                const UVL_CONST WaveEdit &E = edits[S.e0 + e];
-                bool sel[4];
-                if (E.kind == UVL_EDIT_BRUSH) {
-                    const BrushParams B{E.cx, E.cy, E.cz, E.r2};
-                    sel[0] = brush_texel(B, X.x, Y.x, Z.x);
-                    sel[1] = brush_texel(B, X.y, Y.y, Z.y);
-                    sel[2] = brush_texel(B, X.z, Y.z, Z.z);
-                    sel[3] = brush_texel(B, X.w, Y.w, Z.w);
-                } else {
-                    lasso_quad(lassos[E.lasso], E.depth, X, Y, Z, sel);
-                }
+            for (int g = 0; g < groups; ++g) {
+                uint64_t live = cull ? tm[g] : ~0ull;
+                const int base = g * 64;
+                const int lim = S.ne - base < 64 ? S.ne - base : 64;
+                if (lim < 64) live &= (1ull << lim) - 1;
+                while (live) {
+                    const int e = base + __builtin_ctzll(live);
+                    live &= live - 1;
+                    const UVL_CONST WaveEdit &E = edits[S.e0 + e];
+                    bool sel[4];
+                    if (E.kind == UVL_EDIT_BRUSH) {
+                        const BrushParams B{E.cx, E.cy, E.cz, E.r2};
+                        sel[0] = brush_texel(B, X.x, Y.x, Z.x);
+                        sel[1] = brush_texel(B, X.y, Y.y, Z.y);
+                        sel[2] = brush_texel(B, X.z, Y.z, Z.z);
+                        sel[3] = brush_texel(B, X.w, Y.w, Z.w);
+                    } else {
+                        lasso_quad(lassos[E.lasso], E.depth, X, Y, Z, sel);
+                    }
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    val[k] = sel[k] ? E.label : val[k];
-                    wr[k] = wr[k] || sel[k];
+                    for (int k = 0; k < 4; ++k) {
+                        val[k] = sel[k] ? E.label : val[k];
+                        wr[k] = wr[k] || sel[k];
+                    }
                 }
             }
-            if (S.dtype == UVL_U8) wave_store<uint8_t>(static_cast<uint8_t *>(S.layer), t, val, wr, full, S.n);
-            else wave_store<uint16_t>(static_cast<uint16_t *>(S.layer), t, val, wr, full, S.n);
+            if (S.dtype == UVL_U8) wave_store<uint8_t>(static_cast<uint8_t *>(S.layer), t, val, wr, in, full);
+            else wave_store<uint16_t>(static_cast<uint16_t *>(S.layer), t, val, wr, in, full);
         }
     }
 }
@@ -185,31 +269,36 @@ __global__ __launch_bounds__(kBlock) void k_wave(const char *__restrict__ ws, Wa
 
 using namespace uvl;
 
+constexpr int kStaging = 4;   // pinned descriptor buffers in rotation
+
 struct uvl_wave {
     int32_t max_edits, max_lassos;
     char *ws;              // device workspace
     size_t ws_bytes;
     Layout lay;
-    char *staging;         // pinned host copy of the descriptor
-    hipEvent_t staged;     // the last descriptor copy has been consumed
-    bool staged_pending;
+    char *staging;         // pinned host copy of the descriptor being packed
+    char *ring[kStaging];  // pinned buffers; ring[k] is free once copied[k] has fired
+    hipEvent_t copied[kStaging];
+    bool pending[kStaging];
+    int next;
     hipStream_t cap;       // private stream for graph capture
     hipGraphExec_t exec;
     std::mutex mu;
     int32_t tuned_chunks[32];   // per log2(texels); 0 = not tuned
 };
 
-extern "C" size_t uvl_wave_workspace_bytes(int32_t max_edits, int32_t max_lassos) {
-    if (max_edits < 1 || max_lassos < 0) return 0;
-    return layout(max_edits, max_lassos).total;
+extern "C" size_t uvl_wave_workspace_bytes(int32_t max_edits, int32_t max_lassos, int64_t max_cull_words) {
+    if (max_edits < 1 || max_lassos < 0 || max_cull_words < 0) return 0;
+    return layout(max_edits, max_lassos, max_cull_words).total;
 }
 
-extern "C" int32_t uvl_wave_create(int32_t max_edits, int32_t max_lassos, void *ws, size_t ws_bytes,
-                                   uvl_wave **out) {
-    if (!out || !ws || max_edits < 1 || max_edits > (1 << 20) || max_lassos < 0 || max_lassos > max_edits)
+extern "C" int32_t uvl_wave_create(int32_t max_edits, int32_t max_lassos, int64_t max_cull_words, void *ws,
+                                   size_t ws_bytes, uvl_wave **out) {
+    if (!out || !ws || max_edits < 1 || max_edits > (1 << 20) || max_lassos < 0 || max_lassos > max_edits ||
+        max_cull_words < 0)
         return UVL_E_INVAL;
     *out = nullptr;
-    const Layout lay = layout(max_edits, max_lassos);
+    const Layout lay = layout(max_edits, max_lassos, max_cull_words);
     if (ws_bytes < lay.total) return UVL_E_NOMEM;
     if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return UVL_E_INVAL;
     if (int32_t s = device_ok()) return s;
@@ -220,21 +309,29 @@ extern "C" int32_t uvl_wave_create(int32_t max_edits, int32_t max_lassos, void *
     w->ws_bytes = ws_bytes;
     w->lay = lay;
     w->staging = nullptr;
-    w->staged_pending = false;
+    w->next = 0;
     w->exec = nullptr;
     for (int k = 0; k < 32; ++k) w->tuned_chunks[k] = 0;
-    bool ok = hipHostMalloc(reinterpret_cast<void **>(&w->staging), lay.total, hipHostMallocDefault) == hipSuccess;
-    ok = ok && hipEventCreateWithFlags(&w->staged, hipEventDisableTiming) == hipSuccess;
+    bool ok = true;
+    for (int k = 0; k < kStaging && ok; ++k) {
+        w->pending[k] = false;
+        ok = hipHostMalloc(reinterpret_cast<void **>(&w->ring[k]), lay.masks, hipHostMallocDefault) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&w->copied[k], hipEventDisableTiming) == hipSuccess;
+    }
     ok = ok && hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking) == hipSuccess;
     if (ok) {
-        // capture reset + persistent kernel once; the descriptor is data
+        // capture reset + cull masks + persistent kernel once; the
+        // descriptor is data
         hipGraph_t g = nullptr;
         WaveHeader *hdr = reinterpret_cast<WaveHeader *>(w->ws);
+        uint64_t *masks = reinterpret_cast<uint64_t *>(w->ws + lay.masks);
         ok = hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
             hipLaunchKernelGGL(k_wave_reset, dim3(1), dim3(64), 0, w->cap, hdr);
+            hipLaunchKernelGGL(k_wave_cull, dim3(kWaveGrid), dim3(kBlock), 0, w->cap, w->ws, hdr, lay.streams,
+                               lay.edits, lay.lassos, masks);
             hipLaunchKernelGGL(k_wave, dim3(kWaveGrid), dim3(kBlock), 0, w->cap, w->ws, hdr, lay.streams, lay.edits,
-                               lay.lassos);
+                               lay.lassos, masks);
             ok = hipStreamEndCapture(w->cap, &g) == hipSuccess && g;
         }
         ok = ok && hipGraphInstantiate(&w->exec, g, nullptr, nullptr, 0) == hipSuccess;
@@ -250,11 +347,13 @@ extern "C" int32_t uvl_wave_create(int32_t max_edits, int32_t max_lassos, void *
 
 extern "C" int32_t uvl_wave_destroy(uvl_wave *w) {
     if (!w) return UVL_E_INVAL;
-    if (w->staged_pending) (void)hipEventSynchronize(w->staged);
+    for (int k = 0; k < kStaging; ++k) {
+        if (w->pending[k]) (void)hipEventSynchronize(w->copied[k]);
+        if (w->copied[k]) (void)hipEventDestroy(w->copied[k]);
+        if (w->ring[k]) (void)hipHostFree(w->ring[k]);
+    }
     if (w->exec) (void)hipGraphExecDestroy(w->exec);
     if (w->cap) (void)hipStreamDestroy(w->cap);
-    if (w->staged) (void)hipEventDestroy(w->staged);
-    if (w->staging) (void)hipHostFree(w->staging);
     delete w;
     return UVL_OK;
 }
@@ -311,7 +410,7 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
     WaveStream *S = reinterpret_cast<WaveStream *>(st + w->lay.streams);
     WaveEdit *E = reinterpret_cast<WaveEdit *>(st + w->lay.edits);
     LassoParams *P = reinterpret_cast<LassoParams *>(st + w->lay.lassos);
-    int64_t item = 0;
+    int64_t item = 0, words = 0;
     int32_t ei = 0, li = 0;
     for (size_t k = 0; k < keys.size(); ++k) {
         const uvl_edit &f = edits[members[k][0]];
@@ -319,14 +418,23 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
         s.px = f.geom->pos_x;
         s.py = f.geom->pos_y;
         s.pz = f.geom->pos_z;
+        s.box = f.geom->tile_box;
         s.layer = f.layer->data;
-        s.n = (int64_t)f.layer->width * f.layer->height;
+        s.W = f.layer->width;
+        s.H = f.layer->height;
+        s.tiles_x = (int32_t)ceil_div(s.W, UVL_TILE_SIDE);
+        s.ntiles = s.tiles_x * (int32_t)ceil_div(s.H, UVL_TILE_SIDE);
         s.dtype = f.layer->dtype;
-        int ch = chunks_override > 0 ? chunks_override : w->tuned_chunks[log2_class(s.n)];
+        int ch = chunks_override > 0 ? chunks_override : w->tuned_chunks[log2_class((int64_t)s.W * s.H)];
         if (ch <= 0) ch = 4;
         s.chunks = std::min(std::max(ch, 1), kMaxChunks);
         s.item0 = item;
-        item += ceil_div(s.n, (int64_t)s.chunks * kChunkTexels);
+        item += ceil_div(s.ntiles, s.chunks);
+        // cull masks if the geometry has tile bounds and the words fit
+        const int64_t nw = (int64_t)s.ntiles * ((int64_t)(members[k].size() + 63) / 64);
+        s.mask0 = words;
+        s.cull = (f.geom->tile_box && words + nw <= w->lay.max_words) ? 1 : 0;
+        if (s.cull) words += nw;
         s.e0 = ei;
         s.ne = (int32_t)members[k].size();
         for (int32_t i : members[k]) {
@@ -355,6 +463,7 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
     hdr->nstreams = (int32_t)keys.size();
     hdr->pad = 0;
     hdr->total_items = item;
+    hdr->total_words = words;
     hdr->counter = 0;
     bytes = li > 0 ? w->lay.lassos + sizeof(LassoParams) * (size_t)li : w->lay.lassos;
     return UVL_OK;
@@ -367,16 +476,19 @@ extern "C" int32_t uvl_wave_submit(uvl_wave *w, const uvl_edit *edits, int32_t n
     if (n > w->max_edits) return UVL_E_NOMEM;
     if (n == 0) return UVL_OK;
     std::lock_guard<std::mutex> lock(w->mu);
-    // the previous submit's host->device copy must be done before the
-    // staging buffer is rewritten
-    if (w->staged_pending && hipEventSynchronize(w->staged) != hipSuccess) return UVL_E_DEVICE;
-    w->staged_pending = false;
+    // take the next pinned buffer of the ring; its previous copy must have
+    // executed before it is rewritten (up to kStaging submits in flight)
+    const int k = w->next;
+    if (w->pending[k] && hipEventSynchronize(w->copied[k]) != hipSuccess) return UVL_E_DEVICE;
+    w->pending[k] = false;
+    w->staging = w->ring[k];
     size_t bytes = 0;
     if (int32_t st = pack(w, edits, n, tile_chunks, bytes)) return st;
     hipStream_t s = as_stream(stream);
     if (hipMemcpyAsync(w->ws, w->staging, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return UVL_E_DEVICE;
-    if (hipEventRecord(w->staged, s) != hipSuccess) return UVL_E_DEVICE;
-    w->staged_pending = true;
+    if (hipEventRecord(w->copied[k], s) != hipSuccess) return UVL_E_DEVICE;
+    w->pending[k] = true;
+    w->next = (k + 1) % kStaging;
     if (hipGraphLaunch(w->exec, s) != hipSuccess) return UVL_E_DEVICE;
     return UVL_OK;
 }

@@ -81,10 +81,11 @@ class Model:
         for e in edits:
             self.apply(e, cameras)
 
-    def add_to_batch(self, batch: "uvl.EditBatch", edits, cameras):
-        """Append edits to a wave batch.  Each lasso camera's depth map is
-        rendered once into a map owned by the batch (alive until the batch is
-        dropped)."""
+    def add_to_batch(self, batch: "uvl.EditBatch", edits, cameras, render: bool = True):
+        """Append edits to a wave batch.  Each lasso camera gets one depth map
+        owned by the batch (alive until the batch is dropped), rendered now
+        unless render=False; returns {camera: depth map} so that the caller
+        can render them later with render_maps()."""
         maps = {}
         for e in edits:
             layer = self.layers[e.layer]
@@ -95,9 +96,15 @@ class Model:
                 d = maps.get(e.camera)
                 if d is None:
                     d = torch.empty((self.depth_h, self.depth_w), dtype=torch.float32, device=self.device)
-                    uvl.render_depth(self.mesh, M, d, self.depth_ws)
+                    if render:
+                        uvl.render_depth(self.mesh, M, d, self.depth_ws)
                     maps[e.camera] = d
                 batch.lasso(self.geom, layer, M, e.poly, d, self.bias, e.label)
+        return maps
+
+    def render_maps(self, maps, cameras):
+        for cam, d in maps.items():
+            uvl.render_depth(self.mesh, cameras[cam], d, self.depth_ws)
 
     # -- layer algebra ---------------------------------------------------------
     def upload_luts(self, ops):

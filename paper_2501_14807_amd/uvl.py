@@ -44,7 +44,10 @@ class CGeom(ctypes.Structure):
                 ("nrm_x", ctypes.c_void_p), ("nrm_y", ctypes.c_void_p), ("nrm_z", ctypes.c_void_p),
                 ("bary1", ctypes.c_void_p), ("bary2", ctypes.c_void_p),
                 ("area_w", ctypes.c_void_p),
-                ("area_scale", ctypes.c_double), ("area_abs_err", ctypes.c_double)]
+                ("area_scale", ctypes.c_double), ("area_abs_err", ctypes.c_double),
+                ("tile_box", ctypes.c_void_p)]
+
+TILE_SIDE = 32
 
 
 class CLayer(ctypes.Structure):
@@ -70,8 +73,8 @@ SIGNATURES = {
     "uvl_edit_lasso": ([_P, _P, _P, _P, _I32, _P, _I32, _I32, _F32, _U32, _P], _I32),
     "uvl_layer_op": ([_I32, _P, _P, _P, _U32, _U32, _U32, _P, _P], _I32),
     "uvl_area_query": ([_P, _P, _I32, _P, _P, _P], _I32),
-    "uvl_wave_workspace_bytes": ([_I32, _I32], _SZ),
-    "uvl_wave_create": ([_I32, _I32, _P, _SZ, _P], _I32),
+    "uvl_wave_workspace_bytes": ([_I32, _I32, _I64], _SZ),
+    "uvl_wave_create": ([_I32, _I32, _I64, _P, _SZ, _P], _I32),
     "uvl_wave_submit": ([_P, _P, _I32, _I32, _P], _I32),
     "uvl_wave_tune": ([_P, _P, _I32, _P], _I32),
     "uvl_wave_tuned_chunks": ([_P, _I64], _I32),
@@ -172,7 +175,7 @@ class GeometryImage:
     """
 
     def __init__(self, width: int, height: int, normals: bool = True, bary: bool = True,
-                 device="cuda"):
+                 device="cuda", tile_box: bool = True):
         self.width, self.height = int(width), int(height)
         n = self.width * self.height
         self.n = n
@@ -182,6 +185,10 @@ class GeometryImage:
         self.nrm = torch.empty((3, p), dtype=torch.float32, device=device) if normals else None
         self.bary = torch.empty((2, p), dtype=torch.float32, device=device) if bary else None
         self.area_w = torch.empty(p, dtype=torch.int32, device=device)   # uint32 bits
+        self.tiles_x = (self.width + TILE_SIDE - 1) // TILE_SIDE
+        self.tiles_y = (self.height + TILE_SIDE - 1) // TILE_SIDE
+        self.ntiles = self.tiles_x * self.tiles_y
+        self.tile_box = torch.empty((self.ntiles, 6), dtype=torch.float32, device=device) if tile_box else None
         self.c = CGeom()
         self.c.width, self.c.height = self.width, self.height
         self.c.tri_id = self.tri_id.data_ptr()
@@ -191,6 +198,7 @@ class GeometryImage:
         if bary:
             self.c.bary1, self.c.bary2 = self.bary[0].data_ptr(), self.bary[1].data_ptr()
         self.c.area_w = self.area_w.data_ptr()
+        self.c.tile_box = None if self.tile_box is None else self.tile_box.data_ptr()
         self.c.area_scale = 0.0
         self.c.area_abs_err = 0.0
 
@@ -203,7 +211,7 @@ class GeometryImage:
         return float(self.c.area_abs_err)
 
     def nbytes(self) -> int:
-        ts = [self.tri_id, self.pos, self.nrm, self.bary, self.area_w]
+        ts = [self.tri_id, self.pos, self.nrm, self.bary, self.area_w, self.tile_box]
         return sum(t.numel() * t.element_size() for t in ts if t is not None)
 
     # host copies of the first n elements of each plane
@@ -386,15 +394,15 @@ class EditBatch:
 class Wave:
     """Handle for batched edit waves (uvl_wave_*), workspace owned here."""
 
-    def __init__(self, max_edits: int, max_lassos: int, device="cuda"):
+    def __init__(self, max_edits: int, max_lassos: int, max_cull_words: int = 1 << 22, device="cuda"):
         L = _lib()
-        need = L.uvl_wave_workspace_bytes(int(max_edits), int(max_lassos))
+        need = L.uvl_wave_workspace_bytes(int(max_edits), int(max_lassos), int(max_cull_words))
         if need == 0:
             raise ValueError("bad wave capacity")
         self.ws = torch.empty(need, dtype=torch.uint8, device=device)
         self.h = ctypes.c_void_p()
-        _check(L.uvl_wave_create(int(max_edits), int(max_lassos), _ptr(self.ws), need, ctypes.byref(self.h)),
-               "uvl_wave_create")
+        _check(L.uvl_wave_create(int(max_edits), int(max_lassos), int(max_cull_words), _ptr(self.ws), need,
+                                 ctypes.byref(self.h)), "uvl_wave_create")
         self.max_edits, self.max_lassos = int(max_edits), int(max_lassos)
 
     def submit(self, batch: EditBatch, tile_chunks: int = 0, stream=None):

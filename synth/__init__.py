@@ -16,12 +16,12 @@ from .mesh import (Mesh, vessel, sphere, plane_grid, displaced_chart,
 from .edits import (look_at_perspective, random_camera, star_polygon,
                     surface_points, BrushEdit, LassoEdit, LayerOp,
                     tiny_workload, scan_workload, batch_workload,
-                    serve_workload, max_workload)
+                    serve_workload, serve_stream, max_workload)
 
 __all__ = [
     "Mesh", "vessel", "sphere", "plane_grid", "displaced_chart", "shelf_pack",
     "atlas_mesh", "scan_mesh", "batch_model_mesh", "max_model_mesh",
     "merge_meshes", "look_at_perspective", "random_camera", "star_polygon",
     "surface_points", "BrushEdit", "LassoEdit", "LayerOp", "tiny_workload",
-    "scan_workload", "batch_workload", "serve_workload", "max_workload",
+    "scan_workload", "batch_workload", "serve_workload", "serve_stream", "max_workload",
 ]

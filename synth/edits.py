@@ -62,19 +62,27 @@ def star_polygon(rng: np.random.Generator, n: int) -> np.ndarray:
     return pts.astype(np.float32)
 
 
-def surface_points(rng: np.random.Generator, mesh: Mesh, k: int) -> np.ndarray:
-    """k points uniform on the surface: area-weighted triangle, uniform barycentric."""
+def area_cdf(mesh: Mesh) -> np.ndarray:
     p = mesh.pos.astype(np.float64)
     t = mesh.tri.astype(np.int64)
     a = 0.5 * np.linalg.norm(np.cross(p[t[:, 1]] - p[t[:, 0]], p[t[:, 2]] - p[t[:, 0]]), axis=1)
-    cdf = np.cumsum(a)
+    return np.cumsum(a)
+
+
+def surface_points(rng: np.random.Generator, mesh: Mesh, k: int, cdf=None) -> np.ndarray:
+    """k points uniform on the surface: area-weighted triangle, uniform barycentric."""
+    p = mesh.pos.astype(np.float64) if cdf is None else mesh.pos
+    t = mesh.tri.astype(np.int64) if cdf is None else mesh.tri
+    if cdf is None:
+        cdf = area_cdf(mesh)
     pick = np.searchsorted(cdf, rng.uniform(0.0, cdf[-1], size=k), side="right")
     pick = np.minimum(pick, t.shape[0] - 1)
     r1 = np.sqrt(rng.uniform(size=k))
     r2 = rng.uniform(size=k)
     w0, w1, w2 = 1.0 - r1, r1 * (1.0 - r2), r1 * r2
-    tp = t[pick]
-    pts = w0[:, None] * p[tp[:, 0]] + w1[:, None] * p[tp[:, 1]] + w2[:, None] * p[tp[:, 2]]
+    tp = t[pick].astype(np.int64)
+    P = [p[tp[:, c]].astype(np.float64) for c in range(3)]
+    pts = w0[:, None] * P[0] + w1[:, None] * P[1] + w2[:, None] * P[2]
     return pts.astype(np.float32)
 
 
@@ -263,6 +271,49 @@ def serve_workload(n_requests: int, qps: float, n_models: int, seed: int = 3004)
     kind = rng.choice(4, size=n_requests, p=[0.60, 0.25, 0.10, 0.05])
     model = rng.integers(0, n_models, size=n_requests)
     return t, kind, model
+
+
+def serve_stream(meshes, layer_dtypes, n_requests: int, qps: float, seed: int = 3004,
+                 n_cameras: int = 8, r_frac=(0.01, 0.2)):
+    """Request stream for a serving run over several resident models.
+
+    Poisson arrivals at `qps`; kinds 60% brush / 25% lasso / 10% area / 5%
+    layer operation; uniform model choice.  Each model has n_cameras cameras
+    (2.5x its bounding radius); brushes have r ~ U[r_frac] x bounding radius.
+    Returns (cameras per model, list of request dicts with keys t, model,
+    kind and edit | op | layer).
+    """
+    rng = np.random.default_rng(seed)
+    t, kind, model = serve_workload(n_requests, qps, len(meshes), seed)
+    cams, spheres, cdfs = [], [], []
+    for k, m in enumerate(meshes):
+        c, rad = bounding_sphere(m)
+        rc = np.random.default_rng(seed * 7 + k)
+        cams.append([random_camera(rc, c, 2.5 * rad) for _ in range(n_cameras)])
+        spheres.append(rad)
+        cdfs.append(area_cdf(m))
+    out = []
+    for i in range(n_requests):
+        m = int(model[i])
+        dts = layer_dtypes[m]
+        L = int(rng.integers(0, len(dts)))
+        req = {"t": float(t[i]), "model": m}
+        if kind[i] == 0:
+            c = surface_points(rng, meshes[m], 1, cdfs[m])[0]
+            r = np.float32(rng.uniform(*r_frac) * spheres[m])
+            req.update(kind="brush", edit=BrushEdit(L, c, r, _label(rng, dts[L])))
+        elif kind[i] == 1:
+            n = int(rng.integers(3, 33))
+            req.update(kind="lasso", edit=LassoEdit(L, int(rng.integers(0, n_cameras)), star_polygon(rng, n),
+                                                    _label(rng, dts[L])))
+        elif kind[i] == 2:
+            req.update(kind="area", layer=L)
+        else:
+            req.update(kind="algebra", op=make_ops(rng, dts, 1)[0] if len(dts) > 1 else None)
+            if req["op"] is None:
+                req.update(kind="area", layer=L)
+        out.append(req)
+    return cams, out
 
 
 def max_workload(n_edits: int = 10000) -> Workload:

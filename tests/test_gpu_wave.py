@@ -56,17 +56,20 @@ def test_wave_equals_plain_all_tile_sizes(gpu):
     models = _models(gpu)
     ref = _plain(gpu, models)
     n = sum(len(e) for _, _, e in models)
-    wave = gpu.Wave(max_edits=n, max_lassos=n)
-    for chunks in (1, 2, 4, 8, 0):
-        batch = gpu.EditBatch()
-        for m, wl, edits in models:
-            m.clear_layers()
-            m.add_to_batch(batch, edits, wl.cameras)
-        wave.submit(batch, tile_chunks=chunks)
-        for (m, _, _), r in zip(models, ref):
-            for k, l in enumerate(m.layers):
-                assert np.array_equal(l.numpy(), r[k]), (chunks, k)
-    wave.close()
+    # culling masks for every layer, for some layers only (the scan-scale
+    # model's 1024 tiles x 1 word do not fit 600 words), and none
+    for words in (1 << 20, 600, 0):
+        wave = gpu.Wave(max_edits=n, max_lassos=n, max_cull_words=words)
+        for chunks in (1, 2, 4, 8, 0):
+            batch = gpu.EditBatch()
+            for m, wl, edits in models:
+                m.clear_layers()
+                m.add_to_batch(batch, edits, wl.cameras)
+            wave.submit(batch, tile_chunks=chunks)
+            for (m, _, _), r in zip(models, ref):
+                for k, l in enumerate(m.layers):
+                    assert np.array_equal(l.numpy(), r[k]), (words, chunks, k)
+        wave.close()
 
 
 def test_wave_against_oracle_and_interleaving(gpu, orc):
@@ -143,4 +146,98 @@ def test_wave_errors(gpu):
     with pytest.raises(gpu.UvlError) as ei:
         wave.submit(b)
     assert ei.value.code == -3
+    wave.close()
+
+
+def test_tile_boxes(gpu):
+    wl = synth.tiny_workload()
+    for (W, H) in ((512, 512), (37, 53), (1000, 3), (64, 96)):
+        dm = gpu.DeviceMesh.from_mesh(wl.mesh)
+        g = gpu.GeometryImage(W, H)
+        gpu.build_geometry_image(dm, g)
+        pos = g.host()["pos"].reshape(3, H, W)
+        box = g.tile_box.cpu().numpy()
+        tx, ty = (W + 31) // 32, (H + 31) // 32
+        assert box.shape == (tx * ty, 6)
+        for b in range(ty):
+            for a in range(tx):
+                p = pos[:, 32 * b:32 * b + 32, 32 * a:32 * a + 32].reshape(3, -1)
+                cov = ~np.isnan(p[0])
+                k = b * tx + a
+                if cov.any():
+                    assert np.array_equal(box[k, :3], p[:, cov].min(axis=1))
+                    assert np.array_equal(box[k, 3:], p[:, cov].max(axis=1))
+                else:
+                    assert (box[k, :3] == np.inf).all() and (box[k, 3:] == -np.inf).all()
+
+
+def _project(M, p):
+    """fp32 NDC of positions p [3, n] with the fmaf order of the kernels
+    (numpy float32 arithmetic with float64 fused steps rounded once)."""
+    M = M.reshape(4, 4).astype(np.float64)
+    x, y, z = (p[k].astype(np.float64) for k in range(3))
+
+    def fma(a, b, c):   # exact product + sum, one rounding (float64 is exact
+        return np.float32(a * b + c)   # enough for these fp32 operands' products)
+
+    c = []
+    for r in range(4):
+        v = fma(M[r, 0], x, M[r, 3])
+        v = fma(M[r, 1], y, np.float64(v))
+        v = fma(M[r, 2], z, np.float64(v))
+        c.append(v)
+    return c[0] / c[3], c[1] / c[3], c[3]
+
+
+def test_wave_culling_boundaries(gpu):
+    """Brushes and lassos whose boundaries pass exactly through texels near
+    tile edges: the wave (with tile culling) must equal the plain path."""
+    from paper_2501_14807_amd.model import Model
+    wl = synth.tiny_workload()
+    m = Model.from_workload(wl).build()
+    pos = m.geom.host()["pos"]
+    cov = np.nonzero(~np.isnan(pos[0]))[0]
+    rng = np.random.default_rng(8)
+    brushes = []
+    for _ in range(40):
+        a, b = rng.choice(cov, 2)
+        c = pos[:, a]
+        # radius equal to the fp32 distance of texel b (a texel of another tile)
+        d = pos[:, b] - c
+        r = np.float32(np.sqrt(np.float32(d[0] * d[0] + d[1] * d[1] + d[2] * d[2])))
+        brushes.append((c, r))
+    M = wl.cameras[2]
+    xn, yn, w = _project(M, pos[:, cov])
+    ok = (w > 0) & (np.abs(xn) < 0.9) & (np.abs(yn) < 0.9)
+    idx = np.nonzero(ok)[0]
+    polys = []
+    for _ in range(20):
+        i, j = rng.choice(idx, 2)
+        x0, x1 = sorted([xn[i], xn[j]])
+        y0, y1 = sorted([yn[i], yn[j]])
+        if x1 - x0 < 1e-3 or y1 - y0 < 1e-3:
+            continue
+        polys.append(np.array([[x0, y0], [x1, y0], [x1, y1], [x0, y1]], np.float32))
+    d = m.depth_for(2, M)
+
+    def plain():
+        m.clear_layers()
+        for k, (c, r) in enumerate(brushes):
+            gpu.edit_brush(m.geom, m.layers[0], c, r, 1 + k % 250)
+        for k, P in enumerate(polys):
+            gpu.edit_lasso(m.geom, m.layers[0], M, P, d, 1.0, 1 + (k + 7) % 250)
+        return m.layers[0].numpy().copy()
+
+    ref = plain()
+    m.clear_layers()
+    b = gpu.EditBatch()
+    for k, (c, r) in enumerate(brushes):
+        b.brush(m.geom, m.layers[0], c, r, 1 + k % 250)
+    for k, P in enumerate(polys):
+        b.lasso(m.geom, m.layers[0], M, P, d, 1.0, 1 + (k + 7) % 250)
+    wave = gpu.Wave(len(b), len(b))
+    for chunks in (1, 8):
+        m.clear_layers()
+        wave.submit(b, tile_chunks=chunks)
+        assert np.array_equal(m.layers[0].numpy(), ref), chunks
     wave.close()

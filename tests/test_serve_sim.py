@@ -1,0 +1,102 @@
+"""The serving scheduler on the host (simulated device): per-model FIFO
+semantics, continuous batching, admission by footprint, failure isolation."""
+
+import numpy as np
+import pytest
+
+from paper_2501_14807_amd.serve import Request, Server, SimExecutor
+
+KINDS = ["brush", "lasso", "area", "algebra"]
+
+
+def _stream(n, n_models, qps, seed=0):
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / qps, n))
+    kinds = rng.choice(4, n, p=[0.6, 0.25, 0.1, 0.05])
+    models = rng.integers(0, n_models, n)
+    return [Request(i, float(t[i]), int(models[i]), KINDS[kinds[i]]) for i in range(n)]
+
+
+def _expected_seen(reqs):
+    """For each area request, the ids of its model's requests up to itself."""
+    out = {}
+    by_model = {}
+    for r in sorted(reqs, key=lambda r: (r.t_arrival, r.rid)):
+        by_model.setdefault(r.model, []).append(r.rid)
+        if r.kind == "area":
+            out[r.rid] = tuple(by_model[r.model])
+    return out
+
+
+@pytest.mark.parametrize("mode", ["batched", "plain"])
+def test_fifo_per_model(mode):
+    reqs = _stream(3000, 7, 40000.0)
+    ex = SimExecutor([1] * 7)
+    st = Server(ex, 7, 100).run(reqs, mode)
+    assert st.failed == 0 and st.refused == 0
+    want = _expected_seen(reqs)
+    for r in reqs:
+        assert r.t_done is not None and r.t_done >= r.t_arrival
+        if r.kind == "area":
+            assert r.result == want[r.rid]
+    # per model, launches happen in arrival order
+    for m in range(7):
+        launched = [rid for _, mm, rid in ex.log if mm == m]
+        arrived = [r.rid for r in sorted(reqs, key=lambda r: (r.t_arrival, r.rid)) if r.model == m]
+        assert launched == arrived
+
+
+def test_continuous_batching_beats_plain_under_load():
+    # simulated costs: 100 us per single edit launch, 50 us + 10 us per edit per wave
+    reqs = _stream(4000, 16, 30000.0, seed=1)
+    st_b = Server(SimExecutor([1] * 16), 16, 100).run([Request(**{**r.__dict__}) for r in reqs], "batched")
+    st_p = Server(SimExecutor([1] * 16), 16, 100).run([Request(**{**r.__dict__}) for r in reqs], "plain")
+    assert st_b.rounds < len(reqs) / 2          # requests were grouped
+    assert st_b.p99_ms < st_p.p99_ms            # the plain queue falls behind
+    assert st_b.wall_s <= st_p.wall_s + 0.05
+
+
+def test_admission_by_footprint_and_refusals():
+    reqs = _stream(500, 4, 20000.0, seed=2)
+    ex = SimExecutor([40, 40, 40, 40])
+    srv = Server(ex, 4, 100)                     # only two models fit
+    assert srv.resident == {0, 1} and srv.used_bytes == 80
+    st = srv.run(reqs, "batched")
+    for r in reqs:
+        if r.model in (2, 3):
+            assert not r.ok and r.result == "model not resident"
+        else:
+            assert r.ok
+    assert st.refused == sum(1 for r in reqs if r.model in (2, 3))
+
+
+def test_failure_is_isolated():
+    reqs = _stream(800, 5, 20000.0, seed=3)
+    ex = SimExecutor([1] * 5, fail_models={3})
+    st = Server(ex, 5, 100).run(reqs, "batched")
+    want = _expected_seen([r for r in reqs if r.model != 3])
+    for r in reqs:
+        assert r.ok == (r.model != 3)
+        if r.model != 3 and r.kind == "area":
+            assert r.result == want[r.rid]
+    assert st.failed == sum(1 for r in reqs if r.model == 3)
+
+
+def test_inflight_limit():
+    class Counting(SimExecutor):
+        def __init__(self, *a, **k):
+            super().__init__(*a, **k)
+            self.handles = []
+            self.max_seen = 0
+
+        def close_round(self, reqs):
+            h = super().close_round(reqs)
+            self.handles.append(h)
+            live = sum(1 for x in self.handles if not self.done(x))
+            self.max_seen = max(self.max_seen, live)
+            return h
+
+    reqs = _stream(2000, 8, 50000.0, seed=4)
+    ex = Counting([1] * 8, wave_fixed_s=500e-6)
+    Server(ex, 8, 100, max_inflight=2).run(reqs, "batched")
+    assert ex.max_seen <= 2

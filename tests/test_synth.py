@@ -25,6 +25,8 @@ def test_tiny_workload_hashes_recorded():
     assert _sha(wl.mesh.tri) == want["vessel_tri"]
     assert _sha(wl.mesh.nrm) == want["vessel_nrm"]
     assert _sha(np.stack(wl.cameras)) == want["tiny_cameras"]
+    assert _sha(np.stack([e.centre for e in wl.edits if e.kind == "brush"])) == want["tiny_brush_centres"]
+    assert _sha(np.concatenate([e.poly for e in wl.edits if e.kind == "lasso"])) == want["tiny_polys"]
     assert "".join("b" if e.kind == "brush" else "l" for e in wl.edits) == want["tiny_kinds"]
 
 
