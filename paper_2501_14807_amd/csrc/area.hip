@@ -68,6 +68,7 @@ struct AreaArgs {
     const void *data[kGroup];
     unsigned long long *bins[kGroup];
     int32_t dtype[kGroup];
+    int32_t row[kGroup];      // u8 layers: their LDS bin row (rank among the group's u8 layers)
     int32_t nl;
 };
 
@@ -114,16 +115,22 @@ __device__ __forceinline__ void feed(const uint32_t lab[kPer], const uint32_t w[
     }
 }
 
+// kU8 / kU16: the launch's group has u8 / u16 layers; LDS holds only the
+// tables the group needs (u8 bins 2 KiB per layer, the u16 hash 24 KiB), so a
+// one-layer query keeps many workgroups per CU.
+template <int kNU8, bool kU16>
 __global__ __launch_bounds__(kBlock) void k_area(const uint32_t *__restrict__ area_w, int W, int H, int rows_per,
                                                   AreaArgs A) {
-    __shared__ unsigned long long s_bins[kGroup][256];
-    __shared__ uint32_t s_key[kHash];
-    __shared__ unsigned long long s_val[kHash];
-    for (int k = threadIdx.x; k < kGroup * 256; k += kBlock) (&s_bins[0][0])[k] = 0ull;
-    for (int k = threadIdx.x; k < kHash; k += kBlock) {
-        s_key[k] = kEmptyKey;
-        s_val[k] = 0ull;
-    }
+    __shared__ unsigned long long s_bins[kNU8 > 0 ? kNU8 : 1][256];
+    __shared__ uint32_t s_key[kU16 ? kHash : 1];
+    __shared__ unsigned long long s_val[kU16 ? kHash : 1];
+    if (kNU8 > 0)
+        for (int k = threadIdx.x; k < kNU8 * 256; k += kBlock) (&s_bins[0][0])[k] = 0ull;
+    if (kU16)
+        for (int k = threadIdx.x; k < kHash; k += kBlock) {
+            s_key[k] = kEmptyKey;
+            s_val[k] = 0ull;
+        }
     __syncthreads();
     const U16Table table{s_key, s_val, A.bins};
     uint32_t cur[kGroup];
@@ -158,7 +165,7 @@ __global__ __launch_bounds__(kBlock) void k_area(const uint32_t *__restrict__ ar
         for (int l = 0; l < kGroup; ++l) {
             if (l >= A.nl) break;
             uint32_t lab[kPer];
-            if (A.dtype[l] == UVL_U8) {
+            if (kNU8 > 0 && (!kU16 || A.dtype[l] == UVL_U8)) {
                 const uint8_t *L = static_cast<const uint8_t *>(A.data[l]);
                 if (vec) {
                     label16_u8(L + t0, lab);
@@ -166,8 +173,8 @@ __global__ __launch_bounds__(kBlock) void k_area(const uint32_t *__restrict__ ar
 #pragma unroll
                     for (int k = 0; k < kPer; ++k) lab[k] = k < ncol ? L[t0 + k] : cur[l];
                 }
-                feed(lab, w, tot, cur[l], run[l], SinkU8{&s_bins[l][0]});
-            } else {
+                feed(lab, w, tot, cur[l], run[l], SinkU8{&s_bins[A.row[l]][0]});
+            } else if (kU16) {
                 const uint16_t *L = static_cast<const uint16_t *>(A.data[l]);
                 if (vec) {
                     label16_u16(L + t0, lab);
@@ -183,20 +190,33 @@ __global__ __launch_bounds__(kBlock) void k_area(const uint32_t *__restrict__ ar
     for (int l = 0; l < kGroup; ++l) {
         if (l >= A.nl) break;
         if (run[l]) {
-            if (A.dtype[l] == UVL_U8) atomicAdd(&s_bins[l][cur[l]], run[l]);
-            else table_add(table, l, cur[l], run[l]);
+            if (kNU8 > 0 && (!kU16 || A.dtype[l] == UVL_U8)) atomicAdd(&s_bins[A.row[l]][cur[l]], run[l]);
+            else if (kU16) table_add(table, l, cur[l], run[l]);
         }
     }
     __syncthreads();
-    for (int l = 0; l < A.nl; ++l) {
-        if (A.dtype[l] != UVL_U8) continue;
-        const unsigned long long v = s_bins[l][threadIdx.x];
-        if (v) atomicAdd(A.bins[l] + threadIdx.x, v);
-    }
-    for (int k = threadIdx.x; k < kHash; k += kBlock) {
-        const uint32_t key = s_key[k];
-        if (key != kEmptyKey && s_val[k]) atomicAdd(A.bins[key >> 16] + (key & 0xffffu), s_val[k]);
-    }
+    if (kNU8 > 0)
+        for (int l = 0; l < A.nl; ++l) {
+            if (A.dtype[l] != UVL_U8) continue;
+            const unsigned long long v = s_bins[A.row[l]][threadIdx.x];
+            if (v) atomicAdd(A.bins[l] + threadIdx.x, v);
+        }
+    if (kU16)
+        for (int k = threadIdx.x; k < kHash; k += kBlock) {
+            const uint32_t key = s_key[k];
+            if (key != kEmptyKey && s_val[k]) atomicAdd(A.bins[key >> 16] + (key & 0xffffu), s_val[k]);
+        }
+}
+
+// Launch one group with the kernel instance sized to its u8 layer count and
+// whether it has u16 layers.
+template <int kNU8>
+void launch_area(dim3 grid, hipStream_t s, const uint32_t *area_w, int W, int H, int rows_per, const AreaArgs &A,
+                 bool u16) {
+    if (u16)
+        hipLaunchKernelGGL((k_area<kNU8, true>), grid, dim3(kBlock), 0, s, area_w, W, H, rows_per, A);
+    else
+        hipLaunchKernelGGL((k_area<kNU8, false>), grid, dim3(kBlock), 0, s, area_w, W, H, rows_per, A);
 }
 
 }  // namespace
@@ -228,15 +248,28 @@ extern "C" int32_t uvl_area_query(const uvl_geom *geom, const uvl_layer *layers,
     for (int l0 = 0; l0 < nlayers; l0 += kGroup) {
         AreaArgs A{};
         A.nl = nlayers - l0 < kGroup ? nlayers - l0 : kGroup;
+        int nu8 = 0;
+        bool u16 = false;
         for (int k = 0; k < A.nl; ++k) {
             const uvl_layer &L = layers[l0 + k];
             A.data[k] = L.data;
             A.dtype[k] = L.dtype;
             A.bins[k] = reinterpret_cast<unsigned long long *>(bins_dev) + off;
             off += L.dtype == UVL_U8 ? 256 : 65536;
+            if (L.dtype == UVL_U8) A.row[k] = nu8++;
+            else u16 = true;
         }
-        hipLaunchKernelGGL(k_area, dim3((unsigned)bands, (unsigned)groups), dim3(kBlock), 0, s, geom->area_w,
-                           geom->width, geom->height, rows_per, A);
+        const dim3 grid((unsigned)bands, (unsigned)groups);
+        const uint32_t *aw = geom->area_w;
+        const int W = geom->width, H = geom->height;
+        switch (nu8) {
+            case 0: launch_area<0>(grid, s, aw, W, H, rows_per, A, u16); break;
+            case 1: launch_area<1>(grid, s, aw, W, H, rows_per, A, u16); break;
+            case 2: launch_area<2>(grid, s, aw, W, H, rows_per, A, u16); break;
+            case 3:
+            case 4: launch_area<4>(grid, s, aw, W, H, rows_per, A, u16); break;
+            default: launch_area<kGroup>(grid, s, aw, W, H, rows_per, A, u16); break;
+        }
     }
     if (launch_status() != UVL_OK) return UVL_E_DEVICE;
     if (!areas_host) return UVL_OK;

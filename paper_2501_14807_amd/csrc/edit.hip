@@ -5,11 +5,12 @@
 // streaming pass over the geometry image's position planes: 12 bytes read per
 // texel, one label store per selected texel, no read of the layer.
 //
-// Tiling: a 256-thread workgroup owns 4096 consecutive texels as 4 chunks of
-// 1024; lane l of chunk c reads texels [c*1024 + 4l, c*1024 + 4l + 4) of each
-// plane as one 16-byte non-temporal load, so a wave's loads are 1 KiB
-// contiguous per plane.  All 12 loads of a thread are issued before any
-// predicate.
+// Each lane handles 4 consecutive texels of a row and reads them from each
+// plane with one 16-byte non-temporal load; all 12 loads of a thread are
+// issued before any predicate.  The brush walks the atlas as a flat array
+// (a 256-thread workgroup owns 4096 consecutive texels as 4 chunks of 1024, a
+// wave's loads are 1 KiB contiguous per plane); the lasso, which also reads
+// the depth map, walks it in 2D blocks (see k_lasso).
 #include <math.h>
 
 #include "edit_texel.h"
@@ -52,30 +53,26 @@ __device__ __forceinline__ void store4<uint16_t>(uint16_t *__restrict__ L, int64
 }
 
 template <typename T>
-__device__ __forceinline__ void edit_tail(const float *__restrict__ px, const float *__restrict__ py,
-                                          const float *__restrict__ pz, T *__restrict__ L, int64_t n,
-                                          const BrushParams *B, const LassoParams *P,
-                                          const float *__restrict__ depth, T label) {
+__device__ __forceinline__ void brush_tail(const float *__restrict__ px, const float *__restrict__ py,
+                                           const float *__restrict__ pz, T *__restrict__ L, int64_t n,
+                                           const BrushParams &B, T label) {
     const int64_t base = (int64_t)blockIdx.x * kTile + threadIdx.x * 4;
     for (int c = 0; c < 4; ++c)
         for (int k = 0; k < 4; ++k) {
             const int64_t t = base + c * kChunk + k;
-            if (t >= n) continue;
-            const bool s = B ? brush_texel(*B, px[t], py[t], pz[t]) : lasso_texel(*P, depth, px[t], py[t], pz[t]);
-            if (s) L[t] = label;
+            if (t < n && brush_texel(B, px[t], py[t], pz[t])) L[t] = label;
         }
 }
 
-// One workgroup tile of 4096 texels; the full-tile test is uniform over the
-// workgroup, so whole waves take the same path (the lasso's wave-wide
-// polygon test needs every lane).
+// Brush: one workgroup tile of 4096 consecutive texels; the last, partial
+// tile takes the per-texel path.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_brush(const float *__restrict__ px, const float *__restrict__ py,
                                                   const float *__restrict__ pz, T *__restrict__ L, int64_t n,
                                                   BrushParams p, uint32_t label) {
     const int64_t base = (int64_t)blockIdx.x * kTile + threadIdx.x * 4;
     if ((int64_t)(blockIdx.x + 1) * kTile > n) {
-        edit_tail<T>(px, py, pz, L, n, &p, nullptr, nullptr, (T)label);
+        brush_tail<T>(px, py, pz, L, n, p, (T)label);
         return;
     }
     float4 X[4], Y[4], Z[4];
@@ -95,28 +92,72 @@ __global__ __launch_bounds__(kBlock) void k_brush(const float *__restrict__ px, 
     }
 }
 
+// Lasso tiling: a workgroup owns a block of kLassoRows x kLassoCols texels;
+// wave w covers its columns [32w, 32w + 32), in step c the rows
+// [8c, 8c + 8), lane l the 4 texels at row l/8, columns 4(l%8)..+3.  One
+// step of a wave is thus an 8 x 32 patch of the atlas, whose image on the
+// screen is compact, so the depth reads of one instruction touch few cache
+// lines (the image of a 256-texel row segment is a long screen-space curve).
+// Texels beyond the atlas read as NaN positions, which no lasso selects, so
+// edge blocks take the same wave-wide path with bounds-checked loads and
+// stores; atlases whose width is not a multiple of 4 use those loads
+// everywhere (rows are then not 16-byte aligned).
+constexpr int kLassoRows = 32, kLassoCols = 128;
+
+template <typename T>
+__device__ __forceinline__ void store_masked(T *__restrict__ L, int64_t t, int nvalid, const bool s[4], T label) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (k < nvalid && s[k]) L[t + k] = label;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_lasso(const float *__restrict__ px, const float *__restrict__ py,
-                                                  const float *__restrict__ pz, T *__restrict__ L, int64_t n,
-                                                  LassoParams p, const float *__restrict__ depth,
+                                                  const float *__restrict__ pz, T *__restrict__ L, int32_t W,
+                                                  int32_t H, LassoParams p, const float *__restrict__ depth,
                                                   uint32_t label) {
-    const int64_t base = (int64_t)blockIdx.x * kTile + threadIdx.x * 4;
-    if ((int64_t)(blockIdx.x + 1) * kTile > n) {
-        edit_tail<T>(px, py, pz, L, n, nullptr, &p, depth, (T)label);
-        return;
-    }
+    const int lane = threadIdx.x & 63;
+    const int x = blockIdx.x * kLassoCols + (threadIdx.x >> 6) * 32 + (lane & 7) * 4;
+    const int y0 = blockIdx.y * kLassoRows + (lane >> 3);
+    // lane-uniform over full blocks of a width that keeps rows 16-byte aligned
+    const bool vec = (W & 3) == 0 && (blockIdx.x + 1) * kLassoCols <= W && (blockIdx.y + 1) * kLassoRows <= H;
     float4 X[4], Y[4], Z[4];
+    if (vec) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        X[c] = load_stream4(px + base + c * kChunk);
-        Y[c] = load_stream4(py + base + c * kChunk);
-        Z[c] = load_stream4(pz + base + c * kChunk);
+        for (int c = 0; c < 4; ++c) {
+            const int64_t t = (int64_t)(y0 + 8 * c) * W + x;
+            X[c] = load_stream4(px + t);
+            Y[c] = load_stream4(py + t);
+            Z[c] = load_stream4(pz + t);
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int y = y0 + 8 * c;
+            const int64_t t = (int64_t)y * W + x;
+            float v[3][4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const bool in = y < H && x + k < W;
+                v[0][k] = in ? px[t + k] : NAN;
+                v[1][k] = in ? py[t + k] : NAN;
+                v[2][k] = in ? pz[t + k] : NAN;
+            }
+            X[c] = make_float4(v[0][0], v[0][1], v[0][2], v[0][3]);
+            Y[c] = make_float4(v[1][0], v[1][1], v[1][2], v[1][3]);
+            Z[c] = make_float4(v[2][0], v[2][1], v[2][2], v[2][3]);
+        }
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         bool s[4];
         lasso_quad(p, depth, X[c], Y[c], Z[c], s);
-        store4<T>(L, base + c * kChunk, s[0], s[1], s[2], s[3], (T)label);
+        const int y = y0 + 8 * c;
+        const int64_t t = (int64_t)y * W + x;
+        if (vec)
+            store4<T>(L, t, s[0], s[1], s[2], s[3], (T)label);
+        else if (y < H)
+            store_masked<T>(L, t, W - x, s, (T)label);
     }
 }
 
@@ -243,14 +284,14 @@ extern "C" int32_t uvl_edit_lasso(const uvl_geom *geom, const uvl_layer *layer, 
     for (int k = 0; k < 16; ++k)
         if (!std::isfinite(view_proj[k])) return UVL_E_INVAL;
     if (int32_t s = check_edit(geom, layer, label)) return s;
-    const int64_t N = (int64_t)geom->width * geom->height;
-    const dim3 grid((unsigned)ceil_div(N, kTile));
+    const int32_t W = geom->width, H = geom->height;
+    const dim3 grid((unsigned)ceil_div(W, kLassoCols), (unsigned)ceil_div(H, kLassoRows));
     hipStream_t s = as_stream(stream);
     if (layer->dtype == UVL_U8)
         hipLaunchKernelGGL(k_lasso<uint8_t>, grid, dim3(kBlock), 0, s, geom->pos_x, geom->pos_y, geom->pos_z,
-                           static_cast<uint8_t *>(layer->data), N, p, depth, label);
+                           static_cast<uint8_t *>(layer->data), W, H, p, depth, label);
     else
         hipLaunchKernelGGL(k_lasso<uint16_t>, grid, dim3(kBlock), 0, s, geom->pos_x, geom->pos_y, geom->pos_z,
-                           static_cast<uint16_t *>(layer->data), N, p, depth, label);
+                           static_cast<uint16_t *>(layer->data), W, H, p, depth, label);
     return launch_status();
 }

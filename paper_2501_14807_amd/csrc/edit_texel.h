@@ -77,17 +77,22 @@ struct LassoParams {
     LassoCull cull;
 };
 
-// Everything but the polygon test: true if the texel is a candidate, with
-// its NDC position.
+// The projective part of the test (§4.3.1: points projecting outside the
+// unit cube are discarded): clip coordinates c = M [x y z 1]^T, and true if
+// the texel is in front of the camera with its NDC x, y in the frustum and in
+// the polygon's bounding range.  The NDC z / depth part follows in
+// lasso_depth, so that it is evaluated only for texels inside the polygon.
 // PT is LassoParams, possibly qualified with the constant address space so
 // that a parameter block in global memory is read with scalar loads.
 template <class PT>
-__device__ __forceinline__ bool lasso_front(const PT &P, const float *__restrict__ depth, float x, float y,
-                                            float z, float &xn, float &yn) {
+__device__ __forceinline__ bool lasso_front(const PT &P, float x, float y, float z, float &xn, float &yn,
+                                            float &cz, float &cw) {
     float c[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
         c[k] = __builtin_fmaf(P.M[4 * k + 2], z, __builtin_fmaf(P.M[4 * k + 1], y, __builtin_fmaf(P.M[4 * k + 0], x, P.M[4 * k + 3])));
+    cz = c[2];
+    cw = c[3];
     if (!(c[3] > 0.0f)) return false;
     if (c[3] >= 1e-30f) {
         // Pre-test with the hardware reciprocal: x/w and y/w are within 3e-7
@@ -103,8 +108,14 @@ __device__ __forceinline__ bool lasso_front(const PT &P, const float *__restrict
     // Outside [ylo, yhi) no edge straddles yn; right of xhi every straddling
     // edge fails the crossing test even after rounding (monotone rounding of
     // the differences and products): both give "outside" exactly.
-    if (!(yn >= P.ylo && yn < P.yhi && xn <= P.xhi)) return false;
-    const float zn = c[2] / c[3];
+    return yn >= P.ylo && yn < P.yhi && xn <= P.xhi;
+}
+
+// NDC z in [-1, 1] and the depth test of a texel that passed lasso_front.
+template <class PT>
+__device__ __forceinline__ bool lasso_depth(const PT &P, const float *__restrict__ depth, float xn, float yn,
+                                            float cz, float cw) {
+    const float zn = cz / cw;
     if (!(zn >= -1.0f && zn <= 1.0f)) return false;
     int ix = (int)floorf(__builtin_fmaf(xn, 0.5f, 0.5f) * (float)P.dw);
     int iy = (int)floorf(__builtin_fmaf(yn, 0.5f, 0.5f) * (float)P.dh);
@@ -128,22 +139,6 @@ __device__ __forceinline__ void lasso_edge(float ex0, float ey0, float ey1, floa
     const float lhs = (xn - ex0) * esdy;
     const float rhs = esdx * (yn - ey0);
     inside ^= straddle && (lhs < rhs);
-}
-
-// The whole predicate for one texel (edges of its own slab).
-template <class PT>
-__device__ __forceinline__ bool lasso_texel(const PT &P, const float *__restrict__ depth, float x, float y,
-                                            float z) {
-    float xn, yn;
-    if (!lasso_front(P, depth, x, y, z, xn, yn)) return false;
-    uint64_t m = P.slab_edges[lasso_slab(P, yn)];
-    bool inside = false;
-    while (m) {
-        const int e = __builtin_ctzll(m);
-        m &= m - 1;
-        lasso_edge(P.edge[e].x0, P.edge[e].y0, P.edge[e].y1, P.edge[e].sdx, P.edge[e].sdy, xn, yn, inside);
-    }
-    return inside;
 }
 
 // Wave-wide min / max of a uint32 (every lane of the wave must be active):
@@ -185,13 +180,14 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
 // in scalar registers and each of its edges is tested against every texel.
 // An edge whose both ends lie left of every candidate (xmax < min xn) is
 // skipped: for a point right of both ends the crossing test is false even
-// after rounding (the same monotonicity argument as the xhi bound).
+// after rounding (the same monotonicity argument as the xhi bound).  The
+// depth map is read last, only for texels inside the polygon.
 // Must be called by all 64 lanes.
 template <class PT>
 __device__ __forceinline__ void lasso_quad(const PT &P, const float *__restrict__ depth, const float4 &X,
                                            const float4 &Y, const float4 &Z, bool sel[4]) {
     const float xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w}, zs[4] = {Z.x, Z.y, Z.z, Z.w};
-    float xn[4], yn[4];
+    float xn[4], yn[4], cz[4], cw[4];
     bool cand[4], inside[4];
     unsigned smin = kSlabs, smax = 0;
     float xmin = INFINITY;
@@ -199,7 +195,7 @@ __device__ __forceinline__ void lasso_quad(const PT &P, const float *__restrict_
     for (int k = 0; k < 4; ++k) {
         xn[k] = 0.0f;
         yn[k] = 0.0f;
-        cand[k] = lasso_front(P, depth, xs[k], ys[k], zs[k], xn[k], yn[k]);
+        cand[k] = lasso_front(P, xs[k], ys[k], zs[k], xn[k], yn[k], cz[k], cw[k]);
         inside[k] = false;
         if (cand[k]) {
             const unsigned s = (unsigned)lasso_slab(P, yn[k]);
@@ -224,7 +220,7 @@ __device__ __forceinline__ void lasso_quad(const PT &P, const float *__restrict_
         }
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) sel[k] = cand[k] && inside[k];
+    for (int k = 0; k < 4; ++k) sel[k] = cand[k] && inside[k] && lasso_depth(P, depth, xn[k], yn[k], cz[k], cw[k]);
 }
 
 // ---------------------------------------------------------------------------

@@ -201,6 +201,7 @@ class GeometryImage:
         self.c.tile_box = None if self.tile_box is None else self.tile_box.data_ptr()
         self.c.area_scale = 0.0
         self.c.area_abs_err = 0.0
+        self.addr = ctypes.addressof(self.c)     # the uvl_geom the library reads
 
     @property
     def area_scale(self) -> float:
@@ -237,6 +238,7 @@ class Layer:
             data = torch.empty(_pad(n), dtype=tdt, device=device)
         self.data = data
         self.c = CLayer(data.data_ptr(), self.width, self.height, self.dtype)
+        self.addr = ctypes.addressof(self.c)
 
     @property
     def n(self) -> int:
@@ -347,48 +349,63 @@ def area_query(geom: GeometryImage, layers: Sequence[Layer], bins: Optional[torc
 # batched edit waves
 
 
+# uvl_edit as a numpy record (same offsets and size as CEdit), so a batch is
+# filled one tuple per edit and handed to the library without a copy
+EDIT_DTYPE = np.dtype({"names": [f[0] for f in CEdit._fields_],
+                       "formats": ["<u8", "<u8", "<i4", "<u4", ("<f4", (3,)), "<f4", "<u8", "<u8", "<i4", "<i4",
+                                   "<i4", "<f4", "<u8"],
+                       "offsets": [getattr(CEdit, f[0]).offset for f in CEdit._fields_],
+                       "itemsize": ctypes.sizeof(CEdit)})
+
+
+def _addr(a: np.ndarray) -> int:
+    return a.__array_interface__["data"][0]
+
+
 class EditBatch:
     """A packed array of uvl_edit records plus the host arrays they point to."""
 
-    def __init__(self):
-        self._recs = []
+    def __init__(self, capacity: int = 64):
+        self._a = np.zeros(max(1, int(capacity)), EDIT_DTYPE)
+        self._n = 0
+        self._nl = 0
         self._keep = []
+
+    def _slot(self) -> int:
+        if self._n == self._a.shape[0]:
+            a = np.zeros(2 * self._n, EDIT_DTYPE)
+            a[:self._n] = self._a
+            self._a = a
+        self._n += 1
+        return self._n - 1
 
     def brush(self, geom: GeometryImage, layer: Layer, center, radius: float, label: int):
         c = _f32(center, 3)
-        r = CEdit()
-        r.geom, r.layer = ctypes.addressof(geom.c), ctypes.addressof(layer.c)
-        r.kind, r.label = EDIT_BRUSH, int(label)
-        r.center[0], r.center[1], r.center[2] = float(c[0]), float(c[1]), float(c[2])
-        r.radius = float(np.float32(radius))
-        self._recs.append(r)
+        i = self._slot()
+        self._a[i] = (geom.addr, layer.addr, EDIT_BRUSH, int(label), c, np.float32(radius), 0, 0, 0, 0, 0, 0.0, 0)
         self._keep.append((geom, layer))
 
     def lasso(self, geom: GeometryImage, layer: Layer, view_proj, poly, depth: torch.Tensor, bias: float,
               label: int):
         M = _f32(view_proj, 16)
         P = _f32(poly).reshape(-1)
-        r = CEdit()
-        r.geom, r.layer = ctypes.addressof(geom.c), ctypes.addressof(layer.c)
-        r.kind, r.label = EDIT_LASSO, int(label)
-        r.view_proj = M.ctypes.data
-        r.poly_xy = P.ctypes.data
-        r.npoly = P.size // 2
-        r.dh, r.dw = depth.shape
-        r.bias = float(np.float32(bias))
-        r.depth = depth.data_ptr()
-        self._recs.append(r)
+        dh, dw = depth.shape
+        i = self._slot()
+        self._a[i] = (geom.addr, layer.addr, EDIT_LASSO, int(label), (0.0, 0.0, 0.0), 0.0, _addr(M), _addr(P),
+                      P.size // 2, dw, dh, np.float32(bias), depth.data_ptr())
+        self._nl += 1
         self._keep.append((geom, layer, M, P, depth))
 
     def __len__(self):
-        return len(self._recs)
+        return self._n
 
     @property
     def n_lassos(self) -> int:
-        return sum(1 for r in self._recs if r.kind == EDIT_LASSO)
+        return self._nl
 
     def array(self):
-        return (CEdit * len(self._recs))(*self._recs)
+        """Pointer to the records (valid while the batch lives)."""
+        return _addr(self._a)
 
 
 class Wave:

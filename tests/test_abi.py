@@ -9,6 +9,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -144,3 +145,33 @@ def test_build_and_depth_validation(uvl):
     assert L.uvl_render_depth(ctypes.byref(m), M, FAKE, 16, 16, FAKE, dws - 1, None) == -4
     assert L.uvl_create_layer(ctypes.byref(_layer(uvl, dt=5)), None) == -3
     assert L.uvl_create_layer(None, None) == -1
+
+
+def test_edit_records_match_the_c_struct():
+    """EditBatch fills numpy records that the library reads as uvl_edit."""
+    import ctypes
+    import torch
+    from paper_2501_14807_amd import uvl
+
+    class Fake:
+        def __init__(self, addr):
+            self.addr = addr
+
+    g, lay = Fake(0x1000), Fake(0x2000)
+    b = uvl.EditBatch(capacity=1)              # also exercises growth
+    b.brush(g, lay, (0.25, -1.5, 3.0), 0.125, 7)
+    M = np.arange(16, dtype=np.float32)
+    poly = np.array([[0, 0], [1, 0], [0, 1]], np.float32)
+    d = torch.zeros((48, 64), dtype=torch.float32)
+    b.lasso(g, lay, M, poly, d, 1e-4, 9)
+    assert len(b) == 2 and b.n_lassos == 1
+    raw = ctypes.string_at(b.array(), 2 * ctypes.sizeof(uvl.CEdit))
+    r0 = uvl.CEdit()
+    r0.geom, r0.layer, r0.kind, r0.label = 0x1000, 0x2000, uvl.EDIT_BRUSH, 7
+    r0.center[0], r0.center[1], r0.center[2], r0.radius = 0.25, -1.5, 3.0, 0.125
+    r1 = uvl.CEdit()
+    r1.geom, r1.layer, r1.kind, r1.label = 0x1000, 0x2000, uvl.EDIT_LASSO, 9
+    keep = b._keep[1]
+    r1.view_proj, r1.poly_xy, r1.npoly = keep[2].ctypes.data, keep[3].ctypes.data, 3
+    r1.dw, r1.dh, r1.bias, r1.depth = 64, 48, np.float32(1e-4), d.data_ptr()
+    assert raw == bytes(r0) + bytes(r1)

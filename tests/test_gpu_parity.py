@@ -202,7 +202,7 @@ def test_edits_ragged_sizes_and_u16(gpu, orc):
     import torch
     wl = synth.tiny_workload()
     rng = np.random.default_rng(9)
-    for (W, H) in ((37, 53), (1, 1), (4099, 3), (70, 70)):
+    for (W, H) in ((37, 53), (1, 1), (4099, 3), (70, 70), (132, 40), (256, 65)):
         dm = gpu.DeviceMesh.from_mesh(wl.mesh)
         g = gpu.GeometryImage(W, H)
         gpu.build_geometry_image(dm, g)
