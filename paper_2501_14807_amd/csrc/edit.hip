@@ -148,10 +148,21 @@ __global__ __launch_bounds__(kBlock) void k_lasso(const float *__restrict__ px, 
             Z[c] = make_float4(v[2][0], v[2][1], v[2][2], v[2][3]);
         }
     }
+    // all four steps' projections and polygon tests first, then all their
+    // depth reads, so that a wave waits for the depth map once
+    int pix[4][4];
+    float d[4][4], dv[4][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) lasso_quad_index(p, X[c], Y[c], Z[c], pix[c], d[c]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dv[c][k] = pix[c][k] >= 0 ? depth[pix[c][k]] : 0.0f;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         bool s[4];
-        lasso_quad(p, depth, X[c], Y[c], Z[c], s);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[k] = pix[c][k] >= 0 && lasso_depth_pass(p, d[c][k], dv[c][k]);
         const int y = y0 + 8 * c;
         const int64_t t = (int64_t)y * W + x;
         if (vec)

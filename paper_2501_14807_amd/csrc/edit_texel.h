@@ -81,7 +81,8 @@ struct LassoParams {
 // unit cube are discarded): clip coordinates c = M [x y z 1]^T, and true if
 // the texel is in front of the camera with its NDC x, y in the frustum and in
 // the polygon's bounding range.  The NDC z / depth part follows in
-// lasso_depth, so that it is evaluated only for texels inside the polygon.
+// lasso_depth_index, so that it is evaluated only for texels inside the
+// polygon.
 // PT is LassoParams, possibly qualified with the constant address space so
 // that a parameter block in global memory is read with scalar loads.
 template <class PT>
@@ -111,18 +112,26 @@ __device__ __forceinline__ bool lasso_front(const PT &P, float x, float y, float
     return yn >= P.ylo && yn < P.yhi && xn <= P.xhi;
 }
 
-// NDC z in [-1, 1] and the depth test of a texel that passed lasso_front.
+// NDC z in [-1, 1] for a texel that passed lasso_front; then its depth-map
+// index and window depth, the texel being selected iff
+// d <= depth[pix] + bias (lasso_depth_pass).
 template <class PT>
-__device__ __forceinline__ bool lasso_depth(const PT &P, const float *__restrict__ depth, float xn, float yn,
-                                            float cz, float cw) {
+__device__ __forceinline__ bool lasso_depth_index(const PT &P, float xn, float yn, float cz, float cw, int &pix,
+                                                  float &d) {
     const float zn = cz / cw;
     if (!(zn >= -1.0f && zn <= 1.0f)) return false;
     int ix = (int)floorf(__builtin_fmaf(xn, 0.5f, 0.5f) * (float)P.dw);
     int iy = (int)floorf(__builtin_fmaf(yn, 0.5f, 0.5f) * (float)P.dh);
     ix = ix > P.dw - 1 ? P.dw - 1 : ix;
     iy = iy > P.dh - 1 ? P.dh - 1 : iy;
-    const float d = __builtin_fmaf(zn, 0.5f, 0.5f);
-    return d <= depth[(int64_t)iy * P.dw + ix] + P.bias;
+    pix = iy * P.dw + ix;   // < 2^28 for depth maps up to 16384 x 16384
+    d = __builtin_fmaf(zn, 0.5f, 0.5f);
+    return true;
+}
+
+template <class PT>
+__device__ __forceinline__ bool lasso_depth_pass(const PT &P, float d, float stored) {
+    return d <= stored + P.bias;
 }
 
 template <class PT>
@@ -180,12 +189,15 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
 // in scalar registers and each of its edges is tested against every texel.
 // An edge whose both ends lie left of every candidate (xmax < min xn) is
 // skipped: for a point right of both ends the crossing test is false even
-// after rounding (the same monotonicity argument as the xhi bound).  The
-// depth map is read last, only for texels inside the polygon.
+// after rounding (the same monotonicity argument as the xhi bound).  Texels
+// inside the polygon then get their NDC z test; pix[k] is the depth-map
+// index still to be tested (d[k] <= depth[pix[k]] + bias), or -1 if the
+// texel is already rejected.  The depth reads are left to the caller, so
+// that it can issue many of them before waiting.
 // Must be called by all 64 lanes.
 template <class PT>
-__device__ __forceinline__ void lasso_quad(const PT &P, const float *__restrict__ depth, const float4 &X,
-                                           const float4 &Y, const float4 &Z, bool sel[4]) {
+__device__ __forceinline__ void lasso_quad_index(const PT &P, const float4 &X, const float4 &Y, const float4 &Z,
+                                                 int pix[4], float d[4]) {
     const float xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w}, zs[4] = {Z.x, Z.y, Z.z, Z.w};
     float xn[4], yn[4], cz[4], cw[4];
     bool cand[4], inside[4];
@@ -220,7 +232,22 @@ __device__ __forceinline__ void lasso_quad(const PT &P, const float *__restrict_
         }
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) sel[k] = cand[k] && inside[k] && lasso_depth(P, depth, xn[k], yn[k], cz[k], cw[k]);
+    for (int k = 0; k < 4; ++k) {
+        pix[k] = -1;
+        d[k] = 0.0f;
+        if (cand[k] && inside[k] && !lasso_depth_index(P, xn[k], yn[k], cz[k], cw[k], pix[k], d[k])) pix[k] = -1;
+    }
+}
+
+// The whole lasso predicate for 4 texels per lane (all 64 lanes).
+template <class PT>
+__device__ __forceinline__ void lasso_quad(const PT &P, const float *__restrict__ depth, const float4 &X,
+                                           const float4 &Y, const float4 &Z, bool sel[4]) {
+    int pix[4];
+    float d[4];
+    lasso_quad_index(P, X, Y, Z, pix, d);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sel[k] = pix[k] >= 0 && lasso_depth_pass(P, d[k], depth[pix[k]]);
 }
 
 // ---------------------------------------------------------------------------

@@ -10,23 +10,27 @@
 //
 // Work decomposition: edits are grouped by target layer into streams (each
 // stream keeps its edits' order); a stream's atlas is cut into 32 x 32-texel
-// tiles (row-major), and an item is `chunks` consecutive tiles (chunks per
+// tiles (row-major), and an item is `chunks` tiles of one stream (chunks per
 // stream chosen per atlas size by the autotuner); a fixed grid of workgroups
-// takes (stream, item) pairs from an atomic counter until none are left.
-// Every workgroup ends when the counter passes the item count, so the grid
-// always drains.  In a tile, lane t covers row t/8 and columns 4(t%8)..+3.
+// takes items from an atomic counter until none are left.  Every workgroup
+// ends when the counter passes the item count, so the grid always drains.
+// In a tile, lane t covers row t/8 and columns 4(t%8)..+3.
 //
 // Tile culling (when the geometry image has tile bounds): a first kernel
-// gives every (tile, group of 64 edits) one wave, each lane tests one edit
-// against the tile's bounds (exact conservative tests, edit_texel.h), and the
-// ballot -- the mask of edits that may select something there -- is stored in
-// the workspace.  The wave kernel then reads a tile only if some edit is live
-// and evaluates only the live edits.  Streams whose masks do not fit the
-// workspace run without culling.
+// gives every tile one lane; the lane tests the stream's edits against the
+// tile's bounds (exact conservative tests, edit_texel.h) and stores, per
+// group of 64 edits, the mask of edits that may select something there.
+// Tiles with a live edit are appended to the stream's live list (one atomic
+// per wave).  A one-workgroup kernel then turns the per-stream live counts
+// into item ranges, and the wave kernel visits only live tiles, evaluating
+// only their live edits.  Streams whose masks do not fit the workspace run
+// without culling (every tile is an item).
 //
-// The descriptor (streams, edits, lasso parameters) is copied host->device
-// into the caller's workspace before each launch; the counter reset and the
-// persistent kernel are captured once per handle in a HIP graph and replayed.
+// The descriptor (header with the region offsets, streams, per-stream
+// counters, edits, lasso parameters) is packed densely on the host and
+// copied host->device into the caller's workspace before each launch; the
+// counter reset, the cull pass, the planning kernel and the persistent
+// kernel are captured once per handle in a HIP graph and replayed.
 #include <math.h>
 #include <string.h>
 
@@ -54,14 +58,16 @@ struct WaveStream {
     const float *px, *py, *pz;
     const float *box;   // per-tile position bounds, or null (no culling)
     void *layer;
-    int64_t item0;      // first item of this stream
     int64_t mask0;      // first cull-mask word of this stream (running offset)
+    int64_t cwave0;     // first cull wave of this stream (64 tiles per wave)
+    int64_t list0;      // first live-list entry of this stream
     int32_t W, H;       // atlas size
     int32_t tiles_x, ntiles;
     int32_t dtype;
     int32_t e0, ne;     // edits [e0, e0 + ne)
     int32_t chunks;     // tiles per item
     int32_t cull;       // 1: masks at mask0 (tiles x groups words), 0: no culling
+    int32_t pad;
 };
 
 struct WaveEdit {
@@ -73,29 +79,47 @@ struct WaveEdit {
     const float *depth;
 };
 
+// Byte offsets, within the workspace, of the regions of one packed wave.
 struct WaveHeader {
     int32_t nstreams;
     int32_t pad;
-    int64_t total_items;
-    int64_t total_words;     // cull-mask words in use
+    int64_t total_cull_waves;
+    int64_t total_items;     // written by k_wave_plan
+    uint64_t off_streams, off_live_n, off_item0, off_edits, off_lassos;
     unsigned int counter;
     unsigned int pad2[3];
 };
 
-// Workspace layout: header | streams | edits | lassos | cull masks
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Offsets of the descriptor regions for ns streams, n edits, nl lassos:
+// header | streams | live counts (uint32 per stream) | item starts (int64 per
+// stream + 1) | edits | lassos.
+void descriptor_offsets(int64_t ns, int64_t n, int64_t nl, WaveHeader &h, size_t &end) {
+    h.off_streams = 256;
+    h.off_live_n = al256(h.off_streams + sizeof(WaveStream) * (size_t)ns);
+    h.off_item0 = al256(h.off_live_n + sizeof(uint32_t) * (size_t)ns);
+    h.off_edits = al256(h.off_item0 + sizeof(int64_t) * (size_t)(ns + 1));
+    h.off_lassos = al256(h.off_edits + sizeof(WaveEdit) * (size_t)n);
+    end = h.off_lassos + sizeof(LassoParams) * (size_t)nl;
+}
+
+// Workspace layout: descriptor (at most `masks` bytes) | cull masks (uint64
+// per word) | live lists (uint32 tile index per entry, as many as words)
 struct Layout {
-    size_t streams, edits, lassos, masks, total;
+    size_t masks, live, total;
     int64_t max_words;
 };
 
 Layout layout(int32_t max_edits, int32_t max_lassos, int64_t max_words) {
-    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     Layout L;
-    L.streams = 256;
-    L.edits = L.streams + al(sizeof(WaveStream) * (size_t)max_edits);
-    L.lassos = L.edits + al(sizeof(WaveEdit) * (size_t)max_edits);
-    L.masks = L.lassos + al(sizeof(LassoParams) * (size_t)(max_lassos > 0 ? max_lassos : 1));
-    L.total = L.masks + al(sizeof(uint64_t) * (size_t)(max_words > 0 ? max_words : 1));
+    WaveHeader h;
+    size_t end = 0;
+    descriptor_offsets(max_edits, max_edits, max_lassos > 0 ? max_lassos : 0, h, end);
+    L.masks = al256(end);
+    const size_t words = (size_t)(max_words > 0 ? max_words : 1);
+    L.live = L.masks + al256(sizeof(uint64_t) * words);
+    L.total = L.live + al256(sizeof(uint32_t) * words);
     L.max_words = max_words;
     return L;
 }
@@ -121,61 +145,126 @@ __device__ __forceinline__ void wave_store(T *L, int64_t t, const uint32_t val[4
         if (wr[k] && in[k]) L[t + k] = (T)val[k];
 }
 
-// Cull masks: one wave per (tile, group of 64 edits) word, grid-striding
-// over the words in use.
-__global__ __launch_bounds__(kBlock) void k_wave_cull(const char *__restrict__ ws, const WaveHeader *__restrict__ hdr,
-                                                       size_t off_streams, size_t off_edits, size_t off_lassos,
-                                                       uint64_t *__restrict__ masks) {
-    const UVL_CONST WaveStream *streams = (const UVL_CONST WaveStream *)(ws + off_streams);
-    const UVL_CONST WaveEdit *edits = (const UVL_CONST WaveEdit *)(ws + off_edits);
-    const UVL_CONST LassoParams *lassos = (const UVL_CONST LassoParams *)(ws + off_lassos);
+// Last stream s (of n) with key(s) <= v; keys are non-decreasing.
+template <class F>
+__device__ __forceinline__ int last_le(int n, int64_t v, F key) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (key(mid) <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Cull pass: one lane per tile of the culling streams, grid-striding over
+// waves of 64 tiles.  The lane's masks (one word per group of 64 edits) go to
+// masks[mask0 + tile * groups + g]; the wave's tiles with a live edit are
+// appended to the stream's live list.
+__global__ __launch_bounds__(kBlock) void k_wave_cull(char *__restrict__ ws, uint64_t *__restrict__ masks,
+                                                       uint32_t *__restrict__ live) {
+    const UVL_CONST WaveHeader *hdr = (const UVL_CONST WaveHeader *)ws;
+    const UVL_CONST WaveStream *streams = (const UVL_CONST WaveStream *)(ws + hdr->off_streams);
+    const UVL_CONST WaveEdit *edits = (const UVL_CONST WaveEdit *)(ws + hdr->off_edits);
+    const UVL_CONST LassoParams *lassos = (const UVL_CONST LassoParams *)(ws + hdr->off_lassos);
+    uint32_t *live_n = reinterpret_cast<uint32_t *>(ws + hdr->off_live_n);
     const int32_t nstreams = hdr->nstreams;
-    const int64_t total = hdr->total_words;
+    const int64_t total = hdr->total_cull_waves;
     const int lane = threadIdx.x & 63;
     const int64_t wave0 = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
-    for (int64_t word = wave0; word < total; word += nwaves) {
-        // stream owning the word: the last stream with mask0 <= word (streams
-        // without culling own no words, so this is a culling stream)
-        int lo = 0, hi = nstreams - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (streams[mid].mask0 <= word) lo = mid;
-            else hi = mid - 1;
-        }
-        const UVL_CONST WaveStream &S = streams[lo];
+    for (int64_t cw = wave0; cw < total; cw += nwaves) {
+        // streams without culling own no cull waves and every culling stream
+        // owns at least one, so this is the culling stream owning the wave
+        const int si = last_le(nstreams, cw, [&](int k) { return streams[k].cwave0; });
+        const UVL_CONST WaveStream &S = streams[si];
         const int groups = (S.ne + 63) >> 6;
-        const int64_t rel = word - S.mask0;
-        const int64_t ti = rel / groups;
-        const int g = (int)(rel % groups);
+        const int64_t ti = (cw - S.cwave0) * 64 + lane;
+        const bool in = ti < S.ntiles;
         float box[6];
-        const UVL_CONST float *bp = (const UVL_CONST float *)(S.box + 6 * ti);
 #pragma unroll
-        for (int q = 0; q < 6; ++q) box[q] = bp[q];
-        const int e = g * 64 + lane;
-        bool alive = false;
-        if (e < S.ne) {
-            const UVL_CONST WaveEdit &E = edits[S.e0 + e];
-            alive = E.kind == UVL_EDIT_BRUSH ? !brush_culls(BrushParams{E.cx, E.cy, E.cz, E.r2}, box)
-                                             : !lasso_culls(lassos[E.lasso], box);
+        for (int q = 0; q < 6; ++q) box[q] = in ? S.box[6 * ti + q] : 1.0f;
+        if (!in) box[0] = 2.0f;   // empty box: min > max
+        bool any = false;
+        for (int g = 0; g < groups; ++g) {
+            uint64_t m = 0;
+            const int lim = S.ne - 64 * g < 64 ? S.ne - 64 * g : 64;
+            for (int k = 0; k < lim; ++k) {
+                const UVL_CONST WaveEdit &E = edits[S.e0 + 64 * g + k];
+                const bool alive = E.kind == UVL_EDIT_BRUSH ? !brush_culls(BrushParams{E.cx, E.cy, E.cz, E.r2}, box)
+                                                            : !lasso_culls(lassos[E.lasso], box);
+                m |= (uint64_t)alive << k;
+            }
+            if (in) masks[S.mask0 + ti * groups + g] = m;
+            any = any || m != 0;
         }
-        const uint64_t m = __ballot(alive);
-        if (lane == 0) masks[word] = m;
+        const uint64_t b = __ballot(any && in);
+        if (b) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(live_n + si, (uint32_t)__popcll(b));
+            base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+            if (any && in) {
+                const uint32_t rank = (uint32_t)__popcll(b & ((1ull << lane) - 1));
+                live[S.list0 + base + rank] = (uint32_t)ti;
+            }
+        }
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_wave(const char *__restrict__ ws, WaveHeader *__restrict__ hdr,
-                                                  size_t off_streams, size_t off_edits, size_t off_lassos,
-                                                  const uint64_t *__restrict__ masks_in) {
-    // read-only descriptor and masks viewed in the constant address space:
-    // uniform reads become scalar loads
-    const UVL_CONST WaveStream *streams = (const UVL_CONST WaveStream *)(ws + off_streams);
-    const UVL_CONST WaveEdit *edits = (const UVL_CONST WaveEdit *)(ws + off_edits);
-    const UVL_CONST LassoParams *lassos = (const UVL_CONST LassoParams *)(ws + off_lassos);
+// Item ranges: stream s owns items [item0[s], item0[s + 1]), ceil(tiles /
+// chunks) of them, tiles being its live-list length (culling streams) or all
+// its tiles.  One workgroup: a per-thread serial range, then a block scan.
+__global__ __launch_bounds__(kBlock) void k_wave_plan(char *__restrict__ ws) {
+    WaveHeader *hdr = reinterpret_cast<WaveHeader *>(ws);
+    const WaveStream *streams = reinterpret_cast<const WaveStream *>(ws + hdr->off_streams);
+    const uint32_t *live_n = reinterpret_cast<const uint32_t *>(ws + hdr->off_live_n);
+    int64_t *item0 = reinterpret_cast<int64_t *>(ws + hdr->off_item0);
+    const int n = hdr->nstreams;
+    const int per = (n + kBlock - 1) / kBlock;
+    const int a = threadIdx.x * per, b = a + per < n ? a + per : n;
+    auto items = [&](int k) {
+        const WaveStream &S = streams[k];
+        const int64_t tiles = S.cull ? (int64_t)live_n[k] : (int64_t)S.ntiles;
+        return (tiles + S.chunks - 1) / S.chunks;
+    };
+    int64_t sum = 0;
+    for (int k = a; k < b; ++k) sum += items(k);
+    __shared__ int64_t part[kBlock];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int d = 1; d < kBlock; d <<= 1) {
+        const int64_t v = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t run = part[threadIdx.x] - sum;   // exclusive prefix
+    for (int k = a; k < b; ++k) {
+        item0[k] = run;
+        run += items(k);
+    }
+    if (threadIdx.x == kBlock - 1) {
+        item0[n] = part[kBlock - 1];
+        hdr->total_items = part[kBlock - 1];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_wave(char *__restrict__ ws, const uint64_t *__restrict__ masks_in,
+                                                  const uint32_t *__restrict__ live_in) {
+    // read-only descriptor, masks and live lists viewed in the constant
+    // address space: uniform reads become scalar loads
+    WaveHeader *hdr = reinterpret_cast<WaveHeader *>(ws);
+    const UVL_CONST WaveHeader *chdr = (const UVL_CONST WaveHeader *)ws;
+    const UVL_CONST WaveStream *streams = (const UVL_CONST WaveStream *)(ws + chdr->off_streams);
+    const UVL_CONST WaveEdit *edits = (const UVL_CONST WaveEdit *)(ws + chdr->off_edits);
+    const UVL_CONST LassoParams *lassos = (const UVL_CONST LassoParams *)(ws + chdr->off_lassos);
+    const UVL_CONST uint32_t *live_n = (const UVL_CONST uint32_t *)(ws + chdr->off_live_n);
+    const UVL_CONST int64_t *item0 = (const UVL_CONST int64_t *)(ws + chdr->off_item0);
     const UVL_CONST uint64_t *masks = (const UVL_CONST uint64_t *)masks_in;
+    const UVL_CONST uint32_t *live = (const UVL_CONST uint32_t *)live_in;
     __shared__ long long s_item;
-    const int32_t nstreams = hdr->nstreams;
-    const int64_t total = hdr->total_items;
+    const int32_t nstreams = chdr->nstreams;
+    const int64_t total = chdr->total_items;
     const int trow = threadIdx.x >> 3, tcol = (threadIdx.x & 7) * 4;
     for (;;) {
         if (threadIdx.x == 0) s_item = (long long)atomicAdd(&hdr->counter, 1u);
@@ -183,27 +272,19 @@ __global__ __launch_bounds__(kBlock) void k_wave(const char *__restrict__ ws, Wa
         const int64_t item = s_item;
         __syncthreads();
         if (item >= total) break;
-        // stream holding the item: last stream with item0 <= item
-        int lo = 0, hi = nstreams - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (streams[mid].item0 <= item) lo = mid;
-            else hi = mid - 1;
-        }
-        const UVL_CONST WaveStream &S = streams[lo];
+        // stream holding the item (streams owning no items share their
+        // start with the next stream, which is found instead)
+        const int si = last_le(nstreams, item, [&](int k) { return item0[k]; });
+        const UVL_CONST WaveStream &S = streams[si];
         const int chunks = S.chunks, W = S.W, H = S.H;
         const int groups = (S.ne + 63) >> 6;
         const bool cull = S.cull != 0;
-        const int64_t tile_first = (item - S.item0) * (int64_t)chunks;
+        const int64_t first = (item - item0[si]) * (int64_t)chunks;
+        const int64_t ntiles = cull ? (int64_t)live_n[si] : (int64_t)S.ntiles;
         for (int c = 0; c < chunks; ++c) {
-            const int64_t ti = tile_first + c;
-            if (ti >= S.ntiles) break;
+            if (first + c >= ntiles) break;
+            const int64_t ti = cull ? (int64_t)live[S.list0 + first + c] : first + c;
             const UVL_CONST uint64_t *tm = masks + (cull ? S.mask0 + ti * groups : 0);
-            if (cull) {
-                uint64_t any = 0;
-                for (int g = 0; g < groups; ++g) any |= tm[g];
-                if (!any) continue;
-            }
             const int tx = (int)(ti % S.tiles_x), ty = (int)(ti / S.tiles_x);
             // uniform over the workgroup: whole tile inside, rows 16-byte aligned
             const bool full = (tx + 1) * UVL_TILE_SIDE <= W && (ty + 1) * UVL_TILE_SIDE <= H && (W & 3) == 0;
@@ -233,13 +314,13 @@ __global__ __launch_bounds__(kBlock) void k_wave(const char *__restrict__ ws, Wa
             uint32_t val[4] = {0, 0, 0, 0};
             bool wr[4] = {false, false, false, false};
             for (int g = 0; g < groups; ++g) {
-                uint64_t live = cull ? tm[g] : ~0ull;
+                uint64_t lm = cull ? tm[g] : ~0ull;
                 const int base = g * 64;
                 const int lim = S.ne - base < 64 ? S.ne - base : 64;
-                if (lim < 64) live &= (1ull << lim) - 1;
-                while (live) {
-                    const int e = base + __builtin_ctzll(live);
-                    live &= live - 1;
+                if (lim < 64) lm &= (1ull << lim) - 1;
+                while (lm) {
+                    const int e = base + __builtin_ctzll(lm);
+                    lm &= lm - 1;
                     const UVL_CONST WaveEdit &E = edits[S.e0 + e];
                     bool sel[4];
                     if (E.kind == UVL_EDIT_BRUSH) {
@@ -325,13 +406,13 @@ extern "C" int32_t uvl_wave_create(int32_t max_edits, int32_t max_lassos, int64_
         hipGraph_t g = nullptr;
         WaveHeader *hdr = reinterpret_cast<WaveHeader *>(w->ws);
         uint64_t *masks = reinterpret_cast<uint64_t *>(w->ws + lay.masks);
+        uint32_t *live = reinterpret_cast<uint32_t *>(w->ws + lay.live);
         ok = hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
             hipLaunchKernelGGL(k_wave_reset, dim3(1), dim3(64), 0, w->cap, hdr);
-            hipLaunchKernelGGL(k_wave_cull, dim3(kWaveGrid), dim3(kBlock), 0, w->cap, w->ws, hdr, lay.streams,
-                               lay.edits, lay.lassos, masks);
-            hipLaunchKernelGGL(k_wave, dim3(kWaveGrid), dim3(kBlock), 0, w->cap, w->ws, hdr, lay.streams, lay.edits,
-                               lay.lassos, masks);
+            hipLaunchKernelGGL(k_wave_cull, dim3(kWaveGrid), dim3(kBlock), 0, w->cap, w->ws, masks, live);
+            hipLaunchKernelGGL(k_wave_plan, dim3(1), dim3(kBlock), 0, w->cap, w->ws);
+            hipLaunchKernelGGL(k_wave, dim3(kWaveGrid), dim3(kBlock), 0, w->cap, w->ws, masks, live);
             ok = hipStreamEndCapture(w->cap, &g) == hipSuccess && g;
         }
         ok = ok && hipGraphInstantiate(&w->exec, g, nullptr, nullptr, 0) == hipSuccess;
@@ -407,10 +488,13 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
     }
     char *st = w->staging;
     WaveHeader *hdr = reinterpret_cast<WaveHeader *>(st);
-    WaveStream *S = reinterpret_cast<WaveStream *>(st + w->lay.streams);
-    WaveEdit *E = reinterpret_cast<WaveEdit *>(st + w->lay.edits);
-    LassoParams *P = reinterpret_cast<LassoParams *>(st + w->lay.lassos);
-    int64_t item = 0, words = 0;
+    size_t end = 0;
+    descriptor_offsets((int64_t)keys.size(), n, nl, *hdr, end);
+    WaveStream *S = reinterpret_cast<WaveStream *>(st + hdr->off_streams);
+    uint32_t *live_n = reinterpret_cast<uint32_t *>(st + hdr->off_live_n);
+    WaveEdit *E = reinterpret_cast<WaveEdit *>(st + hdr->off_edits);
+    LassoParams *P = reinterpret_cast<LassoParams *>(st + hdr->off_lassos);
+    int64_t words = 0, cwaves = 0;
     int32_t ei = 0, li = 0;
     for (size_t k = 0; k < keys.size(); ++k) {
         const uvl_edit &f = edits[members[k][0]];
@@ -425,16 +509,23 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
         s.tiles_x = (int32_t)ceil_div(s.W, UVL_TILE_SIDE);
         s.ntiles = s.tiles_x * (int32_t)ceil_div(s.H, UVL_TILE_SIDE);
         s.dtype = f.layer->dtype;
+        s.pad = 0;
         int ch = chunks_override > 0 ? chunks_override : w->tuned_chunks[log2_class((int64_t)s.W * s.H)];
         if (ch <= 0) ch = 4;
         s.chunks = std::min(std::max(ch, 1), kMaxChunks);
-        s.item0 = item;
-        item += ceil_div(s.ntiles, s.chunks);
-        // cull masks if the geometry has tile bounds and the words fit
+        // cull masks (tiles x groups words) and the live list (up to one
+        // entry per tile, fewer than the words) if the geometry has tile
+        // bounds and the words fit
         const int64_t nw = (int64_t)s.ntiles * ((int64_t)(members[k].size() + 63) / 64);
-        s.mask0 = words;
         s.cull = (f.geom->tile_box && words + nw <= w->lay.max_words) ? 1 : 0;
-        if (s.cull) words += nw;
+        s.mask0 = words;
+        s.list0 = words;
+        s.cwave0 = cwaves;
+        if (s.cull) {
+            words += nw;
+            cwaves += ceil_div(s.ntiles, 64);
+        }
+        live_n[k] = 0;
         s.e0 = ei;
         s.ne = (int32_t)members[k].size();
         for (int32_t i : members[k]) {
@@ -462,10 +553,10 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
     }
     hdr->nstreams = (int32_t)keys.size();
     hdr->pad = 0;
-    hdr->total_items = item;
-    hdr->total_words = words;
+    hdr->total_cull_waves = cwaves;
+    hdr->total_items = 0;
     hdr->counter = 0;
-    bytes = li > 0 ? w->lay.lassos + sizeof(LassoParams) * (size_t)li : w->lay.lassos;
+    bytes = end;
     return UVL_OK;
 }
 
