@@ -200,6 +200,10 @@ def bench_batched(n_models, reps, torch, uvl):
     }
 
 
+# offered request rates of the serving sweep (requests/s)
+SERVE_RATES = (4000.0, 8000.0, 12000.0, 16000.0, 24000.0, 32000.0, 48000.0, 64000.0)
+
+
 def bench_serving(n_each, n_requests, slo_ms, torch, uvl):
     """Continuous batching against plain one-launch-per-request serving.
 
@@ -227,7 +231,7 @@ def bench_serving(n_each, n_requests, slo_ms, torch, uvl):
     models = [Model(m, s_, s_, dt, depth_w=d, depth_h=d).build() for m, s_, dt, d in zip(meshes, sizes, dtypes, depth)]
     log(f"serving: {len(models)} models resident after {time.perf_counter() - t:.1f} s")
     sweep = []
-    for qps in (1000.0, 4000.0, 16000.0, 64000.0):
+    for qps in SERVE_RATES:
         cams, stream = synth.serve_stream(meshes, dtypes, n_requests, qps, seed=int(qps))
         row = {"qps": qps}
         for mode in ("plain", "batched"):

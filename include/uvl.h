@@ -265,8 +265,12 @@ int32_t uvl_wave_create(int32_t max_edits, int32_t max_lassos, int64_t max_cull_
                         uvl_wave **out);
 
 /* Apply edits[0..n) on `stream`: the descriptor is copied host->device into
- * the workspace, then the captured graph (counter reset, tile-culling masks,
- * persistent kernel) is replayed.  tile_chunks in 1..8 forces tiles of tile_chunks*1024 texels;
+ * the workspace, then the captured graph (counter reset, tile culling into
+ * per-layer lists of live tiles, item planning, persistent kernel) is
+ * replayed.  A tile is skipped when its position bounds prove that no edit
+ * selects a texel there: brushes by distance, lassos by the polygon's screen
+ * extent and, when the tile's depth-map footprint is at most 1024 pixels,
+ * by the depth test (every texel behind the stored depth plus bias).  tile_chunks in 1..8 forces tiles of tile_chunks*1024 texels;
  * 0 uses the tuned size of each layer's atlas size (4 if not tuned).  Edits
  * of different layers are independent; edits of one layer apply in order.
  * The edits array may be freed on return.  Submits on one handle are
@@ -286,6 +290,12 @@ int32_t uvl_wave_tune(uvl_wave *w, const uvl_edit *edits, int32_t n, void *strea
 /* The tuned tile size (chunks of 1024 texels) for an atlas of `texels`
  * texels, 0 if that size class is not tuned. */
 int32_t uvl_wave_tuned_chunks(const uvl_wave *w, int64_t texels);
+
+/* Tiles the last submit on this handle visited (the live tiles of layers
+ * with culling plus every tile of layers without), written to *tiles.
+ * SYNCHRONOUS on `stream`, which must be the stream of that submit.
+ * Errors: UVL_E_INVAL, UVL_E_DEVICE. */
+int32_t uvl_wave_visited_tiles(uvl_wave *w, int64_t *tiles, void *stream);
 
 /* Release the handle (waits for its last descriptor copy). */
 int32_t uvl_wave_destroy(uvl_wave *w);

@@ -228,6 +228,7 @@ bool make_lasso_params(const float view_proj[16], const float *poly, int32_t n, 
             p.cull.wrow[j] = Md[12 + j];
             p.cull.ax[j] = fabs(Md[j]);
             p.cull.ay[j] = fabs(Md[4 + j]);
+            p.cull.az[j] = fabs(Md[8 + j]);
             p.cull.aw[j] = fabs(Md[12 + j]);
         }
     }

@@ -57,7 +57,7 @@ struct alignas(32) LassoEdge {
 struct LassoCull {
     double plane[4][4];
     double wrow[4];
-    double ax[4], ay[4], aw[4];
+    double ax[4], ay[4], az[4], aw[4];
     // x-range of the edges that can straddle a point of slab s:
     // [slab_x0[s], slab_x1[s]] (min / max over the edges of slab_edges[s];
     // empty slab: x0 = +inf, x1 = -inf)
@@ -293,51 +293,41 @@ __device__ __forceinline__ double box_abs_max(const double a[4], const float box
 }
 
 template <class PT>
-__device__ __forceinline__ bool lasso_culls_slabs(const PT &P, const float box[6]);
-
-template <class PT>
-__device__ __forceinline__ bool lasso_culls(const PT &P, const float box[6]) {
-    const auto &C = P.cull;
-    if (!(box[0] <= box[3] && box[1] <= box[4] && box[2] <= box[5])) return true;
-    double wneg[4];
+__device__ __forceinline__ double row_abs_max(const PT &row, const float box[6]) {
+    double a[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) wneg[j] = -C.wrow[j];
-    const double wmin = -box_max(wneg, box);
-    double ax[4], ay[4], aw[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        ax[j] = C.ax[j];
-        ay[j] = C.ay[j];
-        aw[j] = C.aw[j];
-    }
-    const double smax = fmax(box_abs_max(ax, box), box_abs_max(ay, box)) + box_abs_max(aw, box);
-    if (!(wmin >= 1e-3 * smax) || !(wmin > 0.0)) return false;
-#pragma unroll 1
-    for (int k = 0; k < 4; ++k) {
-        double a[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) a[j] = C.plane[k][j];
-        if (box_max(a, box) < 0.0) return true;
-    }
-    return lasso_culls_slabs(P, box);
+    for (int j = 0; j < 4; ++j) a[j] = row[j];
+    return box_abs_max(a, box);
 }
 
-// Tighter lasso test by y-slabs (reached only with the conditioning above
-// satisfied).  With every corner in front of the camera
-// (wmin > 0 above) the box projects into the bounding box of its corners'
-// NDC images (fp64 here, so within 1e-12), and every texel's fp32 NDC
-// position lies within eps = 5e-4 of that box.  A texel whose fp32 y falls in
-// slab s and whose fp32 x exceeds slab_x1[s] is right of every edge that can
-// straddle it (outside exactly), and one with x below slab_x0[s] - 1e-3 is
-// left of all of them by the margin (outside).  The texel slab index is
-// floor((y - ylo) inv_h) of an fp32 y; the slab range of the tile's y-range
-// is taken one slab wider on each side.  If every slab in that range misses
-// the tile's x-range, the tile is culled.
+// Further lasso tests, reached with the conditioning satisfied and every
+// corner in front of the camera (wmin > 0).  The box then projects into the
+// bounding box of its corners' NDC images (fp64 here, so within 1e-12), and
+// every texel's fp32 NDC position lies within eps = 5e-4 of that box.
+//
+// Slabs: a texel whose fp32 y falls in slab s and whose fp32 x exceeds
+// slab_x1[s] is right of every edge that can straddle it (outside exactly),
+// and one with x below slab_x0[s] - 1e-3 is left of all of them by the margin
+// (outside).  The texel slab index is floor((y - ylo) inv_h) of an fp32 y;
+// the slab range of the tile's y-range is taken one slab wider on each side.
+// If every slab in that range misses the tile's x-range, the tile is culled.
+//
+// Depth (when a depth map is given): z/w over the box is a linear-fractional
+// function with a positive denominator, so its minimum is the corners'
+// minimum zmin.  A texel's fp32 NDC z differs from its exact z/w by at most
+// (|dc_z| + 2 |dc_w|) / w_hat + u (its fp32 z being in [-1, 1] when it gets
+// that far, so its exact z/w is within 2), where |dc| <= 3.01 u (row |M|
+// sum over the box) bounds the fma chains and u = 2^-24; its window depth
+// adds u.  Its depth-map pixel lies in the rectangle of the NDC box widened
+// by eps, one pixel more on each side.  If the smallest window depth a texel
+// can have exceeds the largest fl(D + bias) over that rectangle, every texel
+// fails the depth test.  The rectangle is read directly when it has at most
+// kDepthCullPixels pixels.
+constexpr int kDepthCullPixels = 1024;
+
 template <class PT>
-__device__ __forceinline__ bool lasso_culls_slabs(const PT &P, const float box[6]) {
-    if (!(P.inv_h > 0.0f)) return false;
-    
-    double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+__device__ __forceinline__ bool lasso_culls_more(const PT &P, const float box[6], const float *depth, double wmin) {
+    double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY, zmin = INFINITY;
 #pragma unroll 1
     for (int k = 0; k < 8; ++k) {
         const double x = (k & 1) ? box[3] : box[0];
@@ -348,25 +338,72 @@ __device__ __forceinline__ bool lasso_culls_slabs(const PT &P, const float box[6
         for (int r = 0; r < 4; ++r)
             c[r] = (double)P.M[4 * r] * x + (double)P.M[4 * r + 1] * y + (double)P.M[4 * r + 2] * z + (double)P.M[4 * r + 3];
         if (!(c[3] > 0.0)) return false;
-        const double xn = c[0] / c[3], yn = c[1] / c[3];
+        const double xn = c[0] / c[3], yn = c[1] / c[3], zn = c[2] / c[3];
         x0 = fmin(x0, xn);
         x1 = fmax(x1, xn);
         y0 = fmin(y0, yn);
         y1 = fmax(y1, yn);
+        zmin = fmin(zmin, zn);
     }
     const double eps = 5e-4;
-    x0 -= eps;
-    x1 += eps;
-    const double h = 1.0 / (double)P.inv_h;
-    int s0 = (int)floor((y0 - eps - (double)P.ylo) / h) - 1;
-    int s1 = (int)floor((y1 + eps - (double)P.ylo) / h) + 1;
-    s0 = s0 < 0 ? 0 : s0;
-    s1 = s1 > kSlabs - 1 ? kSlabs - 1 : s1;
-    for (int s = s0; s <= s1; ++s) {
-        const double a = (double)P.cull.slab_x0[s] - 1e-3, b = (double)P.cull.slab_x1[s];
-        if (a <= x1 && b >= x0) return false;
+    if (P.inv_h > 0.0f) {
+        const double h = 1.0 / (double)P.inv_h;
+        int s0 = (int)floor((y0 - eps - (double)P.ylo) / h) - 1;
+        int s1 = (int)floor((y1 + eps - (double)P.ylo) / h) + 1;
+        s0 = s0 < 0 ? 0 : s0;
+        s1 = s1 > kSlabs - 1 ? kSlabs - 1 : s1;
+        bool hit = false;
+        for (int s = s0; s <= s1 && !hit; ++s) {
+            const double a = (double)P.cull.slab_x0[s] - 1e-3, b = (double)P.cull.slab_x1[s];
+            hit = a <= x1 + eps && b >= x0 - eps;
+        }
+        if (!hit) return true;
     }
+    if (!depth) return false;
+    const double u = 0x1p-24;
+    const double az = row_abs_max(P.cull.az, box), aw = row_abs_max(P.cull.aw, box);
+    const double dcz = 3.01 * u * az, dcw = 3.01 * u * aw;
+    if (!(dcw < 0.5 * wmin)) return false;
+    const double err_z = (dcz + 2.0 * dcw) / (wmin - dcw) + 2.0 * u + 1e-12;
+    const double dlo = 0.5 * (zmin - err_z) + 0.5 - 2.0 * u;   // smallest fp32 window depth of a texel
+    const int dw = P.dw, dh = P.dh;
+    int ix0 = (int)floor(((x0 - eps) * 0.5 + 0.5) * dw) - 1, ix1 = (int)floor(((x1 + eps) * 0.5 + 0.5) * dw) + 1;
+    int iy0 = (int)floor(((y0 - eps) * 0.5 + 0.5) * dh) - 1, iy1 = (int)floor(((y1 + eps) * 0.5 + 0.5) * dh) + 1;
+    ix0 = ix0 < 0 ? 0 : ix0;
+    iy0 = iy0 < 0 ? 0 : iy0;
+    ix1 = ix1 > dw - 1 ? dw - 1 : ix1;
+    iy1 = iy1 > dh - 1 ? dh - 1 : iy1;
+    if (ix0 > ix1 || iy0 > iy1) return false;
+    if ((int64_t)(ix1 - ix0 + 1) * (iy1 - iy0 + 1) > kDepthCullPixels) return false;
+    // fl(D + bias) <= (D + bias) + u |D + bias|; culled iff dlo exceeds that
+    // for every pixel of the rectangle
+    const double bias = P.bias;
+    for (int iy = iy0; iy <= iy1; ++iy)
+        for (int ix = ix0; ix <= ix1; ++ix) {
+            const double v = (double)depth[(int64_t)iy * dw + ix] + bias;
+            if (!(dlo > v + u * fabs(v) + 1e-12)) return false;
+        }
     return true;
+}
+
+template <class PT>
+__device__ __forceinline__ bool lasso_culls(const PT &P, const float box[6], const float *depth = nullptr) {
+    const auto &C = P.cull;
+    if (!(box[0] <= box[3] && box[1] <= box[4] && box[2] <= box[5])) return true;
+    double wneg[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) wneg[j] = -C.wrow[j];
+    const double wmin = -box_max(wneg, box);
+    const double smax = fmax(row_abs_max(C.ax, box), row_abs_max(C.ay, box)) + row_abs_max(C.aw, box);
+    if (!(wmin >= 1e-3 * smax) || !(wmin > 0.0)) return false;
+#pragma unroll 1
+    for (int k = 0; k < 4; ++k) {
+        double a[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a[j] = C.plane[k][j];
+        if (box_max(a, box) < 0.0) return true;
+    }
+    return lasso_culls_more(P, box, depth, wmin);
 }
 
 }  // namespace uvl

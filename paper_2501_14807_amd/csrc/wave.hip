@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_wave_cull(char *__restrict__ ws, uin
             for (int k = 0; k < lim; ++k) {
                 const UVL_CONST WaveEdit &E = edits[S.e0 + 64 * g + k];
                 const bool alive = E.kind == UVL_EDIT_BRUSH ? !brush_culls(BrushParams{E.cx, E.cy, E.cz, E.r2}, box)
-                                                            : !lasso_culls(lassos[E.lasso], box);
+                                                            : !lasso_culls(lassos[E.lasso], box, E.depth);
                 m |= (uint64_t)alive << k;
             }
             if (in) masks[S.mask0 + ti * groups + g] = m;
@@ -631,6 +631,32 @@ extern "C" int32_t uvl_wave_tune(uvl_wave *w, const uvl_edit *edits, int32_t n, 
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     return status;
+}
+
+extern "C" int32_t uvl_wave_visited_tiles(uvl_wave *w, int64_t *tiles, void *stream) {
+    if (!w || !tiles) return UVL_E_INVAL;
+    std::lock_guard<std::mutex> lock(w->mu);
+    hipStream_t s = as_stream(stream);
+    // the header (for the region offsets and stream count), then the streams
+    // and their live counters
+    WaveHeader h;
+    if (hipMemcpyAsync(&h, w->ws, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return UVL_E_DEVICE;
+    if (h.nstreams < 0 || h.nstreams > w->max_edits) return UVL_E_DEVICE;
+    std::vector<WaveStream> st((size_t)h.nstreams);
+    std::vector<uint32_t> live_n((size_t)h.nstreams);
+    if (h.nstreams > 0 &&
+        (hipMemcpyAsync(st.data(), w->ws + h.off_streams, sizeof(WaveStream) * st.size(), hipMemcpyDeviceToHost,
+                        s) != hipSuccess ||
+         hipMemcpyAsync(live_n.data(), w->ws + h.off_live_n, sizeof(uint32_t) * live_n.size(),
+                        hipMemcpyDeviceToHost, s) != hipSuccess ||
+         hipStreamSynchronize(s) != hipSuccess))
+        return UVL_E_DEVICE;
+    int64_t sum = 0;
+    for (size_t k = 0; k < st.size(); ++k) sum += st[k].cull ? (int64_t)live_n[k] : (int64_t)st[k].ntiles;
+    *tiles = sum;
+    return UVL_OK;
 }
 
 extern "C" int32_t uvl_wave_tuned_chunks(const uvl_wave *w, int64_t texels) {

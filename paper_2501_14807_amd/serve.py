@@ -16,7 +16,10 @@ takes, for every model with queued requests, the prefix of its queue up to
 the first non-edit request; all those edits go into one wave launch
 (uvl_wave_submit); then each such model's following area / algebra requests
 are launched in order.  Up to `max_inflight` rounds are on the device at
-once; requests that arrive while rounds run join the next round.
+once; requests that arrive while rounds run join the next round.  A round
+starts at once when the device is idle; with rounds in flight, the next one
+waits for `min_batch` queued requests or for its oldest request to have
+waited `max_wait_s`, so that a busy device gets fewer, larger waves.
 
 Plain mode: every request is launched on arrival, one launch per request.
 
@@ -265,10 +268,16 @@ class Stats:
 
 class Server:
     def __init__(self, executor: Executor, n_models: int, budget_bytes: int, max_wave_edits: int = 4096,
-                 max_inflight: int = 2):
+                 max_inflight: int = 2, min_batch: int = 32, max_wait_s: float = 2e-3):
         self.ex = executor
         self.max_wave_edits = max_wave_edits
         self.max_inflight = max_inflight
+        # a round starts at once when the device is idle; while rounds are in
+        # flight, a further one starts only with min_batch requests queued or
+        # once the oldest has waited max_wait_s (small rounds pay the fixed
+        # cost of a launch each)
+        self.min_batch = min_batch
+        self.max_wait_s = max_wait_s
         # admission by HBM footprint, in model order, within the budget
         self.resident = set()
         used = 0
@@ -290,6 +299,7 @@ class Server:
         t0 = time.perf_counter()
         n = len(reqs)
         completed = 0
+        nq = 0                                  # queued requests
 
         def now():
             return time.perf_counter() - t0
@@ -306,6 +316,7 @@ class Server:
                     completed += 1
                     continue
                 queues.setdefault(r.model, deque()).append(r)
+                nq += 1
             # completions (in order: one in-order device queue)
             while inflight and self.ex.done(inflight[0].handle):
                 rd = inflight.popleft()
@@ -314,12 +325,18 @@ class Server:
                 for r in rd.requests:
                     r.t_done = tt
                 completed += len(rd.requests)
-            # launch a round if a slot is free
-            if len(inflight) < self.max_inflight and any(queues.values()):
-                launched = self._round(queues, mode)
-                rounds += 1
-                inflight.append(Round(self.ex.close_round(launched), launched))
-                continue
+            # launch a round if a slot is free (see min_batch / max_wait_s)
+            if nq and len(inflight) < self.max_inflight:
+                go = not inflight or mode == "plain" or nq >= self.min_batch
+                if not go:
+                    oldest = min(q[0].t_arrival for q in queues.values() if q)
+                    go = now() - oldest >= self.max_wait_s
+                if go:
+                    launched = self._round(queues, mode)
+                    nq -= len(launched)
+                    rounds += 1
+                    inflight.append(Round(self.ex.close_round(launched), launched))
+                    continue
             if spin_s > 0:
                 time.sleep(spin_s)
         wall = now()

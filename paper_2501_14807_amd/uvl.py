@@ -78,6 +78,7 @@ SIGNATURES = {
     "uvl_wave_submit": ([_P, _P, _I32, _I32, _P], _I32),
     "uvl_wave_tune": ([_P, _P, _I32, _P], _I32),
     "uvl_wave_tuned_chunks": ([_P, _I64], _I32),
+    "uvl_wave_visited_tiles": ([_P, _P, _P], _I32),
     "uvl_wave_destroy": ([_P], _I32),
 }
 
@@ -430,6 +431,12 @@ class Wave:
     def tune(self, batch: EditBatch, stream=None):
         arr = batch.array()
         _check(_lib().uvl_wave_tune(self.h, arr, len(batch), _stream(stream)), "uvl_wave_tune")
+
+    def visited_tiles(self, stream=None) -> int:
+        """Tiles the last submit visited (synchronous)."""
+        v = ctypes.c_int64()
+        _check(_lib().uvl_wave_visited_tiles(self.h, ctypes.byref(v), _stream(stream)), "uvl_wave_visited_tiles")
+        return int(v.value)
 
     def tuned_chunks(self, texels: int) -> int:
         return int(_lib().uvl_wave_tuned_chunks(self.h, int(texels)))

@@ -241,3 +241,54 @@ def test_wave_culling_boundaries(gpu):
         wave.submit(b, tile_chunks=chunks)
         assert np.array_equal(m.layers[0].numpy(), ref), chunks
     wave.close()
+
+
+def test_wave_depth_culling(gpu):
+    """Tiles culled by the depth test (occluded or facing away) change
+    nothing: screen-covering lassos at biases around zero, where texels of
+    the visible surface sit right at the stored depth, give the plain path's
+    layers; and the depth test does cull (fewer tiles visited than with a
+    depth map that hides nothing)."""
+    import torch
+    from paper_2501_14807_amd.model import Model
+    wl = synth.tiny_workload()
+    scan = synth.scan_workload(n_brush=1, n_lasso=8, n_ops=0, W=1024, n_charts=4, nx=64, ny=32, depth=512)
+    poly = np.array([[-0.95, -0.95], [0.95, -0.95], [0.95, 0.95], [-0.95, 0.95]], np.float32)
+    biases = (1e-2, 1e-4, 0.0, -1e-5, -1e-4)
+    visited = []
+    for w_ in (wl, scan):
+        m = Model.from_workload(w_).build()
+        cams = list(range(0, len(w_.cameras), max(1, len(w_.cameras) // 4)))[:4]
+        maps = {}
+        for ci in cams:     # one map per camera, alive for the whole test
+            maps[ci] = torch.empty((m.depth_h, m.depth_w), dtype=torch.float32, device="cuda")
+            gpu.render_depth(m.mesh, w_.cameras[ci], maps[ci], m.depth_ws)
+        wave = gpu.Wave(64, 64)
+        m.clear_layers()
+        for ci in cams:
+            for k, bias in enumerate(biases):
+                gpu.edit_lasso(m.geom, m.layers[0], w_.cameras[ci], poly, maps[ci], bias, 1 + (3 * ci + k) % 250)
+        ref = m.layers[0].numpy().copy()
+        m.clear_layers()
+        b = gpu.EditBatch()
+        for ci in cams:
+            for k, bias in enumerate(biases):
+                b.lasso(m.geom, m.layers[0], w_.cameras[ci], poly, maps[ci], bias, 1 + (3 * ci + k) % 250)
+        wave.submit(b)
+        assert np.array_equal(m.layers[0].numpy(), ref)
+        # one lasso: the real depth map against one that hides nothing
+        M = w_.cameras[cams[0]]
+        d = maps[cams[0]]
+        b1 = gpu.EditBatch()
+        b1.lasso(m.geom, m.layers[0], M, poly, d, 1e-4, 5)
+        wave.submit(b1)
+        culled = wave.visited_tiles()
+        open_map = torch.full_like(d, 2.0)
+        b2 = gpu.EditBatch()
+        b2.lasso(m.geom, m.layers[0], M, poly, open_map, 1e-4, 5)
+        wave.submit(b2)
+        visited.append((culled, wave.visited_tiles()))
+        wave.close()
+    assert all(c <= o for c, o in visited), visited
+    # the vessel hides its far side from every camera
+    assert visited[0][0] < 0.9 * visited[0][1], visited

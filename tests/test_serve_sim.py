@@ -100,3 +100,21 @@ def test_inflight_limit():
     ex = Counting([1] * 8, wave_fixed_s=500e-6)
     Server(ex, 8, 100, max_inflight=2).run(reqs, "batched")
     assert ex.max_seen <= 2
+
+
+def test_busy_device_gets_larger_rounds():
+    # a large fixed cost per wave: eager rounds (one per free slot) pay it
+    # often, the default policy waits for a batch while a round is in flight
+    # (the simulated device runs on the wall clock, so only the round count
+    # is compared)
+    reqs = _stream(3000, 16, 20000.0, seed=5)
+
+    def run(**kw):
+        ex = SimExecutor([1] * 16, wave_fixed_s=300e-6, wave_edit_s=5e-6)
+        return Server(ex, 16, 100, **kw).run([Request(**{**r.__dict__}) for r in reqs], "batched")
+
+    eager = run(min_batch=1)
+    adaptive = run()
+    assert adaptive.rounds < 0.9 * eager.rounds
+    assert adaptive.failed == 0 and adaptive.refused == 0
+    assert adaptive.n == eager.n == len(reqs)
