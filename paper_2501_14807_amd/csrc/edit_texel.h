@@ -141,13 +141,16 @@ __device__ __forceinline__ int lasso_slab(const PT &P, float yn) {
     return s > kSlabs - 1 ? kSlabs - 1 : s;
 }
 
-// Crossing test of edge e for a point; toggles `inside` when it counts.
-__device__ __forceinline__ void lasso_edge(float ex0, float ey0, float ey1, float esdx, float esdy, float xn,
-                                           float yn, bool &inside) {
-    const bool straddle = (ey0 > yn) != (ey1 > yn);
+// Crossing test of edge e (from vertex k to k+1, stored as above) for a
+// wave: the mask of lanes whose point (xn, yn) has the edge counting -- one
+// end above yn and the other not, and the crossing right of xn.  Each
+// comparison's lane mask is taken directly.
+__device__ __forceinline__ uint64_t lasso_crosses_mask(float ex0, float ey0, float ey1, float esdx, float esdy,
+                                                       float xn, float yn) {
+    const uint64_t a = __builtin_amdgcn_ballot_w64(ey0 > yn), b = __builtin_amdgcn_ballot_w64(ey1 > yn);
     const float lhs = (xn - ex0) * esdy;
     const float rhs = esdx * (yn - ey0);
-    inside ^= straddle && (lhs < rhs);
+    return (a ^ b) & __builtin_amdgcn_ballot_w64(lhs < rhs);
 }
 
 // Wave-wide min / max of a uint32 (every lane of the wave must be active):
@@ -221,6 +224,9 @@ __device__ __forceinline__ void lasso_quad_index(const PT &P, const float4 &X, c
         const float wxmin = wave_min_f32(xmin);
         uint64_t m = 0;
         for (unsigned s = wmin; s <= wmax; ++s) m |= P.slab_edges[s];
+        // crossing parities as wave-wide lane masks (one bit per lane per
+        // texel slot), toggled with scalar XORs of the per-edge ballots
+        uint64_t par[4] = {0, 0, 0, 0};
         while (m) {
             const int e = __builtin_ctzll(m);
             m &= m - 1;
@@ -228,8 +234,11 @@ __device__ __forceinline__ void lasso_quad_index(const PT &P, const float4 &X, c
             const float esdx = P.edge[e].sdx, esdy = P.edge[e].sdy, exmax = P.edge[e].xmax;
             if (exmax < wxmin) continue;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) lasso_edge(ex0, ey0, ey1, esdx, esdy, xn[k], yn[k], inside[k]);
+            for (int k = 0; k < 4; ++k) par[k] ^= lasso_crosses_mask(ex0, ey0, ey1, esdx, esdy, xn[k], yn[k]);
         }
+        const int lane = __lane_id();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) inside[k] = (par[k] >> lane) & 1;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
