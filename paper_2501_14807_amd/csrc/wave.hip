@@ -311,17 +311,23 @@ __global__ __launch_bounds__(kBlock) void k_wave(char *__restrict__ ws, const ui
                 Y = make_float4(ys[0], ys[1], ys[2], ys[3]);
                 Z = make_float4(zs[0], zs[1], zs[2], zs[3]);
             }
+            // live edits from the last to the first: a texel takes the
+            // label of the first edit (in this order) that selects it, i.e.
+            // of its last selecting edit, and a wave stops once each of its
+            // texels is taken or uncovered (NaN position)
             uint32_t val[4] = {0, 0, 0, 0};
             bool wr[4] = {false, false, false, false};
-            for (int g = 0; g < groups; ++g) {
+            const bool cov[4] = {X.x == X.x, X.y == X.y, X.z == X.z, X.w == X.w};
+            bool open = true;
+            for (int g = groups - 1; g >= 0 && open; --g) {
                 uint64_t lm = cull ? tm[g] : ~0ull;
                 const int base = g * 64;
                 const int lim = S.ne - base < 64 ? S.ne - base : 64;
                 if (lim < 64) lm &= (1ull << lim) - 1;
                 while (lm) {
-                    const int e = base + __builtin_ctzll(lm);
-                    lm &= lm - 1;
-                    const UVL_CONST WaveEdit &E = edits[S.e0 + e];
+                    const int b = 63 - __builtin_clzll(lm);
+                    lm &= ~(1ull << b);
+                    const UVL_CONST WaveEdit &E = edits[S.e0 + base + b];
                     bool sel[4];
                     if (E.kind == UVL_EDIT_BRUSH) {
                         const BrushParams B{E.cx, E.cy, E.cz, E.r2};
@@ -332,10 +338,16 @@ __global__ __launch_bounds__(kBlock) void k_wave(char *__restrict__ ws, const ui
                     } else {
                         lasso_quad(lassos[E.lasso], E.depth, X, Y, Z, sel);
                     }
+                    bool pending = false;
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        val[k] = sel[k] ? E.label : val[k];
+                        val[k] = sel[k] && !wr[k] ? E.label : val[k];
                         wr[k] = wr[k] || sel[k];
+                        pending = pending || (cov[k] && !wr[k]);
+                    }
+                    if (__builtin_amdgcn_ballot_w64(pending) == 0) {
+                        open = false;
+                        break;
                     }
                 }
             }
