@@ -49,9 +49,9 @@ def parse():
     p.add_argument("--cpu-edits", type=int, default=200, help="edits in the oracle's timed sample")
     p.add_argument("--batch-models", type=int, default=256,
                    help="models in the batched-wave comparison (0: skip it)")
-    p.add_argument("--serve-models", type=int, default=8,
+    p.add_argument("--serve-models", type=int, default=32,
                    help="small + scan-scale models each in the serving comparison (0: skip it)")
-    p.add_argument("--serve-requests", type=int, default=4000)
+    p.add_argument("--serve-requests", type=int, default=20000)
     p.add_argument("--serve-slo-ms", type=float, default=20.0)
     return p.parse_args()
 
@@ -239,6 +239,9 @@ def bench_serving(n_each, n_requests, slo_ms, torch, uvl):
                 m.clear_layers()
             ex = GpuExecutor(models, cams, max_wave_edits=8192)
             srv = Server(ex, len(models), 200 << 30)
+            ex.models_resident = srv.resident
+            ex.prerender()
+            torch.cuda.synchronize()
             reqs = [Request(i, d["t"], d["model"], d["kind"], edit=d.get("edit"), op=d.get("op"),
                             layer=d.get("layer", 0)) for i, d in enumerate(stream)]
             st = srv.run(reqs, mode)

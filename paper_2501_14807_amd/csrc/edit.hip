@@ -184,6 +184,8 @@ int32_t check_edit(const uvl_geom *g, const uvl_layer *l, uint32_t label) {
 
 // Host-side preparation of a lasso's kernel parameters; also used by the
 // batched wave path.  Returns false for an invalid polygon.
+static_assert(sizeof(LassoParams) <= 3584, "lasso parameters travel as a kernel argument");
+
 bool make_lasso_params(const float view_proj[16], const float *poly, int32_t n, int32_t dw, int32_t dh,
                        float bias, LassoParams &p) {
     if (n < 3 || n > kMaxPoly || !poly || !view_proj || dw < 1 || dh < 1 || !std::isfinite(bias)) return false;
@@ -199,7 +201,7 @@ bool make_lasso_params(const float view_proj[16], const float *poly, int32_t n, 
         if (!std::isfinite(x0) || !std::isfinite(y0)) return false;
         const float dx = x1 - x0, dy = y1 - y0;
         const bool up = y1 > y0;
-        p.edge[k] = LassoEdge{x0, y0, y1, up ? dx : -dx, up ? dy : -dy, fmaxf(x0, x1), 0.0f, 0.0f};
+        p.edge[k] = LassoEdge{x0, y0, y1, up ? dx : -dx, up ? dy : -dy, fmaxf(x0, x1), x1, 0.0f};
         ylo = fminf(ylo, y0);
         yhi = fmaxf(yhi, y0);
         xhi = fmaxf(xhi, x0);
@@ -262,6 +264,13 @@ bool make_lasso_params(const float view_proj[16], const float *poly, int32_t n, 
         p.cull.slab_x0[s] = sx0;
         p.cull.slab_x1[s] = sx1;
     }
+    float xabs = 0.0f;
+    for (int k = 0; k < kMaxPoly; ++k) {
+        const LassoEdge &E = p.edge[k];
+        p.cull.slope[k] = (k < n && E.sdy != 0.0f) ? (double)E.sdx / (double)E.sdy : 0.0;
+        if (k < n) xabs = fmaxf(xabs, fabsf(E.x0));
+    }
+    p.cull.xabs = xabs;
     return true;
 }
 

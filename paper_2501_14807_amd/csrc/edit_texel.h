@@ -45,7 +45,7 @@ constexpr int kSlabs = 32;
 // One polygon edge, padded to 32 bytes so that a wave loads it with a single
 // scalar load.
 struct alignas(32) LassoEdge {
-    float x0, y0, y1, sdx, sdy, xmax, pad0, pad1;   // xmax = max(x0, x1)
+    float x0, y0, y1, sdx, sdy, xmax, x1, pad;   // xmax = max(x0, x1)
 };
 
 // Tile-culling data of a lasso, fp64 (filled on the host): four linear
@@ -62,6 +62,10 @@ struct LassoCull {
     // [slab_x0[s], slab_x1[s]] (min / max over the edges of slab_edges[s];
     // empty slab: x0 = +inf, x1 = -inf)
     float slab_x0[kSlabs], slab_x1[kSlabs];
+    // per edge: dx/dy of its stored direction (0 for horizontal edges), and
+    // the largest |x| of a vertex, for the rectangle classification
+    double slope[kMaxPoly];
+    float xabs;
 };
 
 struct LassoParams {
@@ -196,11 +200,13 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
 // inside the polygon then get their NDC z test; pix[k] is the depth-map
 // index still to be tested (d[k] <= depth[pix[k]] + bias), or -1 if the
 // texel is already rejected.  The depth reads are left to the caller, so
-// that it can issue many of them before waiting.
+// that it can issue many of them before waiting.  all_inside: the caller
+// has shown (lasso_rect_class) that every texel here lies inside the polygon
+// by the fp32 test, which is then skipped.
 // Must be called by all 64 lanes.
 template <class PT>
 __device__ __forceinline__ void lasso_quad_index(const PT &P, const float4 &X, const float4 &Y, const float4 &Z,
-                                                 int pix[4], float d[4]) {
+                                                 int pix[4], float d[4], bool all_inside = false) {
     const float xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w}, zs[4] = {Z.x, Z.y, Z.z, Z.w};
     float xn[4], yn[4], cz[4], cw[4];
     bool cand[4], inside[4];
@@ -219,8 +225,11 @@ __device__ __forceinline__ void lasso_quad_index(const PT &P, const float4 &X, c
             xmin = fminf(xmin, xn[k]);
         }
     }
-    const unsigned wmin = wave_min_u32(smin), wmax = wave_max_u32(smax);
-    if (wmin <= wmax) {
+    const unsigned wmin = all_inside ? 1u : wave_min_u32(smin), wmax = all_inside ? 0u : wave_max_u32(smax);
+    if (all_inside) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) inside[k] = true;
+    } else if (wmin <= wmax) {
         const float wxmin = wave_min_f32(xmin);
         uint64_t m = 0;
         for (unsigned s = wmin; s <= wmax; ++s) m |= P.slab_edges[s];
@@ -251,18 +260,18 @@ __device__ __forceinline__ void lasso_quad_index(const PT &P, const float4 &X, c
 // The whole lasso predicate for 4 texels per lane (all 64 lanes).
 template <class PT>
 __device__ __forceinline__ void lasso_quad(const PT &P, const float *__restrict__ depth, const float4 &X,
-                                           const float4 &Y, const float4 &Z, bool sel[4]) {
+                                           const float4 &Y, const float4 &Z, bool sel[4], bool all_inside = false) {
     int pix[4];
     float d[4];
-    lasso_quad_index(P, X, Y, Z, pix, d);
+    lasso_quad_index(P, X, Y, Z, pix, d, all_inside);
 #pragma unroll
     for (int k = 0; k < 4; ++k) sel[k] = pix[k] >= 0 && lasso_depth_pass(P, d[k], depth[pix[k]]);
 }
 
 // ---------------------------------------------------------------------------
 // Conservative tile tests.  box = {min x, min y, min z, max x, max y, max z}
-// of the covered positions of a tile (min > max: no covered texel).  A test
-// returns true only if no texel of the tile can be selected by the fp32
+// of the covered positions of a tile (min > max: no covered texel).  A tile
+// is reported culled only if no texel of it can be selected by the fp32
 // predicate above, so skipping culled tiles leaves every result unchanged.
 
 // Brush: the fp32 squared distance of the box to the centre, D2, is within
@@ -334,8 +343,52 @@ __device__ __forceinline__ double row_abs_max(const PT &row, const float box[6])
 // kDepthCullPixels pixels.
 constexpr int kDepthCullPixels = 1024;
 
+// Results of the lasso tile tests.
+enum LassoTile { kTileCulled = 0, kTileLive = 1, kTileInside = 2 };
+
+// Rectangle R = [rx0, rx1] x [ry0, ry1] that holds the fp32 NDC position of
+// every texel of a tile, against the polygon.  The fp32 crossing test of
+// edge e at a point q uses the line through (x0, y0) with the stored
+// direction (sdx, sdy), over the half-open y-range of the edge; its side test
+// is exact when q is at horizontal distance >= m from that line, m > 4.02 u
+// (1 + X) with X the largest |x| of a vertex (the two rounded products
+// differ from the exact ones by 2.01 u of their sizes, and |xn| <= 1).  If
+// no edge's piece over R's y-range comes within m of R (fp64 here, error
+// far below m), no edge crosses R and the vertices lie outside it, so the
+// even-odd parity is the same at every point of R, and every texel's fp32
+// test gives that parity: the parity of R's centre (fp64).  Horizontal
+// edges never count, but the parity changes across them (the straddle
+// ranges of their neighbours end there), so they take part in the "near R"
+// test as the segment between their vertices.  Returns kTileCulled (all
+// outside), kTileInside (all inside) or kTileLive.
 template <class PT>
-__device__ __forceinline__ bool lasso_culls_more(const PT &P, const float box[6], const float *depth, double wmin) {
+__device__ __forceinline__ int lasso_rect_class(const PT &P, double rx0, double rx1, double ry0, double ry1) {
+    const double m = 1e-5 * (2.0 + (double)P.cull.xabs);
+    const double a0 = rx0 - m, a1 = rx1 + m, b0 = ry0 - m, b1 = ry1 + m;
+    const double cx = 0.5 * (rx0 + rx1), cy = 0.5 * (ry0 + ry1);
+    bool odd = false;
+    for (int k = 0; k < P.n; ++k) {
+        const double ex0 = P.edge[k].x0, ey0 = P.edge[k].y0, ey1 = P.edge[k].y1;
+        if (ey0 == ey1) {
+            // horizontal: never straddles, but bounds the inside
+            const double ex1 = P.edge[k].x1;
+            if (ey0 >= b0 && ey0 <= b1 && fmin(ex0, ex1) <= a1 && fmax(ex0, ex1) >= a0) return kTileLive;
+            continue;
+        }
+        const double slope = P.cull.slope[k];
+        const double ya = fmax(fmin(ey0, ey1), b0), yb = fmin(fmax(ey0, ey1), b1);
+        if (ya <= yb) {
+            const double xa = ex0 + slope * (ya - ey0), xb = ex0 + slope * (yb - ey0);
+            if (fmin(xa, xb) <= a1 && fmax(xa, xb) >= a0) return kTileLive;   // the edge comes near R
+        }
+        const double sdx = P.edge[k].sdx, sdy = P.edge[k].sdy;
+        if (((ey0 > cy) != (ey1 > cy)) && ((cx - ex0) * sdy < sdx * (cy - ey0))) odd = !odd;
+    }
+    return odd ? kTileInside : kTileCulled;
+}
+
+template <class PT>
+__device__ __forceinline__ int lasso_culls_more(const PT &P, const float box[6], const float *depth, double wmin) {
     double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY, zmin = INFINITY;
 #pragma unroll 1
     for (int k = 0; k < 8; ++k) {
@@ -346,7 +399,7 @@ __device__ __forceinline__ bool lasso_culls_more(const PT &P, const float box[6]
 #pragma unroll
         for (int r = 0; r < 4; ++r)
             c[r] = (double)P.M[4 * r] * x + (double)P.M[4 * r + 1] * y + (double)P.M[4 * r + 2] * z + (double)P.M[4 * r + 3];
-        if (!(c[3] > 0.0)) return false;
+        if (!(c[3] > 0.0)) return kTileLive;
         const double xn = c[0] / c[3], yn = c[1] / c[3], zn = c[2] / c[3];
         x0 = fmin(x0, xn);
         x1 = fmax(x1, xn);
@@ -366,13 +419,15 @@ __device__ __forceinline__ bool lasso_culls_more(const PT &P, const float box[6]
             const double a = (double)P.cull.slab_x0[s] - 1e-3, b = (double)P.cull.slab_x1[s];
             hit = a <= x1 + eps && b >= x0 - eps;
         }
-        if (!hit) return true;
+        if (!hit) return kTileCulled;
     }
-    if (!depth) return false;
+    const int cls = lasso_rect_class(P, x0 - eps, x1 + eps, y0 - eps, y1 + eps);
+    if (cls == kTileCulled) return kTileCulled;
+    if (!depth) return cls;
     const double u = 0x1p-24;
     const double az = row_abs_max(P.cull.az, box), aw = row_abs_max(P.cull.aw, box);
     const double dcz = 3.01 * u * az, dcw = 3.01 * u * aw;
-    if (!(dcw < 0.5 * wmin)) return false;
+    if (!(dcw < 0.5 * wmin)) return cls;
     const double err_z = (dcz + 2.0 * dcw) / (wmin - dcw) + 2.0 * u + 1e-12;
     const double dlo = 0.5 * (zmin - err_z) + 0.5 - 2.0 * u;   // smallest fp32 window depth of a texel
     const int dw = P.dw, dh = P.dh;
@@ -382,35 +437,48 @@ __device__ __forceinline__ bool lasso_culls_more(const PT &P, const float box[6]
     iy0 = iy0 < 0 ? 0 : iy0;
     ix1 = ix1 > dw - 1 ? dw - 1 : ix1;
     iy1 = iy1 > dh - 1 ? dh - 1 : iy1;
-    if (ix0 > ix1 || iy0 > iy1) return false;
-    if ((int64_t)(ix1 - ix0 + 1) * (iy1 - iy0 + 1) > kDepthCullPixels) return false;
+    if (ix0 > ix1 || iy0 > iy1) return cls;
+    if ((int64_t)(ix1 - ix0 + 1) * (iy1 - iy0 + 1) > kDepthCullPixels) return cls;
     // fl(D + bias) <= (D + bias) + u |D + bias|; culled iff dlo exceeds that
-    // for every pixel of the rectangle
+    // for every pixel of the rectangle.  The pixels are read 16 at a time
+    // (independent loads in flight together), each batch tested on its max.
     const double bias = P.bias;
-    for (int iy = iy0; iy <= iy1; ++iy)
-        for (int ix = ix0; ix <= ix1; ++ix) {
-            const double v = (double)depth[(int64_t)iy * dw + ix] + bias;
-            if (!(dlo > v + u * fabs(v) + 1e-12)) return false;
+    const int rw = ix1 - ix0 + 1, npix = rw * (iy1 - iy0 + 1);
+    const float inv_rw = 1.0f / (float)rw;   // (p + 0.5) / rw is >= 0.5 / rw from an integer: exact floor
+    for (int p0 = 0; p0 < npix; p0 += 16) {
+        float dmax = -INFINITY;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int p = p0 + i < npix ? p0 + i : npix - 1;
+            const int r = (int)(((float)p + 0.5f) * inv_rw);
+            const float v = depth[(int64_t)(iy0 + r) * dw + ix0 + (p - r * rw)];
+            dmax = fmaxf(dmax, v);
         }
-    return true;
+        const double v = (double)dmax + bias;
+        if (!(dlo > v + u * fabs(v) + 1e-12)) return cls;
+    }
+    return kTileCulled;
 }
 
+// Lasso tile test: kTileCulled if no texel of the box can be selected,
+// kTileInside if every texel that passes the projective tests is inside the
+// polygon, kTileLive otherwise.
 template <class PT>
-__device__ __forceinline__ bool lasso_culls(const PT &P, const float box[6], const float *depth = nullptr) {
+__device__ __forceinline__ int lasso_tile(const PT &P, const float box[6], const float *depth = nullptr) {
     const auto &C = P.cull;
-    if (!(box[0] <= box[3] && box[1] <= box[4] && box[2] <= box[5])) return true;
+    if (!(box[0] <= box[3] && box[1] <= box[4] && box[2] <= box[5])) return kTileCulled;
     double wneg[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) wneg[j] = -C.wrow[j];
     const double wmin = -box_max(wneg, box);
     const double smax = fmax(row_abs_max(C.ax, box), row_abs_max(C.ay, box)) + row_abs_max(C.aw, box);
-    if (!(wmin >= 1e-3 * smax) || !(wmin > 0.0)) return false;
+    if (!(wmin >= 1e-3 * smax) || !(wmin > 0.0)) return kTileLive;
 #pragma unroll 1
     for (int k = 0; k < 4; ++k) {
         double a[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) a[j] = C.plane[k][j];
-        if (box_max(a, box) < 0.0) return true;
+        if (box_max(a, box) < 0.0) return kTileCulled;
     }
     return lasso_culls_more(P, box, depth, wmin);
 }

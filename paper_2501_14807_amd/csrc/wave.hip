@@ -17,9 +17,11 @@
 // In a tile, lane t covers row t/8 and columns 4(t%8)..+3.
 //
 // Tile culling (when the geometry image has tile bounds): a first kernel
-// gives every tile one lane; the lane tests the stream's edits against the
-// tile's bounds (exact conservative tests, edit_texel.h) and stores, per
-// group of 64 edits, the mask of edits that may select something there.
+// gives every block of 8 x 8 tiles one wave and every tile one lane; each
+// edit is tested against the block's bounds and, if it survives, against
+// each tile's bounds (exact conservative tests, edit_texel.h); a lane stores,
+// per group of 64 edits, the mask of edits that may select something in its
+// tile.
 // Tiles with a live edit are appended to the stream's live list (one atomic
 // per wave).  A one-workgroup kernel then turns the per-stream live counts
 // into item ranges, and the wave kernel visits only live tiles, evaluating
@@ -59,7 +61,7 @@ struct WaveStream {
     const float *box;   // per-tile position bounds, or null (no culling)
     void *layer;
     int64_t mask0;      // first cull-mask word of this stream (running offset)
-    int64_t cwave0;     // first cull wave of this stream (64 tiles per wave)
+    int64_t cwave0;     // first cull wave of this stream (one per block of 8 x 8 tiles)
     int64_t list0;      // first live-list entry of this stream
     int32_t W, H;       // atlas size
     int32_t tiles_x, ntiles;
@@ -105,9 +107,10 @@ void descriptor_offsets(int64_t ns, int64_t n, int64_t nl, WaveHeader &h, size_t
 }
 
 // Workspace layout: descriptor (at most `masks` bytes) | cull masks (uint64
-// per word) | live lists (uint32 tile index per entry, as many as words)
+// per word) | inside masks (uint64 per word: lassos whose polygon contains
+// the whole tile) | live lists (uint32 tile index per entry, as many as words)
 struct Layout {
-    size_t masks, live, total;
+    size_t masks, imasks, live, total;
     int64_t max_words;
 };
 
@@ -118,7 +121,8 @@ Layout layout(int32_t max_edits, int32_t max_lassos, int64_t max_words) {
     descriptor_offsets(max_edits, max_edits, max_lassos > 0 ? max_lassos : 0, h, end);
     L.masks = al256(end);
     const size_t words = (size_t)(max_words > 0 ? max_words : 1);
-    L.live = L.masks + al256(sizeof(uint64_t) * words);
+    L.imasks = L.masks + al256(sizeof(uint64_t) * words);
+    L.live = L.imasks + al256(sizeof(uint64_t) * words);
     L.total = L.live + al256(sizeof(uint32_t) * words);
     L.max_words = max_words;
     return L;
@@ -157,12 +161,16 @@ __device__ __forceinline__ int last_le(int n, int64_t v, F key) {
     return lo;
 }
 
-// Cull pass: one lane per tile of the culling streams, grid-striding over
-// waves of 64 tiles.  The lane's masks (one word per group of 64 edits) go to
-// masks[mask0 + tile * groups + g]; the wave's tiles with a live edit are
-// appended to the stream's live list.
+// Cull pass: one wave per block of 8 x 8 tiles of a culling stream (lane l:
+// tile (l % 8, l / 8) of the block), grid-striding over the blocks.  Each
+// edit is first tested against the block's bounds (the union of its tiles'
+// bounds, contains every texel of the block); only edits that survive that
+// are tested per tile.  A lane's masks (one word per group of 64 edits) go
+// to masks[mask0 + tile * groups + g] -- with one group, only for live tiles,
+// the only ones the wave kernel reads -- and the wave's tiles with a live
+// edit are appended to the stream's live list.
 __global__ __launch_bounds__(kBlock) void k_wave_cull(char *__restrict__ ws, uint64_t *__restrict__ masks,
-                                                       uint32_t *__restrict__ live) {
+                                                       uint64_t *__restrict__ imasks, uint32_t *__restrict__ live) {
     const UVL_CONST WaveHeader *hdr = (const UVL_CONST WaveHeader *)ws;
     const UVL_CONST WaveStream *streams = (const UVL_CONST WaveStream *)(ws + hdr->off_streams);
     const UVL_CONST WaveEdit *edits = (const UVL_CONST WaveEdit *)(ws + hdr->off_edits);
@@ -179,23 +187,42 @@ __global__ __launch_bounds__(kBlock) void k_wave_cull(char *__restrict__ ws, uin
         const int si = last_le(nstreams, cw, [&](int k) { return streams[k].cwave0; });
         const UVL_CONST WaveStream &S = streams[si];
         const int groups = (S.ne + 63) >> 6;
-        const int64_t ti = (cw - S.cwave0) * 64 + lane;
-        const bool in = ti < S.ntiles;
+        const int tiles_y = S.ntiles / S.tiles_x;
+        const int64_t blk = cw - S.cwave0;
+        const int nbx = (S.tiles_x + 7) >> 3;
+        const int tx = (int)(blk % nbx) * 8 + (lane & 7), ty = (int)(blk / nbx) * 8 + (lane >> 3);
+        const bool in = tx < S.tiles_x && ty < tiles_y;
+        const int64_t ti = (int64_t)ty * S.tiles_x + tx;
         float box[6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) box[q] = in ? S.box[6 * ti + q] : 1.0f;
-        if (!in) box[0] = 2.0f;   // empty box: min > max
+        for (int q = 0; q < 6; ++q) box[q] = in ? S.box[6 * ti + q] : (q < 3 ? INFINITY : -INFINITY);
+        float bb[6];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            bb[q] = wave_min_f32(box[q]);
+            bb[q + 3] = -wave_min_f32(-box[q + 3]);
+        }
         bool any = false;
         for (int g = 0; g < groups; ++g) {
-            uint64_t m = 0;
+            uint64_t m = 0, im = 0;
             const int lim = S.ne - 64 * g < 64 ? S.ne - 64 * g : 64;
             for (int k = 0; k < lim; ++k) {
                 const UVL_CONST WaveEdit &E = edits[S.e0 + 64 * g + k];
-                const bool alive = E.kind == UVL_EDIT_BRUSH ? !brush_culls(BrushParams{E.cx, E.cy, E.cz, E.r2}, box)
-                                                            : !lasso_culls(lassos[E.lasso], box, E.depth);
-                m |= (uint64_t)alive << k;
+                const bool brush = E.kind == UVL_EDIT_BRUSH;
+                const BrushParams B{E.cx, E.cy, E.cz, E.r2};
+                // block test (the same for every lane), then the lane's tile
+                const bool block_dead = brush ? brush_culls(B, bb)
+                                              : lasso_tile(lassos[E.lasso], bb, E.depth) == kTileCulled;
+                if (block_dead) continue;
+                const int cls = brush ? (brush_culls(B, box) ? kTileCulled : kTileLive)
+                                      : lasso_tile(lassos[E.lasso], box, E.depth);
+                m |= (uint64_t)(cls != kTileCulled) << k;
+                im |= (uint64_t)(cls == kTileInside) << k;
             }
-            if (in) masks[S.mask0 + ti * groups + g] = m;
+            if (in && (groups > 1 || m != 0)) {
+                masks[S.mask0 + ti * groups + g] = m;
+                imasks[S.mask0 + ti * groups + g] = im;
+            }
             any = any || m != 0;
         }
         const uint64_t b = __ballot(any && in);
@@ -250,6 +277,7 @@ __global__ __launch_bounds__(kBlock) void k_wave_plan(char *__restrict__ ws) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_wave(char *__restrict__ ws, const uint64_t *__restrict__ masks_in,
+                                                  const uint64_t *__restrict__ imasks_in,
                                                   const uint32_t *__restrict__ live_in) {
     // read-only descriptor, masks and live lists viewed in the constant
     // address space: uniform reads become scalar loads
@@ -261,6 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_wave(char *__restrict__ ws, const ui
     const UVL_CONST uint32_t *live_n = (const UVL_CONST uint32_t *)(ws + chdr->off_live_n);
     const UVL_CONST int64_t *item0 = (const UVL_CONST int64_t *)(ws + chdr->off_item0);
     const UVL_CONST uint64_t *masks = (const UVL_CONST uint64_t *)masks_in;
+    const UVL_CONST uint64_t *imasks = (const UVL_CONST uint64_t *)imasks_in;
     const UVL_CONST uint32_t *live = (const UVL_CONST uint32_t *)live_in;
     __shared__ long long s_item;
     const int32_t nstreams = chdr->nstreams;
@@ -285,6 +314,7 @@ __global__ __launch_bounds__(kBlock) void k_wave(char *__restrict__ ws, const ui
             if (first + c >= ntiles) break;
             const int64_t ti = cull ? (int64_t)live[S.list0 + first + c] : first + c;
             const UVL_CONST uint64_t *tm = masks + (cull ? S.mask0 + ti * groups : 0);
+            const UVL_CONST uint64_t *tim = imasks + (cull ? S.mask0 + ti * groups : 0);
             const int tx = (int)(ti % S.tiles_x), ty = (int)(ti / S.tiles_x);
             // uniform over the workgroup: whole tile inside, rows 16-byte aligned
             const bool full = (tx + 1) * UVL_TILE_SIDE <= W && (ty + 1) * UVL_TILE_SIDE <= H && (W & 3) == 0;
@@ -321,6 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_wave(char *__restrict__ ws, const ui
             bool open = true;
             for (int g = groups - 1; g >= 0 && open; --g) {
                 uint64_t lm = cull ? tm[g] : ~0ull;
+                const uint64_t ins = cull ? tim[g] : 0ull;   // lassos containing the whole tile
                 const int base = g * 64;
                 const int lim = S.ne - base < 64 ? S.ne - base : 64;
                 if (lim < 64) lm &= (1ull << lim) - 1;
@@ -336,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_wave(char *__restrict__ ws, const ui
                         sel[2] = brush_texel(B, X.z, Y.z, Z.z);
                         sel[3] = brush_texel(B, X.w, Y.w, Z.w);
                     } else {
-                        lasso_quad(lassos[E.lasso], E.depth, X, Y, Z, sel);
+                        lasso_quad(lassos[E.lasso], E.depth, X, Y, Z, sel, ((ins >> b) & 1) != 0);
                     }
                     bool pending = false;
 #pragma unroll
@@ -418,13 +449,14 @@ extern "C" int32_t uvl_wave_create(int32_t max_edits, int32_t max_lassos, int64_
         hipGraph_t g = nullptr;
         WaveHeader *hdr = reinterpret_cast<WaveHeader *>(w->ws);
         uint64_t *masks = reinterpret_cast<uint64_t *>(w->ws + lay.masks);
+        uint64_t *imasks = reinterpret_cast<uint64_t *>(w->ws + lay.imasks);
         uint32_t *live = reinterpret_cast<uint32_t *>(w->ws + lay.live);
         ok = hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
             hipLaunchKernelGGL(k_wave_reset, dim3(1), dim3(64), 0, w->cap, hdr);
-            hipLaunchKernelGGL(k_wave_cull, dim3(kWaveGrid), dim3(kBlock), 0, w->cap, w->ws, masks, live);
+            hipLaunchKernelGGL(k_wave_cull, dim3(kWaveGrid), dim3(kBlock), 0, w->cap, w->ws, masks, imasks, live);
             hipLaunchKernelGGL(k_wave_plan, dim3(1), dim3(kBlock), 0, w->cap, w->ws);
-            hipLaunchKernelGGL(k_wave, dim3(kWaveGrid), dim3(kBlock), 0, w->cap, w->ws, masks, live);
+            hipLaunchKernelGGL(k_wave, dim3(kWaveGrid), dim3(kBlock), 0, w->cap, w->ws, masks, imasks, live);
             ok = hipStreamEndCapture(w->cap, &g) == hipSuccess && g;
         }
         ok = ok && hipGraphInstantiate(&w->exec, g, nullptr, nullptr, 0) == hipSuccess;
@@ -535,7 +567,7 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
         s.cwave0 = cwaves;
         if (s.cull) {
             words += nw;
-            cwaves += ceil_div(s.ntiles, 64);
+            cwaves += ceil_div(s.tiles_x, 8) * ceil_div(s.ntiles / s.tiles_x, 8);   // blocks of 8 x 8 tiles
         }
         live_n[k] = 0;
         s.e0 = ei;

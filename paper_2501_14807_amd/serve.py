@@ -153,6 +153,7 @@ class GpuExecutor(Executor):
         from . import uvl
         self.torch, self.uvl = torch, uvl
         self.models = models                  # list of Model
+        self.models_resident = set(range(len(models)))
         self.cameras = cameras                # per model: list of view-proj matrices
         self.depth: Dict[tuple, object] = {}  # (model, camera) -> resident depth map
         self.wave = uvl.Wave(max_wave_edits, max_wave_edits)
@@ -168,6 +169,14 @@ class GpuExecutor(Executor):
     def footprint(self, model):
         m = self.models[model]
         return m.geom.nbytes() + sum(l.data.numel() * l.data.element_size() for l in m.layers)
+
+    def prerender(self):
+        """Render every (model, camera) depth map now (the cameras are known
+        up front), so that no request pays for a first render."""
+        for mi, cams in enumerate(self.cameras):
+            if mi in self.models_resident:
+                for ci in range(len(cams)):
+                    self._depth(mi, ci)
 
     def _depth(self, model, cam):
         key = (model, cam)

@@ -292,3 +292,44 @@ def test_wave_depth_culling(gpu):
     assert all(c <= o for c, o in visited), visited
     # the vessel hides its far side from every camera
     assert visited[0][0] < 0.9 * visited[0][1], visited
+
+
+def test_wave_adversarial_polygons(gpu):
+    """Self-intersecting, degenerate, tiny, screen-covering and off-screen
+    polygons, and grid-snapped zigzags: the wave (whose cull pass classifies
+    tiles as outside / inside / crossed by the polygon) gives the plain
+    path's layers."""
+    import torch
+    from paper_2501_14807_amd.model import Model
+    from test_gpu_parity import _adversarial_polygons
+    wl = synth.tiny_workload()
+    m = Model.from_workload(wl).build()
+    polys = _adversarial_polygons()
+    rng = np.random.default_rng(33)
+    polys += [synth.star_polygon(rng, int(n)) for n in rng.integers(3, 65, 12)]
+    for ci in (0, 5, 11):
+        M = wl.cameras[ci]
+        d = torch.empty((256, 256), dtype=torch.float32, device="cuda")
+        gpu.render_depth(m.mesh, M, d, m.depth_ws)
+        m.clear_layers()
+        for k, P in enumerate(polys):
+            gpu.edit_lasso(m.geom, m.layers[0], M, P, d, 1e-4, 1 + k % 250)
+        ref = m.layers[0].numpy().copy()
+        m.clear_layers()
+        b = gpu.EditBatch()
+        for k, P in enumerate(polys):
+            b.lasso(m.geom, m.layers[0], M, P, d, 1e-4, 1 + k % 250)
+        wave = gpu.Wave(len(b), len(b))
+        wave.submit(b)
+        assert np.array_equal(m.layers[0].numpy(), ref), ci
+        # one at a time too (no later edit hides a wrong tile)
+        for k, P in enumerate(polys):
+            m.clear_layers()
+            gpu.edit_lasso(m.geom, m.layers[0], M, P, d, 1e-4, 7)
+            one = m.layers[0].numpy().copy()
+            m.clear_layers()
+            b1 = gpu.EditBatch()
+            b1.lasso(m.geom, m.layers[0], M, P, d, 1e-4, 7)
+            wave.submit(b1)
+            assert np.array_equal(m.layers[0].numpy(), one), (ci, k)
+        wave.close()
