@@ -31,6 +31,7 @@ drives the same scheduler in tests without a GPU.
 
 from __future__ import annotations
 
+import gc
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -298,7 +299,19 @@ class Server:
         self.used_bytes = used
 
     def run(self, requests: Sequence[Request], mode: str = "batched", spin_s: float = 20e-6) -> Stats:
+        """Serve `requests` (arrival times in seconds from now).  Python's
+        cyclic garbage collector is paused meanwhile: its pauses land in the
+        latency tail."""
         assert mode in ("batched", "plain")
+        was = gc.isenabled()
+        gc.disable()
+        try:
+            return self._run(requests, mode, spin_s)
+        finally:
+            if was:
+                gc.enable()
+
+    def _run(self, requests, mode, spin_s) -> Stats:
         reqs = sorted(requests, key=lambda r: (r.t_arrival, r.rid))
         queues: Dict[int, deque] = {}
         inflight: deque = deque()
