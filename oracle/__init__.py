@@ -64,6 +64,10 @@ def lib():
         L.orc_layer_op.argtypes = [i32, P, i32, P, i32, P, i32, i64, u32, u32, u32, P]
         L.orc_layer_op.restype = i32
         L.orc_area.argtypes = [P, P, P, i32, i64, P, i32]
+        L.orc_outline.argtypes = [P, i32, i32, i32, P]
+        L.orc_outline.restype = i64
+        L.orc_pad.argtypes = [P, P, i32, i32, i32, u32, P, i32]
+        L.orc_pad.restype = i64
         L.orc_area.restype = i32
         _lib = L
     return _lib
@@ -184,3 +188,23 @@ def area(geom: GeomImage, layer: np.ndarray, nbins=None) -> np.ndarray:
     if rc != 0:
         raise ValueError("orc_area failed")
     return out
+
+
+def outline(tri_id: np.ndarray, W: int, H: int, k: int = 1) -> np.ndarray:
+    """Outline mask of texture padding (uint8 [H*W]): uncovered texels within
+    Chebyshev distance k of a covered one (§4.3.2)."""
+    tri = _c(tri_id, np.int32).reshape(-1)
+    assert tri.size == W * H
+    out = np.zeros(W * H, np.uint8)
+    lib().orc_outline(_p(tri), int(W), int(H), int(k), _p(out))
+    return out
+
+
+def pad(outline_mask: np.ndarray, edited: np.ndarray, W: int, H: int, k: int, layer: np.ndarray,
+        label: int) -> int:
+    """Texture padding after one edit, in place: outline texels within
+    Chebyshev distance k of an edited texel take `label` (§4.3.2)."""
+    o = _c(outline_mask, np.uint8).reshape(-1)
+    e = _c(edited, np.uint8).reshape(-1)
+    assert o.size == W * H and e.size == W * H and layer.flags.c_contiguous
+    return int(lib().orc_pad(_p(o), _p(e), int(W), int(H), int(k), int(label), _p(layer), _dtype_code(layer)))

@@ -424,3 +424,50 @@ int orc_area(const double *w, const int32_t *tri_id, const void *layer, int dtyp
     free(comp);
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Texture padding (§4.3.2, TPA).  The outline mask holds the texels around
+ * the texture islands: texels no triangle covers whose distance to a
+ * covered texel is at most k.  After an edit, every outline texel whose
+ * distance to the edited area (the texels that edit selected) is at most k
+ * takes the edit's label.  Reading: distance between texels is the
+ * Chebyshev distance of their indices (the paper's square kernel of radius
+ * k, a (2k+1) x (2k+1) window), windows clipped at the atlas border; the
+ * paper pads one texel, k = 1, for both masks.
+ * ------------------------------------------------------------------------ */
+int64_t orc_outline(const int32_t *tri_id, int W, int H, int k, uint8_t *outline)
+{
+    int64_t count = 0;
+    for (int j = 0; j < H; ++j)
+        for (int i = 0; i < W; ++i) {
+            int64_t t = (int64_t)j * W + i;
+            outline[t] = 0;
+            if (tri_id[t] >= 0) continue;
+            for (int v = j - k; v <= j + k && !outline[t]; ++v)
+                for (int u = i - k; u <= i + k; ++u) {
+                    if (u < 0 || v < 0 || u >= W || v >= H) continue;
+                    if (tri_id[(int64_t)v * W + u] >= 0) { outline[t] = 1; break; }
+                }
+            count += outline[t];
+        }
+    return count;
+}
+
+int64_t orc_pad(const uint8_t *outline, const uint8_t *edited, int W, int H, int k, uint32_t label,
+                void *layer, int dtype)
+{
+    int64_t count = 0;
+    for (int j = 0; j < H; ++j)
+        for (int i = 0; i < W; ++i) {
+            int64_t t = (int64_t)j * W + i;
+            if (!outline[t]) continue;
+            int hit = 0;
+            for (int v = j - k; v <= j + k && !hit; ++v)
+                for (int u = i - k; u <= i + k; ++u) {
+                    if (u < 0 || v < 0 || u >= W || v >= H) continue;
+                    if (edited[(int64_t)v * W + u]) { hit = 1; break; }
+                }
+            if (hit) { put(layer, dtype, t, label); ++count; }
+        }
+    return count;
+}
