@@ -28,6 +28,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -263,6 +265,35 @@ def bench_serving(n_each, n_requests, slo_ms, torch, uvl):
             "batched_edits_per_s_at_slo": bb, "ratio_at_slo": (bb / bp) if bp and bb else None}
 
 
+def bench_padding(m, wl, uvl, torch, n_edits=200):
+    """Texture padding (§4.3.2) on the workload's model: the outline list
+    (radius 1, built once per model) and the padding pass after each of the
+    first n_edits edits (the paper's per-edit cost is editing + padding)."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    o = uvl.Outline(m.geom, 1)
+    build_ms = 1e3 * (time.perf_counter() - t)
+    per = {"brush": [], "lasso": []}
+    for e in wl.edits[:n_edits]:
+        lay = m.layers[e.layer]
+        if e.kind == "brush":
+            fn = lambda: uvl.pad_brush(m.geom, lay, o, e.centre, e.radius, e.label)
+        else:
+            M = wl.cameras[e.camera]
+            d = m.depth_for(e.camera, M)
+            fn = lambda: uvl.pad_lasso(m.geom, lay, o, M, e.poly, d, m.bias, e.label)
+        fn()
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        per[e.kind].append(e0.elapsed_time(e1) * 1e3)
+    return {"outline_texels": o.n, "outline_build_ms": build_ms, "edits": n_edits,
+            "pad_brush_us": float(np.mean(per["brush"])) if per["brush"] else None,
+            "pad_lasso_us": float(np.mean(per["lasso"])) if per["lasso"] else None}
+
+
 def copy_bandwidth(torch, nbytes=2 << 30, reps=10):
     """Achievable HBM bandwidth of a plain device-to-device copy (read + write)."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -384,6 +415,9 @@ def main():
     if "area_query" in stats:
         ab = N * (4 + sum(layer_bytes))
         kernels["area_query"]["gbps"] = ab / (stats["area_query"]["avg_us"] * 1e-6) / 1e9
+    padding = bench_padding(m, wl, uvl, torch)
+    log(f"padding: {padding['outline_texels']} outline texels, brush {padding['pad_brush_us']:.1f} us, "
+        f"lasso {padding['pad_lasso_us']:.1f} us per edit")
     copy_gbps = copy_bandwidth(torch)
     log(f"device copy bandwidth {copy_gbps:.0f} GB/s")
     batched = None
@@ -418,6 +452,7 @@ def main():
                      "bytes_per_launch": per_launch[kern], "avg_us": stats[kern]["avg_us"]},
         "kernels": kernels,
         "copy_gbps": copy_gbps,
+        "padding": padding,
         "batched": batched,
         "serving": serving,
     }

@@ -219,6 +219,44 @@ int32_t uvl_area_query(const uvl_geom *geom, const uvl_layer *layers, int32_t nl
                        uint64_t *bins_dev, double *areas_host, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Texture padding (§4.3.2).  Around every texture island (the texels
+ * triangles cover) the outline is the band of uncovered texels within
+ * Chebyshev distance k of a covered texel (the paper's square kernel; it
+ * pads one texel, k = 1).  After an edit, padding writes the edit's label
+ * into every outline texel within distance k of a texel the edit selected,
+ * so that sampling across an island's border reads the edited value.
+ * Padding writes uncovered texels only (areas never change) and edits write
+ * covered texels only, so a padding call may follow its edit at any time.
+ * ------------------------------------------------------------------------ */
+
+/* Device workspace bytes uvl_build_outline needs for a width x height
+ * atlas (0 if the size is invalid). */
+size_t uvl_outline_workspace_bytes(int32_t width, int32_t height);
+
+/* Outline texels of geom for radius k (0..8): their indices j*W+i, in
+ * ascending order, into outline (device int32, capacity entries); *count
+ * (host) receives their number.  SYNCHRONOUS.
+ * Errors: UVL_E_INVAL, UVL_E_NOMEM (ws too small, or more than capacity
+ * outline texels: *count is still set and the first capacity are written),
+ * UVL_E_DEVICE. */
+int32_t uvl_build_outline(const uvl_geom *geom, int32_t k, int32_t *outline, int64_t capacity, int64_t *count,
+                          void *ws, size_t ws_bytes, void *stream);
+
+/* Padding after a brush edit (same center, radius, label as the edit):
+ * outline[0..n) from uvl_build_outline on this geometry image (entries that
+ * are not texel indices are ignored), k the padding radius (0..8).  Each
+ * outline texel tests the brush predicate of uvl_edit_brush on the covered
+ * texels of its (2k+1)^2 window.  Errors as uvl_edit_brush, plus UVL_E_INVAL
+ * for k out of range and UVL_E_SHAPE for n > width*height. */
+int32_t uvl_pad_brush(const uvl_geom *geom, const uvl_layer *layer, const int32_t *outline, int64_t n, int32_t k,
+                      const float center[3], float radius, uint32_t label, void *stream);
+
+/* Padding after a lasso edit (same arguments as the edit's). */
+int32_t uvl_pad_lasso(const uvl_geom *geom, const uvl_layer *layer, const int32_t *outline, int64_t n, int32_t k,
+                      const float view_proj[16], const float *poly_xy, int32_t npoly, const float *depth, int32_t dw,
+                      int32_t dh, float bias, uint32_t label, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batched edit waves.  The paper applies one edit per rendering pass
  * (§4.3.1); a wave applies many pending edits -- of many models and layers --
  * with one persistent-kernel launch.  Each edit's selection depends only on

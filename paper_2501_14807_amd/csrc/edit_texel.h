@@ -157,6 +157,32 @@ __device__ __forceinline__ uint64_t lasso_crosses_mask(float ex0, float ey0, flo
     return (a ^ b) & __builtin_amdgcn_ballot_w64(lhs < rhs);
 }
 
+// The whole lasso predicate for one texel (a lane on its own, no wave-wide
+// step): the edges of its own slab, then the depth test.  Gives the same
+// result as lasso_quad for that texel.
+template <class PT>
+__device__ __forceinline__ bool lasso_texel(const PT &P, const float *__restrict__ depth, float x, float y,
+                                            float z) {
+    float xn, yn, cz, cw;
+    if (!lasso_front(P, x, y, z, xn, yn, cz, cw)) return false;
+    uint64_t m = P.slab_edges[lasso_slab(P, yn)];
+    bool inside = false;
+    while (m) {
+        const int e = __builtin_ctzll(m);
+        m &= m - 1;
+        const float ex0 = P.edge[e].x0, ey0 = P.edge[e].y0, ey1 = P.edge[e].y1;
+        const float esdx = P.edge[e].sdx, esdy = P.edge[e].sdy;
+        const float lhs = (xn - ex0) * esdy;
+        const float rhs = esdx * (yn - ey0);
+        inside ^= ((ey0 > yn) != (ey1 > yn)) && (lhs < rhs);
+    }
+    if (!inside) return false;
+    int pix;
+    float d;
+    if (!lasso_depth_index(P, xn, yn, cz, cw, pix, d)) return false;
+    return lasso_depth_pass(P, d, depth[pix]);
+}
+
 // Wave-wide min / max of a uint32 (every lane of the wave must be active):
 // rotations within each 16-lane row by DPP, then the four row results.
 __device__ __forceinline__ unsigned wave_min_u32(unsigned v) {

@@ -80,6 +80,10 @@ SIGNATURES = {
     "uvl_wave_tuned_chunks": ([_P, _I64], _I32),
     "uvl_wave_visited_tiles": ([_P, _P, _P], _I32),
     "uvl_wave_destroy": ([_P], _I32),
+    "uvl_outline_workspace_bytes": ([_I32, _I32], _SZ),
+    "uvl_build_outline": ([_P, _I32, _P, _I64, _P, _P, _SZ, _P], _I32),
+    "uvl_pad_brush": ([_P, _P, _P, _I64, _I32, _P, _F32, _U32, _P], _I32),
+    "uvl_pad_lasso": ([_P, _P, _P, _I64, _I32, _P, _P, _I32, _P, _I32, _I32, _F32, _U32, _P], _I32),
 }
 
 EDIT_BRUSH, EDIT_LASSO = 0, 1
@@ -306,6 +310,52 @@ def edit_lasso(geom: GeometryImage, layer: Layer, view_proj, poly, depth: torch.
     _check(_lib().uvl_edit_lasso(ctypes.byref(geom.c), ctypes.byref(layer.c), M.ctypes.data_as(ctypes.c_void_p),
                                  P.ctypes.data_as(ctypes.c_void_p), P.size // 2, _ptr(depth), dw, dh,
                                  float(np.float32(bias)), int(label), _stream(stream)), "uvl_edit_lasso")
+
+
+class Outline:
+    """Outline texels of a geometry image for texture padding (§4.3.2)."""
+
+    def __init__(self, geom: GeometryImage, k: int = 1, stream=None):
+        L = _lib()
+        need = L.uvl_outline_workspace_bytes(geom.width, geom.height)
+        if need == 0:
+            raise ValueError("bad atlas size")
+        ws = torch.empty(need, dtype=torch.uint8, device=geom.tri_id.device)
+        cap = max(1, geom.n // 8)
+        while True:
+            idx = torch.empty(cap, dtype=torch.int32, device=geom.tri_id.device)
+            n = ctypes.c_int64()
+            rc = L.uvl_build_outline(ctypes.byref(geom.c), int(k), _ptr(idx), cap, ctypes.byref(n), _ptr(ws), need,
+                                     _stream(stream))
+            if rc == -4 and n.value > cap:          # UVL_E_NOMEM: room for all of them, then again
+                cap = int(n.value)
+                continue
+            _check(rc, "uvl_build_outline")
+            break
+        self.k = int(k)
+        self.n = int(n.value)
+        self.idx = idx[:max(self.n, 1)]
+
+    def numpy(self) -> np.ndarray:
+        return self.idx[:self.n].cpu().numpy()
+
+
+def pad_brush(geom: GeometryImage, layer: Layer, outline: Outline, center, radius: float, label: int, stream=None):
+    c = _f32(center, 3)
+    _check(_lib().uvl_pad_brush(ctypes.byref(geom.c), ctypes.byref(layer.c), _ptr(outline.idx), outline.n, outline.k,
+                                c.ctypes.data_as(ctypes.c_void_p), float(np.float32(radius)), int(label),
+                                _stream(stream)), "uvl_pad_brush")
+
+
+def pad_lasso(geom: GeometryImage, layer: Layer, outline: Outline, view_proj, poly, depth: torch.Tensor, bias: float,
+              label: int, stream=None):
+    M = _f32(view_proj, 16)
+    P = _f32(poly).reshape(-1)
+    dh, dw = depth.shape
+    _check(_lib().uvl_pad_lasso(ctypes.byref(geom.c), ctypes.byref(layer.c), _ptr(outline.idx), outline.n, outline.k,
+                                M.ctypes.data_as(ctypes.c_void_p), P.ctypes.data_as(ctypes.c_void_p), P.size // 2,
+                                _ptr(depth), dw, dh, float(np.float32(bias)), int(label), _stream(stream)),
+           "uvl_pad_lasso")
 
 
 def layer_op(op: int, dst: Layer, a: Layer, b: Optional[Layer] = None, sel_a: int = 0, sel_b: int = 0,

@@ -175,3 +175,29 @@ def test_edit_records_match_the_c_struct():
     r1.view_proj, r1.poly_xy, r1.npoly = keep[2].ctypes.data, keep[3].ctypes.data, 3
     r1.dw, r1.dh, r1.bias, r1.depth = 64, 48, np.float32(1e-4), d.data_ptr()
     assert raw == bytes(r0) + bytes(r1)
+
+
+def test_padding_validation(uvl):
+    L = uvl.lib()
+    g, l = _geom(uvl), _layer(uvl)
+    c = (ctypes.c_float * 3)(0, 0, 0)
+    s = None
+    assert L.uvl_outline_workspace_bytes(0, 5) == 0 and L.uvl_outline_workspace_bytes(64, 32) >= 8
+    n = ctypes.c_int64()
+    ws_bytes = L.uvl_outline_workspace_bytes(64, 32)
+    assert L.uvl_build_outline(None, 1, FAKE, 10, ctypes.byref(n), FAKE, ws_bytes, s) == -1
+    assert L.uvl_build_outline(ctypes.byref(g), 9, FAKE, 10, ctypes.byref(n), FAKE, ws_bytes, s) == -1
+    assert L.uvl_build_outline(ctypes.byref(g), -1, FAKE, 10, ctypes.byref(n), FAKE, ws_bytes, s) == -1
+    assert L.uvl_build_outline(ctypes.byref(g), 1, FAKE, 10, None, FAKE, ws_bytes, s) == -1
+    assert L.uvl_build_outline(ctypes.byref(g), 1, FAKE, 10, ctypes.byref(n), FAKE, ws_bytes - 1, s) == -4
+    pad = lambda k=1, n_=4, label=1, layer=l, out=FAKE: L.uvl_pad_brush(
+        ctypes.byref(g), ctypes.byref(layer), out, n_, k, c, 1.0, label, s)
+    assert pad(k=9) == -1 and pad(k=-1) == -1
+    assert pad(n_=-1) == -1 and pad(out=None) == -1
+    assert pad(n_=64 * 32 + 1) == -2
+    assert pad(label=256) == -3
+    assert pad(layer=_layer(uvl, w=63)) == -2
+    M = (ctypes.c_float * 16)(*([1.0] * 16))
+    poly = (ctypes.c_float * 6)(0, 0, 1, 0, 0, 1)
+    assert L.uvl_pad_lasso(ctypes.byref(g), ctypes.byref(l), FAKE, 4, 1, M, poly, 2, FAKE, 32, 32, 1e-4, 1, s) == -1
+    assert L.uvl_pad_lasso(ctypes.byref(g), ctypes.byref(l), FAKE, 4, 1, M, poly, 3, None, 32, 32, 1e-4, 1, s) == -1
