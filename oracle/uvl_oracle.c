@@ -29,9 +29,9 @@
 #define ORC_REMAP 3
 
 /* ------------------------------------------------------------------------
- * Shared 2D raster rule (used by the texture-space raster, §4.3.1 "rendered
- * ... using the texture coordinates of the 3D model as vertex positions", and
- * by the depth texture of the same section).  The paper relies on the GPU
+ * Shared 2D raster rule (used by the texture-space raster of §4.3.1, where
+ * the mesh is drawn with its texture coordinates in place of its positions,
+ * and by the depth texture of the same section).  The paper relies on the GPU
  * rasteriser and states no sample or tie rule, so the reading is:
  *   - coordinates are snapped to fixed point with 8 fractional bits,
  *     X = round-half-even(x * 256) in fp64;
@@ -225,8 +225,8 @@ static int project(const float M[16], float x, float y, float z, float *xn, floa
 }
 
 /* ------------------------------------------------------------------------
- * Depth texture (§4.3.1: scene depth from the current point of view, used to
- * discard occluded fragments).  Rows [r0, r1) of a Wd x Hd map, initialised
+ * Depth texture (§4.3.1: the depth of the scene seen from the editing
+ * camera, against which occluded fragments are discarded).  Rows [r0, r1) of a Wd x Hd map, initialised
  * to 1.0 (far).  Reading: GL window depth d = 0.5 z_ndc + 0.5; pixel (ix, iy)
  * samples its centre, row 0 at NDC y = -1.  A triangle is drawn only if all
  * three vertices have clip w > 0 and |x_ndc|, |y_ndc| <= 16 (a guard band in
@@ -286,8 +286,8 @@ int orc_depth_map(const float *pos, const int32_t *tri, int64_t nv, int64_t nt, 
 }
 
 /* ------------------------------------------------------------------------
- * Layer write (§4.3.1: the selected value is stored in the data texture of
- * the layer).  Reading: overwrite; label 0 erases; u8 or u16 planes.
+ * Layer write (§4.3.1: the edit writes its value into the layer's data
+ * texture wherever the tool selects).  Reading: overwrite; label 0 erases; u8 or u16 planes.
  * ------------------------------------------------------------------------ */
 static void put(void *layer, int dtype, int64_t t, uint32_t label)
 {
