@@ -64,6 +64,10 @@ def lib():
         L.orc_layer_op.argtypes = [i32, P, i32, P, i32, P, i32, i64, u32, u32, u32, P]
         L.orc_layer_op.restype = i32
         L.orc_area.argtypes = [P, P, P, i32, i64, P, i32]
+        L.orc_tool_coeffs.argtypes = [P, P]
+        L.orc_tool_coeffs.restype = None
+        L.orc_tool.argtypes = [P, P, P, i64, P, P, P, i32, i32, P, i32, i32, f32, u32, P, i32]
+        L.orc_tool.restype = i64
         L.orc_outline.argtypes = [P, i32, i32, i32, P]
         L.orc_outline.restype = i64
         L.orc_pad.argtypes = [P, P, i32, i32, i32, u32, P, i32]
@@ -208,3 +212,27 @@ def pad(outline_mask: np.ndarray, edited: np.ndarray, W: int, H: int, k: int, la
     e = _c(edited, np.uint8).reshape(-1)
     assert o.size == W * H and e.size == W * H and layer.flags.c_contiguous
     return int(lib().orc_pad(_p(o), _p(e), int(W), int(H), int(k), int(label), _p(layer), _dtype_code(layer)))
+
+
+def tool_coeffs(tool) -> np.ndarray:
+    """fp32 (a_x, b_x, a_y, b_y) of the tool transform for tool = (Ww, Wh,
+    Tpx, Tpy, Tw, Th): s = fmaf(xn, a_x, b_x), t = fmaf(yn, a_y, b_y)."""
+    t = _c(tool, np.float64)
+    out = np.zeros(4, np.float32)
+    lib().orc_tool_coeffs(_p(t), _p(out))
+    return out
+
+
+def tool(pos32: np.ndarray, layer: np.ndarray, M, tool_params, shape: np.ndarray, depth: np.ndarray,
+         bias: float, label: int) -> int:
+    """The paper's screen-space tool (§4.3.1) in place; shape is u8 [sh, sw]."""
+    pos32 = _c(pos32, np.float32)
+    Mf = _c(M, np.float32).reshape(16)
+    tp = _c(tool_params, np.float64)
+    sh_ = _c(shape, np.uint8)
+    depth = _c(depth, np.float32)
+    Hd, Wd = depth.shape
+    assert layer.flags.c_contiguous and tp.size == 6
+    return int(lib().orc_tool(_p(pos32[0]), _p(pos32[1]), _p(pos32[2]), pos32.shape[1], _p(Mf), _p(tp), _p(sh_),
+                              sh_.shape[1], sh_.shape[0], _p(depth), Wd, Hd, float(np.float32(bias)), int(label),
+                              _p(layer), _dtype_code(layer)))

@@ -471,3 +471,62 @@ int64_t orc_pad(const uint8_t *outline, const uint8_t *edited, int W, int H, int
         }
     return count;
 }
+
+/* ------------------------------------------------------------------------
+ * Screen-space tool (§4.3.1, the paper's own TEA selection): the camera
+ * doubles as a slide projector whose frustum is narrowed, by the tool
+ * transform of §4.3.1, to the tool's square on the window; a fragment's
+ * projective texture coordinates outside [0,1] are discarded, the rest
+ * index the tool's shape texture, and the depth test applies.
+ * Reading (the printed translate factor has the sign that does not centre
+ * the tool on its position): with window size (Ww, Wh), tool position
+ * (Tpx, Tpy) in window pixels from the lower-left corner and tool size
+ * (Tw, Th) pixels, a point with NDC (xn, yn) gets
+ *   s = xn Ww/(2 Tw) - (Tpx - Ww/2)/Tw + 1/2,   t likewise with Wh, Tpy, Th,
+ * i.e. s = (wx - Tpx)/Tw + 1/2 for its window position wx = (xn + 1) Ww/2:
+ * the Tw x Th square centred on the tool maps onto [0,1]^2.  In fp32,
+ * s = fmaf(xn, a, b) with a = Ww/(2 Tw) and b = 1/2 - (Tpx - Ww/2)/Tw each
+ * computed in fp64 and rounded once (orc_tool_coeffs).  Selected iff the
+ * lasso's projective and depth tests pass (clip w > 0; x, y, z_ndc in
+ * [-1, 1]; d <= D + bias), s and t lie in [0, 1], and the shape texel
+ * (min(floor(s sw), sw - 1), min(floor(t sh), sh - 1)) of the sw x sh u8
+ * shape texture (row 0 at t = 0) is not 0.
+ * ------------------------------------------------------------------------ */
+void orc_tool_coeffs(const double tool[6], float ab[4])
+{
+    /* tool = {Ww, Wh, Tpx, Tpy, Tw, Th} */
+    ab[0] = (float)(tool[0] / (2.0 * tool[4]));
+    ab[1] = (float)(0.5 - (tool[2] - 0.5 * tool[0]) / tool[4]);
+    ab[2] = (float)(tool[1] / (2.0 * tool[5]));
+    ab[3] = (float)(0.5 - (tool[3] - 0.5 * tool[1]) / tool[5]);
+}
+
+int64_t orc_tool(const float *px, const float *py, const float *pz, int64_t n, const float M[16],
+                 const double tool[6], const uint8_t *shape, int sw, int sh, const float *depth, int Wd,
+                 int Hd, float bias, uint32_t label, void *layer, int dtype)
+{
+    float ab[4];
+    orc_tool_coeffs(tool, ab);
+    int64_t count = 0;
+    for (int64_t t = 0; t < n; ++t) {
+        float xn, yn, zn;
+        if (!project(M, px[t], py[t], pz[t], &xn, &yn, &zn)) continue;
+        if (!(xn >= -1.0f && xn <= 1.0f && yn >= -1.0f && yn <= 1.0f && zn >= -1.0f && zn <= 1.0f))
+            continue;
+        int ix = (int)floorf(fmaf(xn, 0.5f, 0.5f) * (float)Wd);
+        int iy = (int)floorf(fmaf(yn, 0.5f, 0.5f) * (float)Hd);
+        if (ix > Wd - 1) ix = Wd - 1;
+        if (iy > Hd - 1) iy = Hd - 1;
+        float d = fmaf(zn, 0.5f, 0.5f);
+        if (!(d <= depth[(int64_t)iy * Wd + ix] + bias)) continue;
+        float s = fmaf(xn, ab[0], ab[1]), u = fmaf(yn, ab[2], ab[3]);
+        if (!(s >= 0.0f && s <= 1.0f && u >= 0.0f && u <= 1.0f)) continue;
+        int sx = (int)floorf(s * (float)sw), sy = (int)floorf(u * (float)sh);
+        if (sx > sw - 1) sx = sw - 1;
+        if (sy > sh - 1) sy = sh - 1;
+        if (!shape[(int64_t)sy * sw + sx]) continue;
+        put(layer, dtype, t, label);
+        ++count;
+    }
+    return count;
+}
