@@ -265,6 +265,35 @@ def bench_serving(n_each, n_requests, slo_ms, torch, uvl):
             "batched_edits_per_s_at_slo": bb, "ratio_at_slo": (bb / bp) if bp and bb else None}
 
 
+def bench_tool(m, wl, uvl, torch, n_edits=100):
+    """The paper's screen-space tool (§4.3.1) on the workload's model: a
+    200-pixel disk tool at seeded positions on a window the size of the
+    depth maps, with the workload's cameras; per-launch time and the
+    position bytes it streams (12 per texel)."""
+    rng = np.random.default_rng(5001)
+    shape = uvl.disk_shape(256)
+    Ww, Wh = wl.depth_w, wl.depth_h
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for k in range(n_edits):
+        cam = int(rng.integers(0, len(wl.cameras)))
+        M = wl.cameras[cam]
+        d = m.depth_for(cam, M)
+        tool = (Ww, Wh, float(rng.uniform(0.2, 0.8) * Ww), float(rng.uniform(0.2, 0.8) * Wh), 200.0, 200.0)
+        lay = m.layers[k % len(m.layers)]
+        fn = lambda: uvl.edit_tool(m.geom, lay, M, tool, shape, d, m.bias, 1 + k % 200)
+        fn()
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e3)
+    us = float(np.mean(ts))
+    N = wl.W * wl.H
+    return {"edits": n_edits, "tool_px": 200, "window": [Ww, Wh], "tool_us": us, "texels_per_s": N / (us * 1e-6),
+            "gbps": 12.0 * N / (us * 1e-6) / 1e9}
+
+
 def bench_padding(m, wl, uvl, torch, n_edits=200):
     """Texture padding (§4.3.2) on the workload's model: the outline list
     (radius 1, built once per model) and the padding pass after each of the
@@ -415,6 +444,8 @@ def main():
     if "area_query" in stats:
         ab = N * (4 + sum(layer_bytes))
         kernels["area_query"]["gbps"] = ab / (stats["area_query"]["avg_us"] * 1e-6) / 1e9
+    tool = bench_tool(m, wl, uvl, torch)
+    log(f"screen-space tool: {tool['tool_us']:.1f} us per edit ({tool['gbps']:.0f} GB/s)")
     padding = bench_padding(m, wl, uvl, torch)
     log(f"padding: {padding['outline_texels']} outline texels, brush {padding['pad_brush_us']:.1f} us, "
         f"lasso {padding['pad_lasso_us']:.1f} us per edit")
@@ -452,6 +483,7 @@ def main():
                      "bytes_per_launch": per_launch[kern], "avg_us": stats[kern]["avg_us"]},
         "kernels": kernels,
         "copy_gbps": copy_gbps,
+        "tool": tool,
         "padding": padding,
         "batched": batched,
         "serving": serving,

@@ -218,6 +218,26 @@ int32_t uvl_layer_op(int32_t op, const uvl_layer *dst, const uvl_layer *a, const
 int32_t uvl_area_query(const uvl_geom *geom, const uvl_layer *layers, int32_t nlayers,
                        uint64_t *bins_dev, double *areas_host, void *stream);
 
+/* The paper's screen-space editing tool (§4.3.1): projective texture
+ * mapping of the tool's shape texture through the camera, narrowed to the
+ * tool's square on the window.  tool (host double[6]) = {Ww, Wh, Tpx, Tpy,
+ * Tw, Th}: window size, tool position (window pixels from the lower-left
+ * corner) and tool size (pixels), all finite, sizes > 0.  A texel is
+ * selected iff, with xn, yn, z_ndc and the depth test exactly as for
+ * uvl_edit_lasso (view_proj, depth [dh][dw], bias), its tool coordinates
+ *   s = fmaf(xn, ax, bx), t = fmaf(yn, ay, by),
+ *   ax = Ww / (2 Tw), bx = 1/2 - (Tpx - Ww/2) / Tw (fp64, rounded once to
+ *   fp32; ay, by likewise with Wh, Tpy, Th)
+ * lie in [0, 1] and the shape texel (min(floor(s sw), sw-1),
+ * min(floor(t sh), sh-1)) of shape (device u8 [sh][sw], row 0 at t = 0,
+ * 1 <= sw, sh <= 4096) is not 0.  The Tw x Th square centred on the tool
+ * maps onto [0, 1]^2.
+ * Errors: UVL_E_INVAL (pointers, tool, shape or depth sizes, bias),
+ * UVL_E_SHAPE, UVL_E_DTYPE. */
+int32_t uvl_edit_tool(const uvl_geom *geom, const uvl_layer *layer, const float view_proj[16], const double tool[6],
+                      const uint8_t *shape, int32_t sw, int32_t sh, const float *depth, int32_t dw, int32_t dh,
+                      float bias, uint32_t label, void *stream);
+
 /* ------------------------------------------------------------------------
  * Texture padding (§4.3.2).  Around every texture island (the texels
  * triangles cover) the outline is the band of uncovered texels within

@@ -80,6 +80,7 @@ SIGNATURES = {
     "uvl_wave_tuned_chunks": ([_P, _I64], _I32),
     "uvl_wave_visited_tiles": ([_P, _P, _P], _I32),
     "uvl_wave_destroy": ([_P], _I32),
+    "uvl_edit_tool": ([_P, _P, _P, _P, _P, _I32, _I32, _P, _I32, _I32, _F32, _U32, _P], _I32),
     "uvl_outline_workspace_bytes": ([_I32, _I32], _SZ),
     "uvl_build_outline": ([_P, _I32, _P, _I64, _P, _P, _SZ, _P], _I32),
     "uvl_pad_brush": ([_P, _P, _P, _I64, _I32, _P, _F32, _U32, _P], _I32),
@@ -310,6 +311,30 @@ def edit_lasso(geom: GeometryImage, layer: Layer, view_proj, poly, depth: torch.
     _check(_lib().uvl_edit_lasso(ctypes.byref(geom.c), ctypes.byref(layer.c), M.ctypes.data_as(ctypes.c_void_p),
                                  P.ctypes.data_as(ctypes.c_void_p), P.size // 2, _ptr(depth), dw, dh,
                                  float(np.float32(bias)), int(label), _stream(stream)), "uvl_edit_lasso")
+
+
+def edit_tool(geom: GeometryImage, layer: Layer, view_proj, tool, shape: torch.Tensor, depth: torch.Tensor,
+              bias: float, label: int, stream=None):
+    """The paper's screen-space tool: tool = (Ww, Wh, Tpx, Tpy, Tw, Th),
+    shape a device uint8 [sh, sw] tensor."""
+    M = _f32(view_proj, 16)
+    tp = np.ascontiguousarray(np.asarray(tool, dtype=np.float64))
+    if tp.size != 6:
+        raise ValueError("tool needs 6 numbers (Ww, Wh, Tpx, Tpy, Tw, Th)")
+    if shape.dtype != torch.uint8 or shape.dim() != 2 or not shape.is_contiguous():
+        raise ValueError("shape must be a contiguous uint8 [sh, sw] tensor")
+    sh, sw = shape.shape
+    dh, dw = depth.shape
+    _check(_lib().uvl_edit_tool(ctypes.byref(geom.c), ctypes.byref(layer.c), M.ctypes.data_as(ctypes.c_void_p),
+                                tp.ctypes.data_as(ctypes.c_void_p), _ptr(shape), sw, sh, _ptr(depth), dw, dh,
+                                float(np.float32(bias)), int(label), _stream(stream)), "uvl_edit_tool")
+
+
+def disk_shape(n: int = 256, device="cuda") -> torch.Tensor:
+    """The default tool shape: a disk inscribed in an n x n texture (texel
+    centres within radius 1/2 of the centre)."""
+    c = (torch.arange(n, dtype=torch.float64) + 0.5) / n - 0.5
+    return ((c[:, None] ** 2 + c[None, :] ** 2) <= 0.25).to(torch.uint8).to(device).contiguous()
 
 
 class Outline:

@@ -201,3 +201,25 @@ def test_padding_validation(uvl):
     poly = (ctypes.c_float * 6)(0, 0, 1, 0, 0, 1)
     assert L.uvl_pad_lasso(ctypes.byref(g), ctypes.byref(l), FAKE, 4, 1, M, poly, 2, FAKE, 32, 32, 1e-4, 1, s) == -1
     assert L.uvl_pad_lasso(ctypes.byref(g), ctypes.byref(l), FAKE, 4, 1, M, poly, 3, None, 32, 32, 1e-4, 1, s) == -1
+
+
+def test_tool_validation(uvl):
+    L = uvl.lib()
+    g, l = _geom(uvl), _layer(uvl)
+    M = (ctypes.c_float * 16)(*([1.0] * 16))
+    s = None
+    ok = [1024.0, 768.0, 500.0, 400.0, 100.0, 100.0]
+
+    def call(tool=ok, shape=FAKE, sw=16, sh=16, depth=FAKE, dw=32, dh=32, bias=1e-4, label=1, layer=l):
+        t = (ctypes.c_double * 6)(*tool)
+        return L.uvl_edit_tool(ctypes.byref(g), ctypes.byref(layer), M, t, shape, sw, sh, depth, dw, dh, bias,
+                               label, s)
+
+    assert call(tool=[1024, 768, 500, 400, 0, 100]) == -1
+    assert call(tool=[0, 768, 500, 400, 10, 100]) == -1
+    assert call(tool=[1024, 768, float("nan"), 400, 10, 100]) == -1
+    assert call(shape=None) == -1 and call(depth=None) == -1
+    assert call(sw=0) == -1 and call(sh=5000) == -1
+    assert call(dw=0) == -1 and call(bias=float("inf")) == -1
+    assert call(label=256) == -3
+    assert call(layer=_layer(uvl, h=31)) == -2
