@@ -203,7 +203,7 @@ def bench_batched(n_models, reps, torch, uvl):
 
 
 # offered request rates of the serving sweep (requests/s)
-SERVE_RATES = (4000.0, 8000.0, 12000.0, 16000.0, 24000.0, 32000.0, 40000.0, 48000.0, 56000.0, 64000.0)
+SERVE_RATES = (4000.0, 8000.0, 12000.0, 14000.0, 16000.0, 24000.0, 32000.0, 40000.0, 48000.0, 56000.0, 60000.0, 64000.0)
 
 
 def bench_serving(n_each, n_requests, slo_ms, torch, uvl):
