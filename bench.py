@@ -16,6 +16,13 @@ second (every edit evaluates every texel of the atlas, as in the paper's
 editing pass).  Per-kernel durations come from HIP events recorded on the
 launch stream around every launch inside the timed steps.
 
+Beside the step, untimed by the step's clock and reported in their own
+fields: the paper's screen-space tool and texture padding on the same model,
+the batched-wave comparison (256 models of uneven size, one launch per edit
+against one wave) and the serving comparison (32 + 32 resident models,
+Poisson requests swept over rates, p50/p99 and edits/s, plain against
+continuous batching), then the oracle on a bounded sample (`cpu_baseline`).
+
 Prints one JSON line.
 """
 

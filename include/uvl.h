@@ -311,7 +311,8 @@ typedef struct uvl_wave uvl_wave;   /* opaque handle */
  * max_lassos are lassos, with room for max_cull_words tile-culling words (a
  * layer whose geometry image has tile bounds needs ceil(edits / 64) words
  * per 32 x 32 tile of its atlas; layers whose words do not fit run without
- * culling, with identical results). */
+ * culling, with identical results).  Each word takes 20 bytes (the live
+ * mask, the inside mask and a live-list entry). */
 size_t uvl_wave_workspace_bytes(int32_t max_edits, int32_t max_lassos, int64_t max_cull_words);
 
 /* Create a wave handle over a caller-owned device workspace (256-byte
