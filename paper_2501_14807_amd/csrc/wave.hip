@@ -1,12 +1,14 @@
 // Batched edit waves for libuvl: many models' pending brush and lasso edits
 // applied by one persistent-kernel launch.
 //
-// The paper applies one edit per rendering pass (§4.3.1).  Each edit is a
-// pure function of the texel's stored position, and the last selecting edit
-// wins, so a layer's pending edits can be applied in one pass: read the
-// positions of a tile once, evaluate every edit of that layer in submission
-// order in registers, and store each texel's final label once.  The result
-// is bit-identical to applying the edits one launch at a time.
+// The paper applies one edit per rendering pass (§4.3.1).  Each edit's
+// selection is a pure function of the texel's stored position, and the last
+// selecting edit wins, so a layer's pending edits can be applied in one
+// pass: read the positions of a tile once, evaluate the layer's edits in
+// registers from the last to the first (a texel takes the label of the
+// first that selects it; a wave stops once each of its texels is taken or
+// uncovered), and store each texel's final label once.  The result is
+// bit-identical to applying the edits one launch at a time in order.
 //
 // Work decomposition: edits are grouped by target layer into streams (each
 // stream keeps its edits' order); a stream's atlas is cut into 32 x 32-texel
@@ -21,12 +23,13 @@
 // edit is tested against the block's bounds and, if it survives, against
 // each tile's bounds (exact conservative tests, edit_texel.h); a lane stores,
 // per group of 64 edits, the mask of edits that may select something in its
-// tile.
-// Tiles with a live edit are appended to the stream's live list (one atomic
-// per wave).  A one-workgroup kernel then turns the per-stream live counts
-// into item ranges, and the wave kernel visits only live tiles, evaluating
-// only their live edits.  Streams whose masks do not fit the workspace run
-// without culling (every tile is an item).
+// tile and the mask of lassos whose polygon provably contains the whole tile
+// (their polygon test is skipped).  Tiles with a live edit are appended to
+// the stream's live list (one atomic per wave).  A one-workgroup kernel then
+// turns the per-stream live counts into item ranges, and the wave kernel
+// visits only live tiles, evaluating only their live edits.  Streams whose
+// masks do not fit the workspace run without culling (every tile is an
+// item).
 //
 // The descriptor (header with the region offsets, streams, per-stream
 // counters, edits, lasso parameters) is packed densely on the host and
