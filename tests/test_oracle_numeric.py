@@ -1,0 +1,155 @@
+"""Numeric layers in the oracle (§4.2: data texture of integers or floats
+plus a mask texture), pinned against what the number formats and the
+geometry fix:
+
+  - binary16 bit patterns that follow from the IEEE 754 format (normals,
+    subnormals, ties to even, the largest finite value, overflow), and
+    numpy's own double-to-half conversion on random values;
+  - a mask packed by hand;
+  - zonal statistics on an 8 x 8 plane seen as a W x W atlas, whose texel
+    centres sit at x_i = 8 (i + 1/2) / W - 4: the discrete moments
+    mean(x^2) = 16/3 (1 - 1/W^2), min x^2 = (4/W)^2, max x^2 = (4 - 4/W)^2,
+    per-quadrant means of x of -2 and +2, the plane's area 64;
+  - two charts of equal texel count but areas 64 and 4 holding 1 and 3:
+    the area-weighted mean is 76/68, not the texel mean 2;
+  - a brush SET selects pi r^2 of the plane and ERASE takes it back;
+  - a range selection |x| <= 1 labels a band of area 16.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import numeric as N
+
+
+@pytest.mark.parametrize("x,bits", [
+    (1.0, 0x3C00), (-2.5, 0xC100), (0.5, 0x3800), (65504.0, 0x7BFF), (65519.99, 0x7BFF),
+    (2.0 ** -14, 0x0400), (2.0 ** -24, 0x0001), (2.0 ** -25, 0x0000), (3 * 2.0 ** -25, 0x0002),
+    (1 + 2.0 ** -11, 0x3C00), (1 + 3 * 2.0 ** -11, 0x3C02), (1 + 2.0 ** -11 + 2.0 ** -40, 0x3C01),
+    (-0.0, 0x8000), (0.1, 0x2E66), (1 / 3, 0x3555), (2.0 ** -14 - 2.0 ** -25, 0x0400),
+])
+def test_f16_bits_from_the_format(x, bits):
+    assert N.f16_bits(x) == bits
+
+
+def test_f16_overflow_and_numpy_agreement():
+    for x in (65520.0, -65520.0, 1e9, math.inf):
+        with pytest.raises(OverflowError):
+            N.f16_bits(x)
+    rng = np.random.default_rng(3)
+    xs = np.concatenate([rng.normal(0, 1, 4000), rng.normal(0, 1e4, 2000) % 65500,
+                         rng.uniform(-1, 1, 2000) * 2.0 ** -14, rng.uniform(-1, 1, 2000) * 2.0 ** -23])
+    want = xs.astype(np.float16).view(np.uint16)
+    got = np.array([N.f16_bits(float(x)) for x in xs], np.uint16)
+    assert np.array_equal(got, want)
+
+
+def test_encode_ranges():
+    assert N.encode(255, N.U8) == 255 and N.encode(65535, N.U16) == 65535
+    assert N.encode(-2 ** 31, N.I32) == -2 ** 31 and N.encode(2 ** 31 - 1, N.I32) == 2 ** 31 - 1
+    for v, dt in ((256, N.U8), (-1, N.U8), (65536, N.U16), (1.5, N.I32), (2 ** 31, N.I32),
+                  (float("nan"), N.F32), (1e39, N.F32), (7e4, N.F16)):
+        with pytest.raises(ValueError):
+            N.encode(v, dt)
+    assert N.encode(0.1, N.F32) == np.float32(0.1)
+    assert N.encode(3.4e38, N.F32) == np.float32(3.4e38)
+
+
+def test_mask_packing_by_hand():
+    v = np.zeros(71, bool)
+    v[[0, 5, 31, 32, 70]] = True
+    w = N.pack_mask(v)
+    assert w.dtype == np.uint32 and list(w) == [0x80000021, 0x1, 0x40]
+    assert np.array_equal(N.unpack_mask(w, 71), v)
+    assert N.pack_mask(np.ones(64, bool)).tolist() == [0xFFFFFFFF, 0xFFFFFFFF]
+
+
+def _plane(orc, W):
+    A = np.array([[8.0, 0.0], [0.0, 8.0], [0.0, 0.0]])
+    m = synth.plane_grid(5, 5, A=A, b=(-4.0, -4.0, 0.0))
+    g = orc.geometry_image(m, W, W)
+    assert (g.tri_id >= 0).all()
+    return g
+
+
+@pytest.mark.parametrize("W", [64, 96])
+def test_stats_plane_moments(orc, W):
+    g = _plane(orc, W)
+    x = g.pos[0]
+    L = N.NumericLayer(W * W, N.F32)
+    L.data[:] = (x * x).astype(np.float32)
+    L.valid[:] = True
+    s = N.stats(g.tri_id, g.w, L)[0]
+    assert s["count"] == W * W
+    assert abs(s["area"] - 64.0) < 1e-9
+    assert abs(s["wsum"] / s["area"] - 16 / 3 * (1 - 1 / W ** 2)) < 1e-6
+    assert abs(s["vmin"] - (4 / W) ** 2) <= 2 ** -23 * (4 / W) ** 2
+    assert abs(s["vmax"] - (4 - 4 / W) ** 2) <= 2 ** -23 * 16
+    # quadrant labels 1..4; mean x of each is -2 or +2, area 16, count W^2/4
+    y = g.pos[1]
+    region = (1 + (x > 0) + 2 * (y > 0)).astype(np.uint8)
+    X = N.NumericLayer(W * W, N.F32)
+    X.data[:] = x.astype(np.float32)
+    X.valid[:] = True
+    q = N.stats(g.tri_id, g.w, X, region)
+    for lab, sx in ((1, -2), (2, 2), (3, -2), (4, 2)):
+        assert q[lab]["count"] == W * W // 4
+        assert abs(q[lab]["area"] - 16.0) < 1e-9
+        assert abs(q[lab]["wsum"] / q[lab]["area"] - sx) < 1e-6
+    assert q[0]["count"] == 0 and q[0]["vmin"] == np.inf and q[0]["vmax"] == -np.inf
+    # texels outside the mask are left out
+    X.valid[region != 2] = False
+    q2 = N.stats(g.tri_id, g.w, X, region)
+    assert q2[2]["count"] == W * W // 4 and q2[1]["count"] == 0
+
+
+def test_stats_are_area_weighted(orc):
+    W = 64
+    big = synth.plane_grid(5, 5, uv0=(0.0, 0.0), uv1=(0.5, 1.0), A=((16.0, 0.0), (0.0, 8.0), (0.0, 0.0)),
+                           b=(-4.0, -4.0, 0.0))
+    small = synth.plane_grid(5, 5, uv0=(0.5, 0.0), uv1=(1.0, 1.0), A=((4.0, 0.0), (0.0, 2.0), (0.0, 0.0)),
+                             b=(8.0, 0.0, 0.0))
+    g = orc.geometry_image(synth.merge_meshes([big, small]), W, W)
+    assert (g.tri_id >= 0).all()
+    L = N.NumericLayer(W * W, N.F16)
+    L.data[:] = np.where(g.pos[0] < 6.0, 1.0, 3.0).astype(np.float16)
+    L.valid[:] = True
+    s = N.stats(g.tri_id, g.w, L)[0]
+    assert s["count"] == W * W and abs(s["area"] - 68.0) < 1e-9
+    assert abs(s["wsum"] / s["area"] - 76.0 / 68.0) < 1e-12
+    assert s["vmin"] == 1.0 and s["vmax"] == 3.0
+
+
+def test_brush_set_then_erase(orc):
+    W = 256
+    g = _plane(orc, W)
+    for dt, val in ((N.F32, 2.75), (N.F16, -0.1), (N.I32, -7), (N.U16, 40000), (N.U8, 3)):
+        L = N.NumericLayer(W * W, dt)
+        n = N.brush(g.pos32, L, (0.5, -0.25, 0.0), 2.0, N.SET, val)
+        s = N.stats(g.tri_id, g.w, L)[0]
+        assert s["count"] == n and abs(s["area"] / (math.pi * 4.0) - 1) < 1e-2
+        assert s["vmin"] == s["vmax"] == float(N.encode(val, dt))
+        assert (L.data[L.valid] == N.encode(val, dt)).all() and not L.data[~L.valid].any()
+        N.brush(g.pos32, L, (0.5, -0.25, 0.0), 2.0, N.ERASE)
+        assert not L.valid.any() and N.stats(g.tri_id, g.w, L)[0]["count"] == 0
+        assert (L.data != 0).sum() == n                # ERASE keeps the data
+
+
+def test_range_selection_band(orc):
+    W = 128
+    g = _plane(orc, W)
+    L = N.NumericLayer(W * W, N.F32)
+    L.data[:] = (g.pos[0] * g.pos[0]).astype(np.float32)
+    L.valid[:] = True
+    dst = np.zeros(W * W, np.uint8)
+    n = N.select(L, 0.0, 1.0, dst, 5)
+    # |x| <= 1: the band -1 <= x <= 1 of height 8, discretised to whole
+    # texel columns of width 8 / W
+    area = orc.area(g, dst)[5]
+    assert n > 0 and abs(area - 16.0) <= 2 * 8 * (8 / W) + 1e-9
+    assert N.select(L, 2.0, 1.0, dst, 6) == 0
+    L.valid[:W * W // 2] = False
+    assert N.select(L, 0.0, 1.0, dst, 7) == n // 2
