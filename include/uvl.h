@@ -47,10 +47,12 @@ typedef enum {
 } uvl_status;
 
 /* Layer data types (§4.2: the data texture holds 8/16/32-bit integers or
- * 16/32-bit floats; database layers hold unsigned primary keys).  This
- * library implements the unsigned 8- and 16-bit label layers; value 0 is
- * the null key ("no data"), standing in for the layer's mask texture. */
-typedef enum { UVL_U8 = 1, UVL_U16 = 2 } uvl_dtype;
+ * 16/32-bit floats; database layers hold unsigned primary keys).  Label
+ * (database) layers, uvl_layer, are UVL_U8 or UVL_U16; their value 0 is the
+ * null key ("no data"), standing in for the layer's mask texture.  Numeric
+ * layers, uvl_numeric, take any of the five and carry a mask plane.
+ * UVL_I32 is signed; UVL_F16 and UVL_F32 are IEEE binary16 and binary32. */
+typedef enum { UVL_U8 = 1, UVL_U16 = 2, UVL_I32 = 3, UVL_F16 = 4, UVL_F32 = 5 } uvl_dtype;
 
 /* Layer operations (§3.4.2: layer systems combine layers with logic
  * operations).  See uvl_layer_op. */
@@ -275,6 +277,75 @@ int32_t uvl_pad_brush(const uvl_geom *geom, const uvl_layer *layer, const int32_
 int32_t uvl_pad_lasso(const uvl_geom *geom, const uvl_layer *layer, const int32_t *outline, int64_t n, int32_t k,
                       const float view_proj[16], const float *poly_xy, int32_t npoly, const float *depth, int32_t dw,
                       int32_t dh, float bias, uint32_t label, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Numeric layers (§4.2: numeric layers hold integer or real properties such
+ * as curvature or age; an information layer is a data texture plus a mask
+ * texture saying which texels hold valid data).  Edits select texels with
+ * the same predicates as the label edits above and SET them (store the
+ * value, set the mask bit) or ERASE them (clear the mask bit, keep the
+ * data).  The value arrives as a double and is converted once on the host:
+ * integer dtypes need an integral value in range (else UVL_E_DTYPE); floats
+ * round to nearest, ties to even, and must stay finite (else UVL_E_DTYPE);
+ * NaN is UVL_E_INVAL.
+ * ------------------------------------------------------------------------ */
+typedef enum { UVL_SET = 0, UVL_ERASE = 1 } uvl_value_mode;
+
+/* A numeric layer: data as uvl_layer (width*height values of dtype, device,
+ * 16-byte aligned, row-major) and mask, device uint32[ceil(width*height/32)]
+ * 16-byte aligned, texel t = j*W + i valid iff bit t % 32 of mask[t / 32]
+ * is set.  Bits beyond the last texel are never written. */
+typedef struct {
+    void *data;
+    uint32_t *mask;
+    int32_t width, height;
+    int32_t dtype;          /* uvl_dtype, any of the five */
+} uvl_numeric;
+
+/* Zero the data and the mask (no texel valid).  Asynchronous. */
+int32_t uvl_numeric_create(const uvl_numeric *layer, void *stream);
+
+/* Numeric brush, lasso and screen-space tool: the selection of
+ * uvl_edit_brush, uvl_edit_lasso and uvl_edit_tool (same arguments and
+ * errors), then `mode` (uvl_value_mode) with `value` (ignored by ERASE). */
+int32_t uvl_numeric_brush(const uvl_geom *geom, const uvl_numeric *layer, const float center[3], float radius,
+                          int32_t mode, double value, void *stream);
+int32_t uvl_numeric_lasso(const uvl_geom *geom, const uvl_numeric *layer, const float view_proj[16],
+                          const float *poly_xy, int32_t n, const float *depth, int32_t dw, int32_t dh, float bias,
+                          int32_t mode, double value, void *stream);
+int32_t uvl_numeric_tool(const uvl_geom *geom, const uvl_numeric *layer, const float view_proj[16],
+                         const double tool[6], const uint8_t *shape, int32_t sw, int32_t sh, const float *depth,
+                         int32_t dw, int32_t dh, float bias, int32_t mode, double value, void *stream);
+
+/* Range selection, turning quantitative data into a label: every texel of
+ * src whose mask bit is set and whose value v (exact in fp64) satisfies
+ * lo <= v <= hi gets `label` in the label layer dst (same size); other
+ * texels of dst are untouched.  lo > hi selects nothing.
+ * Errors: UVL_E_INVAL (pointers, NaN bounds), UVL_E_SHAPE, UVL_E_DTYPE
+ * (dst not u8/u16 or label too wide). */
+int32_t uvl_numeric_select(const uvl_numeric *src, double lo, double hi, const uvl_layer *dst, uint32_t label,
+                           void *stream);
+
+/* One group of zonal statistics. */
+typedef struct {
+    uint64_t count;     /* texels counted                                     */
+    uint64_t area_w;    /* sum of their area_w (exact); area = area_w * area_scale */
+    double wsum;        /* sum of area_w * value in fp64, in an unspecified order */
+    double vmin, vmax;  /* extremes of the value (+inf / -inf when count is 0) */
+} uvl_numstat;
+
+/* Zonal statistics of a numeric layer (Table 1 gives the surface area one
+ * texel stands for; weighting values by it gives area-weighted means, area
+ * wsum / area_w).  Counted texels: covered (tri_id >= 0) with the mask bit
+ * set.  They are grouped by the value of the label layer `region` (u8: 256
+ * groups, u16: 65536), or form one group when region is NULL.  bins_dev:
+ * device uvl_numstat[groups], 8-byte aligned, overwritten.  If bins_host is
+ * non-NULL the call is SYNCHRONOUS and copies the groups there; otherwise
+ * it is asynchronous.  wsum is within (count + 1) * 2^-53 * sum |area_w v|
+ * of the exact sum.
+ * Errors: UVL_E_INVAL (pointers, alignment), UVL_E_SHAPE, UVL_E_DTYPE. */
+int32_t uvl_numeric_stats(const uvl_geom *geom, const uvl_numeric *layer, const uvl_layer *region,
+                          uvl_numstat *bins_dev, uvl_numstat *bins_host, void *stream);
 
 /* ------------------------------------------------------------------------
  * Batched edit waves.  The paper applies one edit per rendering pass

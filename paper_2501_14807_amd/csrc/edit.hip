@@ -14,6 +14,7 @@
 #include <math.h>
 
 #include "edit_texel.h"
+#include "sink.h"
 #include "uvl_internal.h"
 
 namespace uvl {
@@ -22,57 +23,28 @@ namespace {
 constexpr int kChunk = kBlock * 4;        // texels per chunk
 constexpr int kTile = 4 * kChunk;         // texels per workgroup
 
-template <typename T>
-__device__ __forceinline__ void store4(T *__restrict__ L, int64_t t, bool s0, bool s1, bool s2, bool s3, T label);
-
-template <>
-__device__ __forceinline__ void store4<uint8_t>(uint8_t *__restrict__ L, int64_t t, bool s0, bool s1, bool s2,
-                                                bool s3, uint8_t label) {
-    if (s0 && s1 && s2 && s3) {
-        *reinterpret_cast<uint32_t *>(L + t) = 0x01010101u * label;
-    } else {
-        if (s0) L[t] = label;
-        if (s1) L[t + 1] = label;
-        if (s2) L[t + 2] = label;
-        if (s3) L[t + 3] = label;
-    }
-}
-
-template <>
-__device__ __forceinline__ void store4<uint16_t>(uint16_t *__restrict__ L, int64_t t, bool s0, bool s1, bool s2,
-                                                 bool s3, uint16_t label) {
-    if (s0 && s1 && s2 && s3) {
-        const uint32_t v = 0x00010001u * label;
-        *reinterpret_cast<uint2 *>(L + t) = make_uint2(v, v);
-    } else {
-        if (s0) L[t] = label;
-        if (s1) L[t + 1] = label;
-        if (s2) L[t + 2] = label;
-        if (s3) L[t + 3] = label;
-    }
-}
-
-template <typename T>
+template <typename Sink>
 __device__ __forceinline__ void brush_tail(const float *__restrict__ px, const float *__restrict__ py,
-                                           const float *__restrict__ pz, T *__restrict__ L, int64_t n,
-                                           const BrushParams &B, T label) {
+                                           const float *__restrict__ pz, const Sink &out, int64_t n,
+                                           const BrushParams &B) {
     const int64_t base = (int64_t)blockIdx.x * kTile + threadIdx.x * 4;
     for (int c = 0; c < 4; ++c)
         for (int k = 0; k < 4; ++k) {
             const int64_t t = base + c * kChunk + k;
-            if (t < n && brush_texel(B, px[t], py[t], pz[t])) L[t] = label;
+            if (t < n && brush_texel(B, px[t], py[t], pz[t])) out.put1(t);
         }
 }
 
 // Brush: one workgroup tile of 4096 consecutive texels; the last, partial
-// tile takes the per-texel path.
-template <typename T>
+// tile takes the per-texel path.  Lanes 8g .. 8g+7 of a wave hold 32
+// consecutive texels starting at a multiple of 32 (one mask word).
+template <typename Sink>
 __global__ __launch_bounds__(kBlock) void k_brush(const float *__restrict__ px, const float *__restrict__ py,
-                                                  const float *__restrict__ pz, T *__restrict__ L, int64_t n,
-                                                  BrushParams p, uint32_t label) {
+                                                  const float *__restrict__ pz, Sink out, int64_t n,
+                                                  BrushParams p) {
     const int64_t base = (int64_t)blockIdx.x * kTile + threadIdx.x * 4;
     if ((int64_t)(blockIdx.x + 1) * kTile > n) {
-        brush_tail<T>(px, py, pz, L, n, p, (T)label);
+        brush_tail(px, py, pz, out, n, p);
         return;
     }
     float4 X[4], Y[4], Z[4];
@@ -84,11 +56,9 @@ __global__ __launch_bounds__(kBlock) void k_brush(const float *__restrict__ px, 
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        const bool s0 = brush_texel(p, X[c].x, Y[c].x, Z[c].x);
-        const bool s1 = brush_texel(p, X[c].y, Y[c].y, Z[c].y);
-        const bool s2 = brush_texel(p, X[c].z, Y[c].z, Z[c].z);
-        const bool s3 = brush_texel(p, X[c].w, Y[c].w, Z[c].w);
-        store4<T>(L, base + c * kChunk, s0, s1, s2, s3, (T)label);
+        const bool s[4] = {brush_texel(p, X[c].x, Y[c].x, Z[c].x), brush_texel(p, X[c].y, Y[c].y, Z[c].y),
+                           brush_texel(p, X[c].z, Y[c].z, Z[c].z), brush_texel(p, X[c].w, Y[c].w, Z[c].w)};
+        out.put4(base + c * kChunk, s, true);
     }
 }
 
@@ -101,21 +71,14 @@ __global__ __launch_bounds__(kBlock) void k_brush(const float *__restrict__ px, 
 // Texels beyond the atlas read as NaN positions, which no lasso selects, so
 // edge blocks take the same wave-wide path with bounds-checked loads and
 // stores; atlases whose width is not a multiple of 4 use those loads
-// everywhere (rows are then not 16-byte aligned).
+// everywhere (rows are then not 16-byte aligned).  The 8 lanes of a row hold
+// one mask word of a numeric layer when the width is a multiple of 32.
 constexpr int kLassoRows = 32, kLassoCols = 128;
 
-template <typename T>
-__device__ __forceinline__ void store_masked(T *__restrict__ L, int64_t t, int nvalid, const bool s[4], T label) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        if (k < nvalid && s[k]) L[t + k] = label;
-}
-
-template <typename T>
+template <typename Sink>
 __global__ __launch_bounds__(kBlock) void k_lasso(const float *__restrict__ px, const float *__restrict__ py,
-                                                  const float *__restrict__ pz, T *__restrict__ L, int32_t W,
-                                                  int32_t H, LassoParams p, const float *__restrict__ depth,
-                                                  uint32_t label) {
+                                                  const float *__restrict__ pz, Sink out, int32_t W,
+                                                  int32_t H, LassoParams p, const float *__restrict__ depth) {
     const int lane = threadIdx.x & 63;
     const int x = blockIdx.x * kLassoCols + (threadIdx.x >> 6) * 32 + (lane & 7) * 4;
     const int y0 = blockIdx.y * kLassoRows + (lane >> 3);
@@ -166,9 +129,9 @@ __global__ __launch_bounds__(kBlock) void k_lasso(const float *__restrict__ px, 
         const int y = y0 + 8 * c;
         const int64_t t = (int64_t)y * W + x;
         if (vec)
-            store4<T>(L, t, s[0], s[1], s[2], s[3], (T)label);
+            out.put4(t, s, (W & 31) == 0);
         else if (y < H)
-            store_masked<T>(L, t, W - x, s, (T)label);
+            out.put_some(t, W - x, s);
     }
 }
 
@@ -278,41 +241,75 @@ bool make_lasso_params(const float view_proj[16], const float *poly, int32_t n, 
 
 using namespace uvl;
 
+namespace {
+
+template <typename Sink>
+void launch_brush(const uvl_geom *geom, const float center[3], float radius, const Sink &out, hipStream_t s) {
+    const int64_t n = (int64_t)geom->width * geom->height;
+    const BrushParams p{center[0], center[1], center[2], radius * radius};
+    hipLaunchKernelGGL(k_brush<Sink>, dim3((unsigned)ceil_div(n, kTile)), dim3(kBlock), 0, s, geom->pos_x,
+                       geom->pos_y, geom->pos_z, out, n, p);
+}
+
+template <typename Sink>
+void launch_lasso(const uvl_geom *geom, const LassoParams &p, const float *depth, const Sink &out, hipStream_t s) {
+    const int32_t W = geom->width, H = geom->height;
+    const dim3 grid((unsigned)ceil_div(W, kLassoCols), (unsigned)ceil_div(H, kLassoRows));
+    hipLaunchKernelGGL(k_lasso<Sink>, grid, dim3(kBlock), 0, s, geom->pos_x, geom->pos_y, geom->pos_z, out, W, H,
+                       p, depth);
+}
+
+bool brush_args_ok(const float center[3], float radius) {
+    return center && radius >= 0.0f && std::isfinite(radius) && std::isfinite(center[0]) &&
+           std::isfinite(center[1]) && std::isfinite(center[2]);
+}
+
+// Lasso arguments shared by the label and numeric calls.
+bool lasso_args(const float view_proj[16], const float *poly_xy, int32_t n, const float *depth, int32_t dw,
+                int32_t dh, float bias, LassoParams &p) {
+    if (!depth || dw > kMaxDepthSide || dh > kMaxDepthSide) return false;
+    if (!make_lasso_params(view_proj, poly_xy, n, dw, dh, bias, p)) return false;
+    for (int k = 0; k < 16; ++k)
+        if (!std::isfinite(view_proj[k])) return false;
+    return true;
+}
+
+}  // namespace
+
 extern "C" int32_t uvl_edit_brush(const uvl_geom *geom, const uvl_layer *layer, const float center[3],
                                   float radius, uint32_t label, void *stream) {
-    if (!center || !(radius >= 0.0f) || !std::isfinite(radius)) return UVL_E_INVAL;
-    if (!std::isfinite(center[0]) || !std::isfinite(center[1]) || !std::isfinite(center[2])) return UVL_E_INVAL;
+    if (!brush_args_ok(center, radius)) return UVL_E_INVAL;
     if (int32_t s = check_edit(geom, layer, label)) return s;
-    const int64_t n = (int64_t)geom->width * geom->height;
-    BrushParams p{center[0], center[1], center[2], radius * radius};
-    const dim3 grid((unsigned)ceil_div(n, kTile));
-    hipStream_t s = as_stream(stream);
-    if (layer->dtype == UVL_U8)
-        hipLaunchKernelGGL(k_brush<uint8_t>, grid, dim3(kBlock), 0, s, geom->pos_x, geom->pos_y, geom->pos_z,
-                           static_cast<uint8_t *>(layer->data), n, p, label);
-    else
-        hipLaunchKernelGGL(k_brush<uint16_t>, grid, dim3(kBlock), 0, s, geom->pos_x, geom->pos_y, geom->pos_z,
-                           static_cast<uint16_t *>(layer->data), n, p, label);
+    with_label_sink(layer, label, [&](auto out) { launch_brush(geom, center, radius, out, as_stream(stream)); });
     return launch_status();
 }
 
 extern "C" int32_t uvl_edit_lasso(const uvl_geom *geom, const uvl_layer *layer, const float view_proj[16],
                                   const float *poly_xy, int32_t n, const float *depth, int32_t dw, int32_t dh,
                                   float bias, uint32_t label, void *stream) {
-    if (!depth || dw > kMaxDepthSide || dh > kMaxDepthSide) return UVL_E_INVAL;
     LassoParams p;
-    if (!make_lasso_params(view_proj, poly_xy, n, dw, dh, bias, p)) return UVL_E_INVAL;
-    for (int k = 0; k < 16; ++k)
-        if (!std::isfinite(view_proj[k])) return UVL_E_INVAL;
+    if (!lasso_args(view_proj, poly_xy, n, depth, dw, dh, bias, p)) return UVL_E_INVAL;
     if (int32_t s = check_edit(geom, layer, label)) return s;
-    const int32_t W = geom->width, H = geom->height;
-    const dim3 grid((unsigned)ceil_div(W, kLassoCols), (unsigned)ceil_div(H, kLassoRows));
-    hipStream_t s = as_stream(stream);
-    if (layer->dtype == UVL_U8)
-        hipLaunchKernelGGL(k_lasso<uint8_t>, grid, dim3(kBlock), 0, s, geom->pos_x, geom->pos_y, geom->pos_z,
-                           static_cast<uint8_t *>(layer->data), W, H, p, depth, label);
-    else
-        hipLaunchKernelGGL(k_lasso<uint16_t>, grid, dim3(kBlock), 0, s, geom->pos_x, geom->pos_y, geom->pos_z,
-                           static_cast<uint16_t *>(layer->data), W, H, p, depth, label);
+    with_label_sink(layer, label, [&](auto out) { launch_lasso(geom, p, depth, out, as_stream(stream)); });
+    return launch_status();
+}
+
+extern "C" int32_t uvl_numeric_brush(const uvl_geom *geom, const uvl_numeric *layer, const float center[3],
+                                     float radius, int32_t mode, double value, void *stream) {
+    if (!brush_args_ok(center, radius)) return UVL_E_INVAL;
+    uint32_t bits = 0;
+    if (int32_t s = check_numeric_edit(geom, layer, mode, value, bits)) return s;
+    with_value_sink(layer, bits, mode, [&](auto out) { launch_brush(geom, center, radius, out, as_stream(stream)); });
+    return launch_status();
+}
+
+extern "C" int32_t uvl_numeric_lasso(const uvl_geom *geom, const uvl_numeric *layer, const float view_proj[16],
+                                     const float *poly_xy, int32_t n, const float *depth, int32_t dw, int32_t dh,
+                                     float bias, int32_t mode, double value, void *stream) {
+    LassoParams p;
+    if (!lasso_args(view_proj, poly_xy, n, depth, dw, dh, bias, p)) return UVL_E_INVAL;
+    uint32_t bits = 0;
+    if (int32_t s = check_numeric_edit(geom, layer, mode, value, bits)) return s;
+    with_value_sink(layer, bits, mode, [&](auto out) { launch_lasso(geom, p, depth, out, as_stream(stream)); });
     return launch_status();
 }

@@ -1,0 +1,418 @@
+// Numeric layers for libuvl (§4.2): a data texture of integers or floats
+// with a mask texture of validity bits, one bit per texel (texel t in bit
+// t % 32 of word t / 32).
+//
+// The edits themselves are the brush, lasso and tool kernels with a value
+// sink (sink.h).  This file holds the host-side value conversion and the two
+// passes that read numeric data:
+//  - range selection, a streaming pass that turns values in [lo, hi] into a
+//    label of a label layer (quantitative to qualitative data);
+//  - zonal statistics, one streaming pass over tri_id, area_w, the data, the
+//    mask and an optional label layer that groups the texels.  Table 1 gives
+//    the surface area one texel stands for, so each group reports its count,
+//    exact area (uint64 sum of area_w), area-weighted value sum, minimum and
+//    maximum.
+//
+// Both read 16 consecutive texels per lane per step (16-byte loads of every
+// plane; the mask bits of the 16 texels sit in one word).  Statistics
+// accumulate runs: a lane keeps the running totals of its current group and
+// adds them to the group's bins only when the group changes, since labelled
+// regions are spatially coherent.  Bins of up to 256 groups live in LDS
+// (native 64-bit LDS atomics, flushed once per workgroup); 65536 groups
+// take global atomics per run.  Minima and maxima are 64-bit atomics on an
+// order-preserving encoding of the fp64 value.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "sink.h"
+#include "uvl_internal.h"
+
+namespace uvl {
+
+// ---------------------------------------------------------------------------
+// Host-side value conversion.
+
+namespace {
+
+// IEEE binary16 of a double, rounded to nearest with ties to even, from the
+// formats' bit layouts (binary64: 11-bit exponent, bias 1023, 52 fraction
+// bits; binary16: 5-bit exponent, bias 15, 10 fraction bits, subnormals of
+// spacing 2^-24 below 2^-14).  Returns false if the result is infinite.
+bool f16_from_double(double v, uint16_t &out) {
+    uint64_t b;
+    memcpy(&b, &v, sizeof b);
+    const uint16_t sign = (uint16_t)((b >> 48) & 0x8000u);
+    const int ef = (int)((b >> 52) & 0x7ff);
+    if (ef == 0x7ff) return false;
+    if (ef == 0) {                      // zero or |v| < 2^-1022: rounds to zero
+        out = sign;
+        return true;
+    }
+    const int e = ef - 1023;
+    const uint64_t m = (b & ((1ull << 52) - 1)) | (1ull << 52);   // v = m 2^(e-52)
+    int he = e < -14 ? -14 : e;         // binade of the result (subnormals share 2^-14)
+    const int shift = 42 + (he - e);    // bits of m below the result's last fraction bit
+    uint64_t q = 0;
+    if (shift < 64) {
+        q = m >> shift;
+        const uint64_t rem = m & ((1ull << shift) - 1), half = 1ull << (shift - 1);
+        if (rem > half || (rem == half && (q & 1))) ++q;
+    }
+    if (q == 2048) {                    // rounding carried into the next binade
+        q = 1024;
+        ++he;
+    }
+    if (he > 15) return false;
+    if (q < 1024) {                     // subnormal, he == -14
+        out = sign | (uint16_t)q;
+        return true;
+    }
+    out = sign | (uint16_t)((he + 15) << 10) | (uint16_t)(q - 1024);
+    return true;
+}
+
+}  // namespace
+
+int32_t encode_value(int32_t dt, double value, uint32_t &bits) {
+    if (std::isnan(value)) return UVL_E_INVAL;
+    switch (dt) {
+    case UVL_U8:
+    case UVL_U16:
+    case UVL_I32: {
+        const double lo = dt == UVL_I32 ? -2147483648.0 : 0.0;
+        const double hi = dt == UVL_U8 ? 255.0 : dt == UVL_U16 ? 65535.0 : 2147483647.0;
+        if (value != floor(value) || value < lo || value > hi) return UVL_E_DTYPE;
+        bits = dt == UVL_I32 ? (uint32_t)(int32_t)value : (uint32_t)value;
+        return UVL_OK;
+    }
+    case UVL_F16: {
+        uint16_t h;
+        if (!f16_from_double(value, h)) return UVL_E_DTYPE;
+        bits = h;
+        return UVL_OK;
+    }
+    case UVL_F32: {
+        const float f = (float)value;   // round to nearest even
+        if (!std::isfinite(f)) return UVL_E_DTYPE;
+        memcpy(&bits, &f, sizeof bits);
+        return UVL_OK;
+    }
+    default:
+        return UVL_E_DTYPE;
+    }
+}
+
+int32_t check_numeric_edit(const uvl_geom *g, const uvl_numeric *l, int32_t mode, double value, uint32_t &bits) {
+    if (!geom_pos_ok(g) || !numeric_ok(l)) return UVL_E_INVAL;
+    if (mode != UVL_SET && mode != UVL_ERASE) return UVL_E_INVAL;
+    if (l->width != g->width || l->height != g->height) return UVL_E_SHAPE;
+    bits = 0;
+    if (mode == UVL_SET)
+        if (int32_t s = encode_value(l->dtype, value, bits)) return s;
+    return device_ok();
+}
+
+// ---------------------------------------------------------------------------
+// Device side.
+
+namespace {
+
+constexpr int kPer = 16;                     // texels per lane per step
+constexpr int kStep = kBlock * kPer;         // texels per workgroup per step
+constexpr int kMaxStatBlocks = 2048;         // 8 workgroups per CU
+
+// Value of stored bits in fp64 (exact for every dtype).
+template <int32_t DT>
+__device__ __forceinline__ double decode(uint32_t b) {
+    if constexpr (DT == UVL_I32) return (double)(int32_t)b;
+    else if constexpr (DT == UVL_F32) return (double)__uint_as_float(b);
+    else if constexpr (DT == UVL_F16) return (double)(float)__builtin_bit_cast(_Float16, (uint16_t)b);
+    else return (double)b;
+}
+
+template <int32_t DT>
+using Store = typename std::conditional<DT == UVL_U8, uint8_t,
+              typename std::conditional<DT == UVL_U16 || DT == UVL_F16, uint16_t, uint32_t>::type>::type;
+
+// 16 consecutive elements from a 16-byte aligned plane.
+template <typename T>
+__device__ __forceinline__ void load16(const T *__restrict__ p, int64_t t, uint32_t out[kPer]) {
+    constexpr int kVec = 16 / sizeof(T);     // elements per 16-byte load
+#pragma unroll
+    for (int q = 0; q < kPer / kVec; ++q) {
+        const uint4 v = reinterpret_cast<const uint4 *>(p + t)[q];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < kVec; ++k) {
+            constexpr int kBits = 8 * sizeof(T);
+            out[q * kVec + k] = kBits == 32 ? w[k * kBits / 32]
+                                            : (w[k * kBits / 32] >> ((k * kBits) % 32)) & ((1u << kBits) - 1);
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_tail(const T *__restrict__ p, int64_t t, int64_t n, uint32_t out[kPer]) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) out[k] = t + k < n ? (uint32_t)p[t + k] : 0u;
+}
+
+// Mask bits of texels t .. t+15 (t a multiple of 16): one word holds them.
+__device__ __forceinline__ uint32_t mask16(const uint32_t *__restrict__ mask, int64_t t) {
+    return (mask[t >> 5] >> (t & 31)) & 0xffffu;
+}
+
+// Range selection: dst[t] = label where valid and lo <= v <= hi.
+template <int32_t DT, typename L>
+__global__ __launch_bounds__(kBlock) void k_select(const Store<DT> *__restrict__ data,
+                                                   const uint32_t *__restrict__ mask, int64_t n, double lo,
+                                                   double hi, LabelSink<L> out) {
+    const int64_t t = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kPer;
+    if (t >= n) return;
+    uint32_t v[kPer];
+    const bool full = t + kPer <= n;
+    if (full) load16(data, t, v);
+    else load_tail(data, t, n, v);
+    const uint32_t m = mask16(mask, t);
+    bool s[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const double x = decode<DT>(v[k]);
+        s[k] = ((m >> k) & 1u) && x >= lo && x <= hi;
+    }
+#pragma unroll
+    for (int g = 0; g < kPer / 4; ++g) {
+        if (full) out.put4(t + 4 * g, s + 4 * g, false);
+        else out.put_some(t + 4 * g, (int)(n - (t + 4 * g)), s + 4 * g);
+    }
+}
+
+// Statistics bins while accumulating: min and max as order-preserving keys.
+struct Bin {
+    unsigned long long count, aw;
+    double wsum;
+    unsigned long long kmin, kmax;
+};
+static_assert(sizeof(Bin) == sizeof(uvl_numstat), "bins are finalised in place");
+
+__device__ __forceinline__ unsigned long long order_key(double d) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(d);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ double from_key(unsigned long long k) {
+    const unsigned long long u = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __longlong_as_double((long long)u);
+}
+
+struct Run {
+    uint32_t label;
+    unsigned long long count, aw;
+    double wsum, vmin, vmax;
+
+    __device__ __forceinline__ void reset(uint32_t l) {
+        label = l;
+        count = aw = 0;
+        wsum = 0.0;
+        vmin = INFINITY;
+        vmax = -INFINITY;
+    }
+};
+
+// Add a run to a bin (LDS or global).
+template <bool kGlobal>
+__device__ __forceinline__ void flush(Bin *bins, const Run &r) {
+    if (r.count == 0) return;
+    Bin *b = bins + r.label;
+    atomicAdd(&b->count, r.count);
+    atomicAdd(&b->aw, r.aw);
+    if constexpr (kGlobal) unsafeAtomicAdd(&b->wsum, r.wsum);
+    else atomicAdd(&b->wsum, r.wsum);
+    atomicMin(&b->kmin, order_key(r.vmin));
+    atomicMax(&b->kmax, order_key(r.vmax));
+}
+
+__device__ __forceinline__ void bin_clear(Bin &b) {
+    b.count = b.aw = 0;
+    b.wsum = 0.0;
+    b.kmin = ~0ull;
+    b.kmax = 0;
+}
+
+__global__ void k_stats_clear(Bin *bins, int nbins) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nbins) bin_clear(bins[i]);
+}
+
+__global__ void k_stats_final(Bin *bins, int nbins) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nbins) return;
+    Bin b = bins[i];
+    uvl_numstat s;
+    s.count = b.count;
+    s.area_w = b.aw;
+    s.wsum = b.wsum;
+    s.vmin = b.count ? from_key(b.kmin) : INFINITY;
+    s.vmax = b.count ? from_key(b.kmax) : -INFINITY;
+    reinterpret_cast<uvl_numstat *>(bins)[i] = s;
+}
+
+// Zonal statistics.  R: region storage (void: no region, one group).
+// Groups of up to 256 accumulate in LDS and are flushed once per
+// workgroup; larger group counts go straight to the global bins.
+template <int32_t DT, typename R>
+__global__ __launch_bounds__(kBlock) void k_stats(const int32_t *__restrict__ tri, const uint32_t *__restrict__ aw,
+                                                  const Store<DT> *__restrict__ data,
+                                                  const uint32_t *__restrict__ mask, const R *__restrict__ region,
+                                                  int64_t n, Bin *__restrict__ bins) {
+    constexpr bool kNoRegion = std::is_same<R, void>::value;
+    constexpr bool kLds = kNoRegion || std::is_same<R, uint8_t>::value;
+    constexpr int kLdsBins = kNoRegion ? 1 : 256;
+    __shared__ Bin lds[kLds ? kLdsBins : 1];
+    if constexpr (kLds) {
+        for (int i = threadIdx.x; i < kLdsBins; i += kBlock) bin_clear(lds[i]);
+        __syncthreads();
+    }
+    Bin *target = kLds ? lds : bins;
+    Run run;
+    run.reset(0);
+    const int64_t stride = (int64_t)gridDim.x * kStep;
+    for (int64_t t = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kPer; t < n; t += stride) {
+        uint32_t tr[kPer], w[kPer], v[kPer], lab[kPer];
+        if (t + kPer <= n) {
+            load16(reinterpret_cast<const uint32_t *>(tri), t, tr);
+            load16(aw, t, w);
+            load16(data, t, v);
+            if constexpr (!kNoRegion) load16(region, t, lab);
+        } else {
+            load_tail(reinterpret_cast<const uint32_t *>(tri), t, n, tr);
+            load_tail(aw, t, n, w);
+            load_tail(data, t, n, v);
+            if constexpr (!kNoRegion) load_tail(region, t, n, lab);
+#pragma unroll
+            for (int k = 0; k < kPer; ++k)
+                if (t + k >= n) tr[k] = 0xffffffffu;      // tri_id -1: not counted
+        }
+        const uint32_t m = mask16(mask, t);
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            if ((int32_t)tr[k] < 0 || !((m >> k) & 1u)) continue;
+            const uint32_t l = kNoRegion ? 0u : lab[k];
+            if (l != run.label) {
+                flush<!kLds>(target, run);
+                run.reset(l);
+            }
+            const double x = decode<DT>(v[k]);
+            run.count += 1;
+            run.aw += w[k];
+            run.wsum += (double)w[k] * x;
+            run.vmin = fmin(run.vmin, x);
+            run.vmax = fmax(run.vmax, x);
+        }
+    }
+    flush<!kLds>(target, run);
+    if constexpr (kLds) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < kLdsBins; i += kBlock) {
+            Run r;
+            r.label = (uint32_t)i;
+            r.count = lds[i].count;
+            r.aw = lds[i].aw;
+            r.wsum = lds[i].wsum;
+            r.vmin = from_key(lds[i].kmin);
+            r.vmax = from_key(lds[i].kmax);
+            flush<true>(bins, r);
+        }
+    }
+}
+
+template <int32_t DT>
+void launch_select(const uvl_numeric *src, double lo, double hi, const uvl_layer *dst, uint32_t label,
+                   hipStream_t s) {
+    const int64_t n = (int64_t)src->width * src->height;
+    const dim3 grid((unsigned)ceil_div(n, kStep));
+    const Store<DT> *data = static_cast<const Store<DT> *>(src->data);
+    with_label_sink(dst, label, [&](auto out) {
+        using L = typename std::remove_pointer<decltype(out.L)>::type;
+        hipLaunchKernelGGL((k_select<DT, L>), grid, dim3(kBlock), 0, s, data, src->mask, n, lo, hi, out);
+    });
+}
+
+template <int32_t DT>
+void launch_stats(const uvl_geom *g, const uvl_numeric *l, const uvl_layer *region, Bin *bins, hipStream_t s) {
+    const int64_t n = (int64_t)l->width * l->height;
+    const dim3 grid((unsigned)std::min<int64_t>(ceil_div(n, kStep), kMaxStatBlocks));
+    const Store<DT> *data = static_cast<const Store<DT> *>(l->data);
+    if (!region)
+        hipLaunchKernelGGL((k_stats<DT, void>), grid, dim3(kBlock), 0, s, g->tri_id, g->area_w, data, l->mask,
+                           (const void *)nullptr, n, bins);
+    else if (region->dtype == UVL_U8)
+        hipLaunchKernelGGL((k_stats<DT, uint8_t>), grid, dim3(kBlock), 0, s, g->tri_id, g->area_w, data, l->mask,
+                           static_cast<const uint8_t *>(region->data), n, bins);
+    else
+        hipLaunchKernelGGL((k_stats<DT, uint16_t>), grid, dim3(kBlock), 0, s, g->tri_id, g->area_w, data, l->mask,
+                           static_cast<const uint16_t *>(region->data), n, bins);
+}
+
+template <typename F>
+void by_dtype(int32_t dt, F &&f) {
+    switch (dt) {
+    case UVL_U8: f(std::integral_constant<int32_t, UVL_U8>()); break;
+    case UVL_U16: f(std::integral_constant<int32_t, UVL_U16>()); break;
+    case UVL_I32: f(std::integral_constant<int32_t, UVL_I32>()); break;
+    case UVL_F16: f(std::integral_constant<int32_t, UVL_F16>()); break;
+    default: f(std::integral_constant<int32_t, UVL_F32>()); break;
+    }
+}
+
+}  // namespace
+}  // namespace uvl
+
+using namespace uvl;
+
+extern "C" int32_t uvl_numeric_create(const uvl_numeric *layer, void *stream) {
+    if (!numeric_ok(layer)) return UVL_E_INVAL;
+    if (int32_t s = device_ok()) return s;
+    hipStream_t s = as_stream(stream);
+    fill_bytes(layer->data, (int64_t)layer->width * layer->height * dtype_bytes(layer->dtype), s);
+    fill_bytes(layer->mask, mask_words(layer) * 4, s);
+    return launch_status();
+}
+
+extern "C" int32_t uvl_numeric_select(const uvl_numeric *src, double lo, double hi, const uvl_layer *dst,
+                                      uint32_t label, void *stream) {
+    if (!numeric_ok(src) || !layer_ok(dst) || std::isnan(lo) || std::isnan(hi)) return UVL_E_INVAL;
+    if (!dtype_ok(dst->dtype) || label > dtype_max(dst->dtype)) return UVL_E_DTYPE;
+    if (dst->width != src->width || dst->height != src->height) return UVL_E_SHAPE;
+    if (int32_t s = device_ok()) return s;
+    by_dtype(src->dtype, [&](auto dt) { launch_select<decltype(dt)::value>(src, lo, hi, dst, label, as_stream(stream)); });
+    return launch_status();
+}
+
+extern "C" int32_t uvl_numeric_stats(const uvl_geom *geom, const uvl_numeric *layer, const uvl_layer *region,
+                                     uvl_numstat *bins_dev, uvl_numstat *bins_host, void *stream) {
+    if (!geom || !geom->tri_id || !geom->area_w || !aligned16(geom->tri_id) || !aligned16(geom->area_w))
+        return UVL_E_INVAL;
+    if (!numeric_ok(layer) || !bins_dev || (reinterpret_cast<uintptr_t>(bins_dev) & 7)) return UVL_E_INVAL;
+    if (region && !layer_ok(region)) return UVL_E_INVAL;
+    if (region && !dtype_ok(region->dtype)) return UVL_E_DTYPE;
+    if (layer->width != geom->width || layer->height != geom->height) return UVL_E_SHAPE;
+    if (region && (region->width != geom->width || region->height != geom->height)) return UVL_E_SHAPE;
+    if (int32_t s = device_ok()) return s;
+    const int nbins = !region ? 1 : region->dtype == UVL_U8 ? 256 : 65536;
+    hipStream_t s = as_stream(stream);
+    Bin *bins = reinterpret_cast<Bin *>(bins_dev);
+    hipLaunchKernelGGL(k_stats_clear, dim3((unsigned)ceil_div(nbins, kBlock)), dim3(kBlock), 0, s, bins, nbins);
+    by_dtype(layer->dtype, [&](auto dt) { launch_stats<decltype(dt)::value>(geom, layer, region, bins, s); });
+    hipLaunchKernelGGL(k_stats_final, dim3((unsigned)ceil_div(nbins, kBlock)), dim3(kBlock), 0, s, bins, nbins);
+    if (int32_t st = launch_status()) return st;
+    if (bins_host) {
+        if (hipMemcpyAsync(bins_host, bins_dev, sizeof(uvl_numstat) * nbins, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return UVL_E_DEVICE;
+    }
+    return UVL_OK;
+}

@@ -20,6 +20,7 @@
 #include <math.h>
 
 #include "edit_texel.h"
+#include "sink.h"
 #include "uvl_internal.h"
 
 namespace uvl {
@@ -67,17 +68,16 @@ __device__ __forceinline__ bool tool_texel(const ToolParams &P, const uint8_t *_
     return d <= depth[(int64_t)iy * P.dw + ix] + P.bias;
 }
 
-template <typename T>
+template <typename Sink>
 __global__ __launch_bounds__(kBlock) void k_tool(const float *__restrict__ px, const float *__restrict__ py,
-                                                 const float *__restrict__ pz, T *__restrict__ L, int64_t n,
-                                                 ToolParams p, const uint8_t *__restrict__ shape,
-                                                 const float *__restrict__ depth, uint32_t label) {
+                                                 const float *__restrict__ pz, Sink out, int64_t n, ToolParams p,
+                                                 const uint8_t *__restrict__ shape, const float *__restrict__ depth) {
     const int64_t base = (int64_t)blockIdx.x * kTile + threadIdx.x * 4;
     if ((int64_t)(blockIdx.x + 1) * kTile > n) {
         for (int c = 0; c < 4; ++c)
             for (int k = 0; k < 4; ++k) {
                 const int64_t t = base + c * kChunk + k;
-                if (t < n && tool_texel(p, shape, depth, px[t], py[t], pz[t])) L[t] = (T)label;
+                if (t < n && tool_texel(p, shape, depth, px[t], py[t], pz[t])) out.put1(t);
             }
         return;
     }
@@ -90,11 +90,11 @@ __global__ __launch_bounds__(kBlock) void k_tool(const float *__restrict__ px, c
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        const float xs[4] = {X[c].x, X[c].y, X[c].z, X[c].w}, ys[4] = {Y[c].x, Y[c].y, Y[c].z, Y[c].w};
-        const float zs[4] = {Z[c].x, Z[c].y, Z[c].z, Z[c].w};
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (tool_texel(p, shape, depth, xs[k], ys[k], zs[k])) L[base + c * kChunk + k] = (T)label;
+        const bool s[4] = {tool_texel(p, shape, depth, X[c].x, Y[c].x, Z[c].x),
+                           tool_texel(p, shape, depth, X[c].y, Y[c].y, Z[c].y),
+                           tool_texel(p, shape, depth, X[c].z, Y[c].z, Z[c].z),
+                           tool_texel(p, shape, depth, X[c].w, Y[c].w, Z[c].w)};
+        out.put4(base + c * kChunk, s, true);      // lanes 8g..8g+7: one 32-aligned word
     }
 }
 
@@ -115,23 +115,19 @@ void tool_range(double a, double b, float &lo, float &hi) {
 
 using namespace uvl;
 
-extern "C" int32_t uvl_edit_tool(const uvl_geom *geom, const uvl_layer *layer, const float view_proj[16],
-                                 const double tool[6], const uint8_t *shape, int32_t sw, int32_t sh,
-                                 const float *depth, int32_t dw, int32_t dh, float bias, uint32_t label,
-                                 void *stream) {
-    if (!view_proj || !tool || !shape || !depth) return UVL_E_INVAL;
+namespace {
+
+// Tool arguments shared by the label and numeric calls.
+bool tool_args(const float view_proj[16], const double tool[6], const uint8_t *shape, int32_t sw, int32_t sh,
+               const float *depth, int32_t dw, int32_t dh, float bias, ToolParams &p) {
+    if (!view_proj || !tool || !shape || !depth) return false;
     for (int k = 0; k < 16; ++k)
-        if (!std::isfinite(view_proj[k])) return UVL_E_INVAL;
+        if (!std::isfinite(view_proj[k])) return false;
     for (int k = 0; k < 6; ++k)
-        if (!std::isfinite(tool[k])) return UVL_E_INVAL;
-    if (!(tool[0] > 0.0 && tool[1] > 0.0 && tool[4] > 0.0 && tool[5] > 0.0)) return UVL_E_INVAL;
-    if (sw < 1 || sh < 1 || sw > kMaxShape || sh > kMaxShape) return UVL_E_INVAL;
-    if (dw < 1 || dh < 1 || dw > kMaxDepthSide || dh > kMaxDepthSide || !std::isfinite(bias)) return UVL_E_INVAL;
-    if (!geom_pos_ok(geom) || !layer_ok(layer)) return UVL_E_INVAL;
-    if (!dtype_ok(layer->dtype) || label > dtype_max(layer->dtype)) return UVL_E_DTYPE;
-    if (layer->width != geom->width || layer->height != geom->height) return UVL_E_SHAPE;
-    if (int32_t s = device_ok()) return s;
-    ToolParams p;
+        if (!std::isfinite(tool[k])) return false;
+    if (!(tool[0] > 0.0 && tool[1] > 0.0 && tool[4] > 0.0 && tool[5] > 0.0)) return false;
+    if (sw < 1 || sh < 1 || sw > kMaxShape || sh > kMaxShape) return false;
+    if (dw < 1 || dh < 1 || dw > kMaxDepthSide || dh > kMaxDepthSide || !std::isfinite(bias)) return false;
     for (int k = 0; k < 16; ++k) p.M[k] = view_proj[k];
     const double ax = tool[0] / (2.0 * tool[4]), bx = 0.5 - (tool[2] - 0.5 * tool[0]) / tool[4];
     const double ay = tool[1] / (2.0 * tool[5]), by = 0.5 - (tool[3] - 0.5 * tool[1]) / tool[5];
@@ -147,14 +143,41 @@ extern "C" int32_t uvl_edit_tool(const uvl_geom *geom, const uvl_layer *layer, c
     p.dw = dw;
     p.dh = dh;
     p.bias = bias;
+    return true;
+}
+
+template <typename Sink>
+void launch_tool(const uvl_geom *geom, const ToolParams &p, const uint8_t *shape, const float *depth, const Sink &out,
+                 hipStream_t s) {
     const int64_t n = (int64_t)geom->width * geom->height;
-    const dim3 grid((unsigned)ceil_div(n, kTile));
-    hipStream_t s = as_stream(stream);
-    if (layer->dtype == UVL_U8)
-        hipLaunchKernelGGL(k_tool<uint8_t>, grid, dim3(kBlock), 0, s, geom->pos_x, geom->pos_y, geom->pos_z,
-                           static_cast<uint8_t *>(layer->data), n, p, shape, depth, label);
-    else
-        hipLaunchKernelGGL(k_tool<uint16_t>, grid, dim3(kBlock), 0, s, geom->pos_x, geom->pos_y, geom->pos_z,
-                           static_cast<uint16_t *>(layer->data), n, p, shape, depth, label);
+    hipLaunchKernelGGL(k_tool<Sink>, dim3((unsigned)ceil_div(n, kTile)), dim3(kBlock), 0, s, geom->pos_x,
+                       geom->pos_y, geom->pos_z, out, n, p, shape, depth);
+}
+
+}  // namespace
+
+extern "C" int32_t uvl_edit_tool(const uvl_geom *geom, const uvl_layer *layer, const float view_proj[16],
+                                 const double tool[6], const uint8_t *shape, int32_t sw, int32_t sh,
+                                 const float *depth, int32_t dw, int32_t dh, float bias, uint32_t label,
+                                 void *stream) {
+    ToolParams p;
+    if (!tool_args(view_proj, tool, shape, sw, sh, depth, dw, dh, bias, p)) return UVL_E_INVAL;
+    if (!geom_pos_ok(geom) || !layer_ok(layer)) return UVL_E_INVAL;
+    if (!dtype_ok(layer->dtype) || label > dtype_max(layer->dtype)) return UVL_E_DTYPE;
+    if (layer->width != geom->width || layer->height != geom->height) return UVL_E_SHAPE;
+    if (int32_t s = device_ok()) return s;
+    with_label_sink(layer, label, [&](auto out) { launch_tool(geom, p, shape, depth, out, as_stream(stream)); });
+    return launch_status();
+}
+
+extern "C" int32_t uvl_numeric_tool(const uvl_geom *geom, const uvl_numeric *layer, const float view_proj[16],
+                                    const double tool[6], const uint8_t *shape, int32_t sw, int32_t sh,
+                                    const float *depth, int32_t dw, int32_t dh, float bias, int32_t mode,
+                                    double value, void *stream) {
+    ToolParams p;
+    if (!tool_args(view_proj, tool, shape, sw, sh, depth, dw, dh, bias, p)) return UVL_E_INVAL;
+    uint32_t bits = 0;
+    if (int32_t s = check_numeric_edit(geom, layer, mode, value, bits)) return s;
+    with_value_sink(layer, bits, mode, [&](auto out) { launch_tool(geom, p, shape, depth, out, as_stream(stream)); });
     return launch_status();
 }

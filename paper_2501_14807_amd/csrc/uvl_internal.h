@@ -31,10 +31,31 @@ inline bool dtype_ok(int32_t dt) { return dt == UVL_U8 || dt == UVL_U16; }
 
 inline uint32_t dtype_max(int32_t dt) { return dt == UVL_U8 ? 0xffu : 0xffffu; }
 
+// Bytes per texel of a layer dtype (any of the five).
+inline int dtype_bytes(int32_t dt) { return dt == UVL_U8 ? 1 : (dt == UVL_U16 || dt == UVL_F16) ? 2 : 4; }
+
 inline bool layer_ok(const uvl_layer *l) {
     return l && l->data && l->width >= 1 && l->height >= 1 && l->width <= kMaxSide &&
            l->height <= kMaxSide && aligned16(l->data);
 }
+
+inline bool numeric_ok(const uvl_numeric *l) {
+    return l && l->data && l->mask && l->width >= 1 && l->height >= 1 && l->width <= kMaxSide &&
+           l->height <= kMaxSide && aligned16(l->data) && aligned16(l->mask) && l->dtype >= UVL_U8 &&
+           l->dtype <= UVL_F32;
+}
+
+// Mask words of a numeric layer.
+inline int64_t mask_words(const uvl_numeric *l) { return ceil_div((int64_t)l->width * l->height, 32); }
+
+// The stored bit pattern of `value` in dtype `dt` (numeric.hip): integral
+// and in range for the integer dtypes, rounded to nearest even and finite
+// for the float dtypes.  UVL_E_INVAL for NaN, UVL_E_DTYPE if it does not fit.
+int32_t encode_value(int32_t dt, double value, uint32_t &bits);
+
+// Validation shared by the numeric edits: geometry and layer, matching
+// sizes, mode, value; fills bits.  Also checks the device.
+int32_t check_numeric_edit(const uvl_geom *g, const uvl_numeric *l, int32_t mode, double value, uint32_t &bits);
 
 // The position planes every edit reads.
 inline bool geom_pos_ok(const uvl_geom *g) {

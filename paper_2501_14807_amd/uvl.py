@@ -19,8 +19,9 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libuvl.so")
 
-U8, U16 = 1, 2
+U8, U16, I32, F16, F32 = 1, 2, 3, 4, 5
 AND, OR, XOR, REMAP = 0, 1, 2, 3
+SET, ERASE = 0, 1
 
 STATUS = {0: "UVL_OK", -1: "UVL_E_INVAL", -2: "UVL_E_SHAPE", -3: "UVL_E_DTYPE",
           -4: "UVL_E_NOMEM", -5: "UVL_E_DEVICE", -6: "UVL_E_UNSUPPORTED"}
@@ -55,12 +56,22 @@ class CLayer(ctypes.Structure):
                 ("dtype", ctypes.c_int32)]
 
 
+class CNumeric(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("dtype", ctypes.c_int32)]
+
+
+# uvl_numstat
+NUMSTAT = np.dtype([("count", np.uint64), ("area_w", np.uint64), ("wsum", np.float64), ("vmin", np.float64),
+                    ("vmax", np.float64)])
+
 _L = None
 
 # exported names and ctypes signatures; the CPU tests check that include/uvl.h
 # declares exactly these
 _P, _I32, _I64, _U32, _F32, _SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
                                    ctypes.c_float, ctypes.c_size_t)
+_F64 = ctypes.c_double
 SIGNATURES = {
     "uvl_status_str": ([_I32], ctypes.c_char_p),
     "uvl_device_check": ([], _I32),
@@ -85,6 +96,12 @@ SIGNATURES = {
     "uvl_build_outline": ([_P, _I32, _P, _I64, _P, _P, _SZ, _P], _I32),
     "uvl_pad_brush": ([_P, _P, _P, _I64, _I32, _P, _F32, _U32, _P], _I32),
     "uvl_pad_lasso": ([_P, _P, _P, _I64, _I32, _P, _P, _I32, _P, _I32, _I32, _F32, _U32, _P], _I32),
+    "uvl_numeric_create": ([_P, _P], _I32),
+    "uvl_numeric_brush": ([_P, _P, _P, _F32, _I32, _F64, _P], _I32),
+    "uvl_numeric_lasso": ([_P, _P, _P, _P, _I32, _P, _I32, _I32, _F32, _I32, _F64, _P], _I32),
+    "uvl_numeric_tool": ([_P, _P, _P, _P, _P, _I32, _I32, _P, _I32, _I32, _F32, _I32, _F64, _P], _I32),
+    "uvl_numeric_select": ([_P, _F64, _F64, _P, _U32, _P], _I32),
+    "uvl_numeric_stats": ([_P, _P, _P, _P, _P, _P], _I32),
 }
 
 EDIT_BRUSH, EDIT_LASSO = 0, 1
@@ -261,6 +278,47 @@ class Layer:
         self.data[:self.n].copy_(t.to(self.data.dtype))
 
 
+_TORCH_DTYPE = {U8: torch.uint8, U16: torch.uint16, I32: torch.int32, F16: torch.float16, F32: torch.float32}
+_NP_DTYPE = {U8: np.uint8, U16: np.uint16, I32: np.int32, F16: np.float16, F32: np.float32}
+
+
+class NumericLayer:
+    """A numeric layer: width*height values of dtype (U8, U16, I32, F16,
+    F32) and a mask of one validity bit per texel (bit t % 32 of word t / 32)."""
+
+    def __init__(self, width: int, height: int, dtype: int = F32, device="cuda"):
+        self.width, self.height, self.dtype = int(width), int(height), int(dtype)
+        if self.dtype not in _TORCH_DTYPE:
+            raise ValueError(f"dtype {dtype}")
+        n = self.width * self.height
+        self.data = torch.empty(_pad(n), dtype=_TORCH_DTYPE[self.dtype], device=device)
+        self.mask = torch.empty(_pad((n + 31) // 32), dtype=torch.int32, device=device)
+        self.c = CNumeric(self.data.data_ptr(), self.mask.data_ptr(), self.width, self.height, self.dtype)
+
+    @property
+    def n(self) -> int:
+        return self.width * self.height
+
+    def numpy(self) -> np.ndarray:
+        return self.data[:self.n].cpu().numpy()
+
+    def mask_words(self) -> np.ndarray:
+        return self.mask[:(self.n + 31) // 32].cpu().numpy().view(np.uint32)
+
+    def valid(self) -> np.ndarray:
+        w = self.mask_words().astype(np.uint64)
+        bits = (w[:, None] >> np.arange(32, dtype=np.uint64)) & np.uint64(1)
+        return bits.reshape(-1)[:self.n].astype(bool)
+
+    def copy_from(self, data: np.ndarray, valid: np.ndarray):
+        """Upload values and validity flags (one per texel)."""
+        self.data[:self.n].copy_(torch.from_numpy(np.ascontiguousarray(data, _NP_DTYPE[self.dtype])))
+        v = np.zeros(((self.n + 31) // 32) * 32, np.uint64)
+        v[:self.n] = np.asarray(valid, bool)
+        words = (v.reshape(-1, 32) << np.arange(32, dtype=np.uint64)).sum(axis=1).astype(np.uint32)
+        self.mask[:words.size].copy_(torch.from_numpy(words.view(np.int32)))
+
+
 # ---------------------------------------------------------------------------
 # the C entry points, one function each
 
@@ -328,6 +386,68 @@ def edit_tool(geom: GeometryImage, layer: Layer, view_proj, tool, shape: torch.T
     _check(_lib().uvl_edit_tool(ctypes.byref(geom.c), ctypes.byref(layer.c), M.ctypes.data_as(ctypes.c_void_p),
                                 tp.ctypes.data_as(ctypes.c_void_p), _ptr(shape), sw, sh, _ptr(depth), dw, dh,
                                 float(np.float32(bias)), int(label), _stream(stream)), "uvl_edit_tool")
+
+
+def numeric_create(layer: NumericLayer, stream=None) -> NumericLayer:
+    _check(_lib().uvl_numeric_create(ctypes.byref(layer.c), _stream(stream)), "uvl_numeric_create")
+    return layer
+
+
+def numeric_brush(geom: GeometryImage, layer: NumericLayer, center, radius: float, mode: int, value: float = 0.0,
+                  stream=None):
+    c = _f32(center, 3)
+    _check(_lib().uvl_numeric_brush(ctypes.byref(geom.c), ctypes.byref(layer.c), c.ctypes.data_as(ctypes.c_void_p),
+                                    float(np.float32(radius)), int(mode), float(value), _stream(stream)),
+           "uvl_numeric_brush")
+
+
+def numeric_lasso(geom: GeometryImage, layer: NumericLayer, view_proj, poly, depth: torch.Tensor, bias: float,
+                  mode: int, value: float = 0.0, stream=None):
+    M = _f32(view_proj, 16)
+    P = _f32(poly).reshape(-1)
+    dh, dw = depth.shape
+    _check(_lib().uvl_numeric_lasso(ctypes.byref(geom.c), ctypes.byref(layer.c), M.ctypes.data_as(ctypes.c_void_p),
+                                    P.ctypes.data_as(ctypes.c_void_p), P.size // 2, _ptr(depth), dw, dh,
+                                    float(np.float32(bias)), int(mode), float(value), _stream(stream)),
+           "uvl_numeric_lasso")
+
+
+def numeric_tool(geom: GeometryImage, layer: NumericLayer, view_proj, tool, shape: torch.Tensor, depth: torch.Tensor,
+                 bias: float, mode: int, value: float = 0.0, stream=None):
+    M = _f32(view_proj, 16)
+    tp = np.ascontiguousarray(np.asarray(tool, dtype=np.float64))
+    if tp.size != 6 or shape.dtype != torch.uint8 or shape.dim() != 2 or not shape.is_contiguous():
+        raise ValueError("tool needs 6 numbers and a contiguous uint8 [sh, sw] shape")
+    sh, sw = shape.shape
+    dh, dw = depth.shape
+    _check(_lib().uvl_numeric_tool(ctypes.byref(geom.c), ctypes.byref(layer.c), M.ctypes.data_as(ctypes.c_void_p),
+                                   tp.ctypes.data_as(ctypes.c_void_p), _ptr(shape), sw, sh, _ptr(depth), dw, dh,
+                                   float(np.float32(bias)), int(mode), float(value), _stream(stream)),
+           "uvl_numeric_tool")
+
+
+def numeric_select(src: NumericLayer, lo: float, hi: float, dst: Layer, label: int, stream=None):
+    _check(_lib().uvl_numeric_select(ctypes.byref(src.c), float(lo), float(hi), ctypes.byref(dst.c), int(label),
+                                     _stream(stream)), "uvl_numeric_select")
+
+
+def numeric_stats(geom: GeometryImage, layer: NumericLayer, region: Optional[Layer] = None,
+                  bins: Optional[torch.Tensor] = None, host: bool = True, stream=None):
+    """Zonal statistics: a NUMSTAT record per value of `region` (one when
+    None).  host=True returns them as a numpy array (synchronous); host=False
+    leaves them in `bins` (a device tensor of >= 40 bytes per group) and
+    returns that tensor."""
+    groups = 1 if region is None else (256 if region.dtype == U8 else 65536)
+    if bins is None:
+        bins = torch.empty(groups * NUMSTAT.itemsize, dtype=torch.uint8, device=layer.data.device)
+    if bins.numel() * bins.element_size() < groups * NUMSTAT.itemsize:
+        raise ValueError("bins too small")
+    out = np.empty(groups, NUMSTAT) if host else None
+    _check(_lib().uvl_numeric_stats(ctypes.byref(geom.c), ctypes.byref(layer.c),
+                                    None if region is None else ctypes.byref(region.c), _ptr(bins),
+                                    None if out is None else out.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
+           "uvl_numeric_stats")
+    return out if host else bins
 
 
 def disk_shape(n: int = 256, device="cuda") -> torch.Tensor:

@@ -223,3 +223,44 @@ def test_tool_validation(uvl):
     assert call(dw=0) == -1 and call(bias=float("inf")) == -1
     assert call(label=256) == -3
     assert call(layer=_layer(uvl, h=31)) == -2
+
+
+def test_numeric_validation(uvl):
+    """Numeric layers: every argument error is caught on the host, before the
+    device check (which fails here without a GPU: -5 or -6 means the
+    arguments passed)."""
+    L = uvl.lib()
+    g = _geom(uvl)
+    c = (ctypes.c_float * 3)(0.0, 0.0, 0.0)
+    passed = (-5, -6, 0)
+
+    def nl(dt=uvl.F32, w=64, h=32, mask=FAKE):
+        return uvl.CNumeric(FAKE, mask, w, h, dt)
+
+    def brush(layer, mode=uvl.SET, value=1.0):
+        return L.uvl_numeric_brush(ctypes.byref(g), ctypes.byref(layer), c, 1.0, mode, value, None)
+
+    assert brush(nl(dt=6)) == -1 and brush(nl(dt=0)) == -1
+    assert brush(nl(mask=None)) == -1 and brush(nl(mask=FAKE + 4)) == -1
+    assert brush(nl(), mode=2) == -1
+    assert brush(nl(), value=float("nan")) == -1
+    assert brush(nl(), mode=uvl.ERASE, value=float("nan")) in passed
+    assert brush(nl(h=31)) == -2
+    for dt, bad, good in ((uvl.U8, 256, 255), (uvl.U8, -1, 0), (uvl.U16, 65536, 65535), (uvl.I32, 1.5, -7),
+                          (uvl.I32, 2.0 ** 31, -2.0 ** 31), (uvl.F16, 65520.0, 65519.0),
+                          (uvl.F32, 1e39, 3.4e38), (uvl.F32, float("inf"), -1e-45)):
+        assert brush(nl(dt=dt), value=bad) == -3, (dt, bad)
+        assert brush(nl(dt=dt), value=good) in passed, (dt, good)
+    src, dst = nl(), _layer(uvl)
+    sel = lambda lo=0.0, hi=1.0, d=dst, label=1: L.uvl_numeric_select(ctypes.byref(src), lo, hi, ctypes.byref(d),
+                                                                      label, None)
+    assert sel(lo=float("nan")) == -1 and sel(hi=float("nan")) == -1
+    assert sel(d=_layer(uvl, dt=3)) == -3 and sel(label=256) == -3
+    assert sel(d=_layer(uvl, w=32)) == -2
+    assert sel(lo=2.0, hi=1.0) in passed
+    st = lambda region=None, bins=FAKE, layer=src: L.uvl_numeric_stats(
+        ctypes.byref(g), ctypes.byref(layer), None if region is None else ctypes.byref(region), bins, None, None)
+    assert st(bins=None) == -1 and st(bins=FAKE + 4) == -1
+    assert st(region=_layer(uvl, dt=3)) == -3 and st(region=_layer(uvl, h=16)) == -2
+    assert st(layer=nl(w=32)) == -2
+    assert st() in passed and st(region=_layer(uvl, dt=2)) in passed
