@@ -189,9 +189,13 @@ def stats(tri_id: np.ndarray, w: np.ndarray, layer: NumericLayer, region=None) -
     out = np.zeros(nb, STATS_DTYPE)
     out["vmin"] = np.inf
     out["vmax"] = -np.inf
-    for b in np.unique(lab[keep]):
-        s = keep & (lab == b)
-        vb, wb = v[s], np.asarray(w, np.float64)[s]
-        out[b] = (s.sum(), math.fsum(wb), math.fsum(wb * vb), vb.min(), vb.max(),
-                  math.fsum(np.abs(wb * vb)), math.fsum(np.abs(vb)))
+    w = np.asarray(w, np.float64)
+    idx = np.flatnonzero(keep)
+    idx = idx[np.argsort(lab[idx], kind="stable")]          # texels grouped by label
+    for grp in np.split(idx, np.flatnonzero(np.diff(lab[idx])) + 1):
+        if grp.size == 0:
+            continue
+        vb, wb = v[grp], w[grp]
+        out[lab[grp[0]]] = (grp.size, math.fsum(wb), math.fsum(wb * vb), vb.min(), vb.max(),
+                            math.fsum(np.abs(wb * vb)), math.fsum(np.abs(vb)))
     return out
