@@ -17,8 +17,9 @@ editing pass).  Per-kernel durations come from HIP events recorded on the
 launch stream around every launch inside the timed steps.
 
 Beside the step, untimed by the step's clock and reported in their own
-fields: the paper's screen-space tool and texture padding on the same model,
-the batched-wave comparison (256 models of uneven size, one launch per edit
+fields: the paper's screen-space tool, texture padding and numeric layers
+(a value lasso, zonal statistics, range selection) on the same model, the
+batched-wave comparison (256 models of uneven size, one launch per edit
 against one wave) and the serving comparison (32 + 32 resident models,
 Poisson requests swept over rates, p50/p99 and edits/s, plain against
 continuous batching), then the oracle on a bounded sample (`cpu_baseline`).
@@ -330,6 +331,51 @@ def bench_padding(m, wl, uvl, torch, n_edits=200):
             "pad_lasso_us": float(np.mean(per["lasso"])) if per["lasso"] else None}
 
 
+def bench_numeric(m, wl, uvl, torch, n_edits=100, reps=10):
+    """Numeric layers (§4.2) on the workload's model: a binary32 layer with a
+    validity mask.  Per-launch time of a lasso that SETs a value (next to the
+    same lasso on a label layer), of zonal statistics (no region, the u8
+    and u16 label layers as regions) and of a range selection, with the
+    bytes each streams: statistics read tri_id, area_w and the data (4
+    bytes each per texel), the mask (1/8) and the region (1 or 2); the
+    selection reads the data and the mask."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, k=1):
+        fn()
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / k
+
+    N = wl.W * wl.H
+    L = uvl.numeric_create(uvl.NumericLayer(wl.W, wl.H, uvl.F32))
+    lab = uvl.create_layer(uvl.Layer(wl.W, wl.H, uvl.U8))
+    t_num, t_lab = [], []
+    for i, e in enumerate([e for e in wl.edits if e.kind == "lasso"][:n_edits]):
+        M = wl.cameras[e.camera]
+        d = m.depth_for(e.camera, M)
+        t_num.append(timed(lambda: uvl.numeric_lasso(m.geom, L, M, e.poly, d, m.bias, uvl.SET, 0.5 + i)))
+        t_lab.append(timed(lambda: uvl.edit_lasso(m.geom, lab, M, e.poly, d, m.bias, 1 + i % 200)))
+    rng = np.random.default_rng(6001)
+    L.copy_from(rng.normal(0.0, 1.0, N).astype(np.float32), rng.random(N) < 0.9)
+    bins = torch.empty(65536 * uvl.NUMSTAT.itemsize, dtype=torch.uint8, device="cuda")
+    stats = {}
+    regions = [("none", None, 0)] + [(("u8" if l.dtype == uvl.U8 else "u16"), l, 1 if l.dtype == uvl.U8 else 2)
+                                     for l in m.layers]
+    for name, reg, rb in regions:
+        if name in stats:
+            continue
+        us = timed(lambda: uvl.numeric_stats(m.geom, L, reg, bins, host=False), reps)
+        stats[name] = {"us": us, "gbps": N * (12.125 + rb) / (us * 1e-6) / 1e9}
+    sel_us = timed(lambda: uvl.numeric_select(L, -0.5, 0.5, lab, 7), reps)
+    return {"dtype": "f32", "lasso_edits": len(t_num), "lasso_set_us": float(np.mean(t_num)),
+            "label_lasso_us": float(np.mean(t_lab)), "stats": stats,
+            "select_us": sel_us, "select_gbps": N * 4.125 / (sel_us * 1e-6) / 1e9}
+
+
 def copy_bandwidth(torch, nbytes=2 << 30, reps=10):
     """Achievable HBM bandwidth of a plain device-to-device copy (read + write)."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -456,6 +502,10 @@ def main():
     padding = bench_padding(m, wl, uvl, torch)
     log(f"padding: {padding['outline_texels']} outline texels, brush {padding['pad_brush_us']:.1f} us, "
         f"lasso {padding['pad_lasso_us']:.1f} us per edit")
+    numeric = bench_numeric(m, wl, uvl, torch)
+    log(f"numeric f32: lasso SET {numeric['lasso_set_us']:.1f} us (label {numeric['label_lasso_us']:.1f} us), "
+        + ", ".join(f"stats[{k}] {v['us']:.1f} us {v['gbps']:.0f} GB/s" for k, v in numeric["stats"].items())
+        + f", select {numeric['select_us']:.1f} us")
     copy_gbps = copy_bandwidth(torch)
     log(f"device copy bandwidth {copy_gbps:.0f} GB/s")
     batched = None
@@ -492,6 +542,7 @@ def main():
         "copy_gbps": copy_gbps,
         "tool": tool,
         "padding": padding,
+        "numeric": numeric,
         "batched": batched,
         "serving": serving,
     }

@@ -17,10 +17,11 @@
 // plane; the mask bits of the 16 texels sit in one word).  Statistics
 // accumulate runs: a lane keeps the running totals of its current group and
 // adds them to the group's bins only when the group changes, since labelled
-// regions are spatially coherent.  Bins of up to 256 groups live in LDS
-// (native 64-bit LDS atomics, flushed once per workgroup); 65536 groups
-// take global atomics per run.  Minima and maxima are 64-bit atomics on an
-// order-preserving encoding of the fp64 value.
+// regions are spatially coherent.  A workgroup's bins live in LDS (native
+// 64-bit LDS atomics): 256 direct bins for u8 groups, a tagged hash table for
+// u16 groups; they are added to the global bins once per workgroup.  Minima
+// and maxima are 64-bit atomics on an order-preserving encoding of the fp64
+// value.
 #include <math.h>
 #include <string.h>
 
@@ -122,7 +123,10 @@ namespace {
 
 constexpr int kPer = 16;                     // texels per lane per step
 constexpr int kStep = kBlock * kPer;         // texels per workgroup per step
-constexpr int kMaxStatBlocks = 2048;         // 8 workgroups per CU
+// Statistics workgroups: 2 per CU.  Each adds its LDS bins to the global
+// bins once; with more workgroups those same-address atomics cost more than
+// the extra waves gain (2048 workgroups: +40 us at 8192^2).
+constexpr int kMaxStatBlocks = 512;
 
 // Value of stored bits in fp64 (exact for every dtype).
 template <int32_t DT>
@@ -165,11 +169,28 @@ __device__ __forceinline__ uint32_t mask16(const uint32_t *__restrict__ mask, in
     return (mask[t >> 5] >> (t & 31)) & 0xffffu;
 }
 
-// Range selection: dst[t] = label where valid and lo <= v <= hi.
+// 16 consecutive elements to a 16-byte aligned plane of u8 or u16.
+template <typename T>
+__device__ __forceinline__ void store16(T *__restrict__ p, int64_t t, const uint32_t in[kPer]) {
+    constexpr int kVec = 16 / sizeof(T);
+    constexpr int kBits = 8 * sizeof(T);
+#pragma unroll
+    for (int q = 0; q < kPer / kVec; ++q) {
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int k = 0; k < kVec; ++k) w[k * kBits / 32] |= in[q * kVec + k] << ((k * kBits) % 32);
+        reinterpret_cast<uint4 *>(p + t)[q] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
+// Range selection: dst[t] = label where valid and lo <= v <= hi.  A lane
+// with any selected texel rewrites its 16 labels as whole vectors (the
+// others unchanged): a selection that follows no pattern would otherwise
+// leave partly written lines for the memory side to merge.
 template <int32_t DT, typename L>
 __global__ __launch_bounds__(kBlock) void k_select(const Store<DT> *__restrict__ data,
                                                    const uint32_t *__restrict__ mask, int64_t n, double lo,
-                                                   double hi, LabelSink<L> out) {
+                                                   double hi, L *__restrict__ dst, uint32_t label) {
     const int64_t t = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kPer;
     if (t >= n) return;
     uint32_t v[kPer];
@@ -177,16 +198,23 @@ __global__ __launch_bounds__(kBlock) void k_select(const Store<DT> *__restrict__
     if (full) load16(data, t, v);
     else load_tail(data, t, n, v);
     const uint32_t m = mask16(mask, t);
-    bool s[kPer];
+    uint32_t sel = 0;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         const double x = decode<DT>(v[k]);
-        s[k] = ((m >> k) & 1u) && x >= lo && x <= hi;
+        sel |= (uint32_t)(((m >> k) & 1u) && x >= lo && x <= hi) << k;
     }
+    if (!sel) return;
+    if (full) {
+        uint32_t cur[kPer];
+        load16(dst, t, cur);
 #pragma unroll
-    for (int g = 0; g < kPer / 4; ++g) {
-        if (full) out.put4(t + 4 * g, s + 4 * g, false);
-        else out.put_some(t + 4 * g, (int)(n - (t + 4 * g)), s + 4 * g);
+        for (int k = 0; k < kPer; ++k)
+            if ((sel >> k) & 1u) cur[k] = label;
+        store16(dst, t, cur);
+    } else {
+        for (int k = 0; k < kPer; ++k)
+            if (t + k < n && ((sel >> k) & 1u)) dst[t + k] = (L)label;
     }
 }
 
@@ -222,17 +250,33 @@ struct Run {
     }
 };
 
-// Add a run to a bin (LDS or global).
+// Add totals to a bin: LDS (native LDS atomics) or global memory.
 template <bool kGlobal>
-__device__ __forceinline__ void flush(Bin *bins, const Run &r) {
-    if (r.count == 0) return;
-    Bin *b = bins + r.label;
-    atomicAdd(&b->count, r.count);
-    atomicAdd(&b->aw, r.aw);
-    if constexpr (kGlobal) unsafeAtomicAdd(&b->wsum, r.wsum);
-    else atomicAdd(&b->wsum, r.wsum);
-    atomicMin(&b->kmin, order_key(r.vmin));
-    atomicMax(&b->kmax, order_key(r.vmax));
+__device__ __forceinline__ void add_to(Bin *b, unsigned long long count, unsigned long long aw, double wsum,
+                                       unsigned long long kmin, unsigned long long kmax) {
+    atomicAdd(&b->count, count);
+    atomicAdd(&b->aw, aw);
+    if constexpr (kGlobal) unsafeAtomicAdd(&b->wsum, wsum);
+    else atomicAdd(&b->wsum, wsum);
+    atomicMin(&b->kmin, kmin);
+    atomicMax(&b->kmax, kmax);
+}
+
+// LDS slot of a u16 label: open addressing with linear probing over
+// kHashSlots tagged slots; -1 when 8 probes find neither the label nor a
+// free slot (the run then goes to the global bin).
+constexpr int kHashBits = 9;
+constexpr int kHashSlots = 1 << kHashBits;
+constexpr uint32_t kNoTag = 0xffffffffu;
+
+__device__ __forceinline__ int hash_slot(uint32_t *tags, uint32_t label) {
+    uint32_t h = (label * 2654435761u) >> (32 - kHashBits);
+    for (int probe = 0; probe < 8; ++probe) {
+        const uint32_t prev = atomicCAS(tags + h, kNoTag, label);
+        if (prev == kNoTag || prev == label) return (int)h;
+        h = (h + 1) & (kHashSlots - 1);
+    }
+    return -1;
 }
 
 __device__ __forceinline__ void bin_clear(Bin &b) {
@@ -261,22 +305,33 @@ __global__ void k_stats_final(Bin *bins, int nbins) {
 }
 
 // Zonal statistics.  R: region storage (void: no region, one group).
-// Groups of up to 256 accumulate in LDS and are flushed once per
-// workgroup; larger group counts go straight to the global bins.
+// Every workgroup accumulates its lanes' runs in LDS -- one bin, 256 bins
+// indexed by a u8 label, or kHashSlots tagged slots for u16 labels -- and
+// adds its non-empty bins to the global bins once at the end.
 template <int32_t DT, typename R>
 __global__ __launch_bounds__(kBlock) void k_stats(const int32_t *__restrict__ tri, const uint32_t *__restrict__ aw,
                                                   const Store<DT> *__restrict__ data,
                                                   const uint32_t *__restrict__ mask, const R *__restrict__ region,
                                                   int64_t n, Bin *__restrict__ bins) {
     constexpr bool kNoRegion = std::is_same<R, void>::value;
-    constexpr bool kLds = kNoRegion || std::is_same<R, uint8_t>::value;
-    constexpr int kLdsBins = kNoRegion ? 1 : 256;
-    __shared__ Bin lds[kLds ? kLdsBins : 1];
-    if constexpr (kLds) {
-        for (int i = threadIdx.x; i < kLdsBins; i += kBlock) bin_clear(lds[i]);
-        __syncthreads();
+    constexpr bool kHash = std::is_same<R, uint16_t>::value;
+    constexpr int kSlots = kNoRegion ? 1 : kHash ? kHashSlots : 256;
+    __shared__ Bin lds[kSlots];
+    __shared__ uint32_t tags[kHash ? kSlots : 1];
+    for (int i = threadIdx.x; i < kSlots; i += kBlock) {
+        bin_clear(lds[i]);
+        if constexpr (kHash) tags[i] = kNoTag;
     }
-    Bin *target = kLds ? lds : bins;
+    __syncthreads();
+    auto put = [&](const Run &r) {
+        if (r.count == 0) return;
+        int slot = kNoRegion ? 0 : (int)r.label;
+        if constexpr (kHash) slot = hash_slot(tags, r.label);
+        if (slot >= 0)
+            add_to<false>(lds + slot, r.count, r.aw, r.wsum, order_key(r.vmin), order_key(r.vmax));
+        else
+            add_to<true>(bins + r.label, r.count, r.aw, r.wsum, order_key(r.vmin), order_key(r.vmax));
+    };
     Run run;
     run.reset(0);
     const int64_t stride = (int64_t)gridDim.x * kStep;
@@ -302,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_stats(const int32_t *__restrict__ tr
             if ((int32_t)tr[k] < 0 || !((m >> k) & 1u)) continue;
             const uint32_t l = kNoRegion ? 0u : lab[k];
             if (l != run.label) {
-                flush<!kLds>(target, run);
+                put(run);
                 run.reset(l);
             }
             const double x = decode<DT>(v[k]);
@@ -313,19 +368,13 @@ __global__ __launch_bounds__(kBlock) void k_stats(const int32_t *__restrict__ tr
             run.vmax = fmax(run.vmax, x);
         }
     }
-    flush<!kLds>(target, run);
-    if constexpr (kLds) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < kLdsBins; i += kBlock) {
-            Run r;
-            r.label = (uint32_t)i;
-            r.count = lds[i].count;
-            r.aw = lds[i].aw;
-            r.wsum = lds[i].wsum;
-            r.vmin = from_key(lds[i].kmin);
-            r.vmax = from_key(lds[i].kmax);
-            flush<true>(bins, r);
-        }
+    put(run);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kSlots; i += kBlock) {
+        const Bin &b = lds[i];
+        if (b.count == 0) continue;
+        const uint32_t label = kHash ? tags[i] : (uint32_t)i;
+        add_to<true>(bins + label, b.count, b.aw, b.wsum, b.kmin, b.kmax);
     }
 }
 
@@ -335,10 +384,12 @@ void launch_select(const uvl_numeric *src, double lo, double hi, const uvl_layer
     const int64_t n = (int64_t)src->width * src->height;
     const dim3 grid((unsigned)ceil_div(n, kStep));
     const Store<DT> *data = static_cast<const Store<DT> *>(src->data);
-    with_label_sink(dst, label, [&](auto out) {
-        using L = typename std::remove_pointer<decltype(out.L)>::type;
-        hipLaunchKernelGGL((k_select<DT, L>), grid, dim3(kBlock), 0, s, data, src->mask, n, lo, hi, out);
-    });
+    if (dst->dtype == UVL_U8)
+        hipLaunchKernelGGL((k_select<DT, uint8_t>), grid, dim3(kBlock), 0, s, data, src->mask, n, lo, hi,
+                           static_cast<uint8_t *>(dst->data), label);
+    else
+        hipLaunchKernelGGL((k_select<DT, uint16_t>), grid, dim3(kBlock), 0, s, data, src->mask, n, lo, hi,
+                           static_cast<uint16_t *>(dst->data), label);
 }
 
 template <int32_t DT>
