@@ -334,6 +334,19 @@ typedef struct {
     double vmin, vmax;  /* extremes of the value (+inf / -inf when count is 0) */
 } uvl_numstat;
 
+/* Texture padding of a numeric layer after a numeric brush or lasso edit
+ * (same arguments as uvl_pad_brush / uvl_pad_lasso, with the edit's mode
+ * and value in place of the label): the outline texels the label padding
+ * would label are SET or ERASEd instead.  Errors as those calls and the
+ * numeric edits. */
+int32_t uvl_numeric_pad_brush(const uvl_geom *geom, const uvl_numeric *layer, const int32_t *outline, int64_t n,
+                              int32_t k, const float center[3], float radius, int32_t mode, double value,
+                              void *stream);
+int32_t uvl_numeric_pad_lasso(const uvl_geom *geom, const uvl_numeric *layer, const int32_t *outline, int64_t n,
+                              int32_t k, const float view_proj[16], const float *poly_xy, int32_t npoly,
+                              const float *depth, int32_t dw, int32_t dh, float bias, int32_t mode, double value,
+                              void *stream);
+
 /* Zonal statistics of a numeric layer (Table 1 gives the surface area one
  * texel stands for; weighting values by it gives area-weighted means, area
  * wsum / area_w).  Counted texels: covered (tri_id >= 0) with the mask bit

@@ -20,6 +20,8 @@ here (the paper gives the textures, not the operations on numeric layers):
     0, data untouched); the value is converted once: integers must be exact
     and in range, floats round to nearest, ties to even, and must stay
     finite;
+  - texture padding (§4.3.2) of a numeric layer SETs or ERASEs the
+    outline texels the label padding would label;
   - a range selection turns quantitative data into a label: texels whose
     mask bit is set and whose value v (exact in fp64) satisfies
     lo <= v <= hi take the label in a label layer; others keep theirs;
@@ -42,7 +44,7 @@ import math
 
 import numpy as np
 
-from . import brush as _brush, lasso as _lasso, tool as _tool
+from . import brush as _brush, lasso as _lasso, pad as _pad, tool as _tool
 
 U8, U16, I32, F16, F32 = 1, 2, 3, 4, 5
 SET, ERASE = 0, 1
@@ -158,6 +160,14 @@ def lasso(pos32, layer: NumericLayer, M, poly, depth, bias, mode: int, value: fl
 def tool(pos32, layer: NumericLayer, M, tool_params, shape, depth, bias, mode: int, value: float = 0.0) -> int:
     sel = np.zeros(layer.data.size, np.uint8)
     _tool(pos32, sel, M, tool_params, shape, depth, bias, 1)
+    return apply(layer, sel == 1, mode, value)
+
+
+def pad(outline_mask, edited, W: int, H: int, k: int, layer: NumericLayer, mode: int, value: float = 0.0) -> int:
+    """Texture padding of a numeric layer after one edit (§4.3.2): the
+    outline texels the label padding would label are SET or ERASEd."""
+    sel = np.zeros(layer.data.size, np.uint8)
+    _pad(outline_mask, edited, W, H, k, sel, 1)
     return apply(layer, sel == 1, mode, value)
 
 

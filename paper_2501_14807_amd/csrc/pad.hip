@@ -3,8 +3,8 @@
 // Around every texture island (the texels triangles cover) the outline is
 // the band of uncovered texels within Chebyshev distance k of the island;
 // after an edit, each outline texel within distance k of a texel the edit
-// selected takes the edit's label, so that sampling across an island's
-// border reads the edited value.  Both distances use the paper's square
+// selected takes the edit's label (or, in a numeric layer, the edit's SET or
+// ERASE), so that sampling across an island's border reads the edited value.  Both distances use the paper's square
 // kernel of radius k; the paper pads one texel (k = 1).
 //
 // The outline is built once per geometry image, as a list of texel indices
@@ -17,6 +17,7 @@
 // texels only, so padding and edits touch disjoint texels and a padding
 // pass may run any time after its edit.
 #include "edit_texel.h"
+#include "sink.h"
 #include "uvl_internal.h"
 
 namespace uvl {
@@ -114,10 +115,10 @@ __global__ __launch_bounds__(kBlock) void k_outline_write(const int32_t *__restr
 
 // Padding: lane per outline texel; the covered texels of its window are
 // tested with the edit's predicate until one is selected.
-template <typename T, class Pred>
+template <class Sink, class Pred>
 __device__ __forceinline__ void pad_texel(const float *__restrict__ px, const float *__restrict__ py,
-                                          const float *__restrict__ pz, T *__restrict__ L, int W, int H, int k,
-                                          int32_t t, const Pred &sel, T label) {
+                                          const float *__restrict__ pz, const Sink &out, int W, int H, int k,
+                                          int32_t t, const Pred &sel) {
     if (t < 0 || (int64_t)t >= (int64_t)W * H) return;   // not a texel index: ignored
     const int i = t % W, j = t / W;
     const int u0 = i - k < 0 ? 0 : i - k, u1 = i + k > W - 1 ? W - 1 : i + k;
@@ -128,44 +129,79 @@ __device__ __forceinline__ void pad_texel(const float *__restrict__ px, const fl
             const float x = px[s];
             if (x != x) continue;   // uncovered (NaN position): never edited
             if (sel(x, py[s], pz[s])) {
-                L[t] = label;
+                out.put1(t);
                 return;
             }
         }
 }
 
-template <typename T>
+template <class Sink>
 __global__ __launch_bounds__(kBlock) void k_pad_brush(const float *__restrict__ px, const float *__restrict__ py,
-                                                      const float *__restrict__ pz, T *__restrict__ L, int W, int H,
-                                                      int k, const int32_t *__restrict__ outline, int64_t n,
-                                                      BrushParams B, uint32_t label) {
+                                                      const float *__restrict__ pz, Sink out, int W, int H, int k,
+                                                      const int32_t *__restrict__ outline, int64_t n,
+                                                      BrushParams B) {
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (q >= n) return;
-    pad_texel<T>(px, py, pz, L, W, H, k, outline[q],
-                 [&](float x, float y, float z) { return brush_texel(B, x, y, z); }, (T)label);
+    pad_texel(px, py, pz, out, W, H, k, outline[q],
+              [&](float x, float y, float z) { return brush_texel(B, x, y, z); });
 }
 
-template <typename T>
+template <class Sink>
 __global__ __launch_bounds__(kBlock) void k_pad_lasso(const float *__restrict__ px, const float *__restrict__ py,
-                                                      const float *__restrict__ pz, T *__restrict__ L, int W, int H,
-                                                      int k, const int32_t *__restrict__ outline, int64_t n,
-                                                      LassoParams P, const float *__restrict__ depth,
-                                                      uint32_t label) {
+                                                      const float *__restrict__ pz, Sink out, int W, int H, int k,
+                                                      const int32_t *__restrict__ outline, int64_t n, LassoParams P,
+                                                      const float *__restrict__ depth) {
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (q >= n) return;
-    pad_texel<T>(px, py, pz, L, W, H, k, outline[q],
-                 [&](float x, float y, float z) { return lasso_texel(P, depth, x, y, z); }, (T)label);
+    pad_texel(px, py, pz, out, W, H, k, outline[q],
+              [&](float x, float y, float z) { return lasso_texel(P, depth, x, y, z); });
+}
+
+// Outline list and radius, shared by the label and numeric calls.
+int32_t check_outline(const uvl_geom *g, const int32_t *outline, int64_t n, int32_t k) {
+    if (!geom_pos_ok(g)) return UVL_E_INVAL;
+    if (n < 0 || (n > 0 && !outline) || k < 0 || k > kMaxPadRadius) return UVL_E_INVAL;
+    if (n > (int64_t)g->width * g->height) return UVL_E_SHAPE;
+    return UVL_OK;
 }
 
 int32_t check_pad(const uvl_geom *g, const uvl_layer *l, const int32_t *outline, int64_t n, int32_t k,
                   uint32_t label) {
-    if (!geom_pos_ok(g) || !layer_ok(l)) return UVL_E_INVAL;
-    if (n < 0 || (n > 0 && !outline) || k < 0 || k > kMaxPadRadius) return UVL_E_INVAL;
-    if (n > (int64_t)g->width * g->height) return UVL_E_SHAPE;
+    if (!layer_ok(l)) return UVL_E_INVAL;
+    if (int32_t s = check_outline(g, outline, n, k)) return s;
     if (!dtype_ok(l->dtype)) return UVL_E_DTYPE;
     if (label > dtype_max(l->dtype)) return UVL_E_DTYPE;
     if (l->width != g->width || l->height != g->height) return UVL_E_SHAPE;
     return device_ok();
+}
+
+bool brush_ok(const float center[3], float radius) {
+    return center && radius >= 0.0f && std::isfinite(radius) && std::isfinite(center[0]) &&
+           std::isfinite(center[1]) && std::isfinite(center[2]);
+}
+
+bool lasso_ok(const float view_proj[16], const float *poly_xy, int32_t npoly, const float *depth, int32_t dw,
+              int32_t dh, float bias, LassoParams &p) {
+    if (!depth || dw > kMaxDepthSide || dh > kMaxDepthSide) return false;
+    if (!make_lasso_params(view_proj, poly_xy, npoly, dw, dh, bias, p)) return false;
+    for (int q = 0; q < 16; ++q)
+        if (!std::isfinite(view_proj[q])) return false;
+    return true;
+}
+
+template <class Sink>
+void launch_pad_brush(const uvl_geom *g, const int32_t *outline, int64_t n, int32_t k, const float center[3],
+                      float radius, const Sink &out, hipStream_t s) {
+    const BrushParams p{center[0], center[1], center[2], radius * radius};
+    hipLaunchKernelGGL(k_pad_brush<Sink>, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, s, g->pos_x,
+                       g->pos_y, g->pos_z, out, g->width, g->height, k, outline, n, p);
+}
+
+template <class Sink>
+void launch_pad_lasso(const uvl_geom *g, const int32_t *outline, int64_t n, int32_t k, const LassoParams &p,
+                      const float *depth, const Sink &out, hipStream_t s) {
+    hipLaunchKernelGGL(k_pad_lasso<Sink>, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, s, g->pos_x,
+                       g->pos_y, g->pos_z, out, g->width, g->height, k, outline, n, p, depth);
 }
 
 }  // namespace
@@ -205,19 +241,12 @@ extern "C" int32_t uvl_build_outline(const uvl_geom *geom, int32_t k, int32_t *o
 
 extern "C" int32_t uvl_pad_brush(const uvl_geom *geom, const uvl_layer *layer, const int32_t *outline, int64_t n,
                                  int32_t k, const float center[3], float radius, uint32_t label, void *stream) {
-    if (!center || !(radius >= 0.0f) || !std::isfinite(radius)) return UVL_E_INVAL;
-    if (!std::isfinite(center[0]) || !std::isfinite(center[1]) || !std::isfinite(center[2])) return UVL_E_INVAL;
+    if (!brush_ok(center, radius)) return UVL_E_INVAL;
     if (int32_t s = check_pad(geom, layer, outline, n, k, label)) return s;
     if (n == 0) return UVL_OK;
-    BrushParams p{center[0], center[1], center[2], radius * radius};
-    const dim3 grid((unsigned)ceil_div(n, kBlock));
-    hipStream_t s = as_stream(stream);
-    if (layer->dtype == UVL_U8)
-        hipLaunchKernelGGL(k_pad_brush<uint8_t>, grid, dim3(kBlock), 0, s, geom->pos_x, geom->pos_y, geom->pos_z,
-                           static_cast<uint8_t *>(layer->data), geom->width, geom->height, k, outline, n, p, label);
-    else
-        hipLaunchKernelGGL(k_pad_brush<uint16_t>, grid, dim3(kBlock), 0, s, geom->pos_x, geom->pos_y, geom->pos_z,
-                           static_cast<uint16_t *>(layer->data), geom->width, geom->height, k, outline, n, p, label);
+    with_label_sink(layer, label, [&](auto out) {
+        launch_pad_brush(geom, outline, n, k, center, radius, out, as_stream(stream));
+    });
     return launch_status();
 }
 
@@ -225,22 +254,42 @@ extern "C" int32_t uvl_pad_lasso(const uvl_geom *geom, const uvl_layer *layer, c
                                  int32_t k, const float view_proj[16], const float *poly_xy, int32_t npoly,
                                  const float *depth, int32_t dw, int32_t dh, float bias, uint32_t label,
                                  void *stream) {
-    if (!depth || dw > kMaxDepthSide || dh > kMaxDepthSide) return UVL_E_INVAL;
     LassoParams p;
-    if (!make_lasso_params(view_proj, poly_xy, npoly, dw, dh, bias, p)) return UVL_E_INVAL;
-    for (int q = 0; q < 16; ++q)
-        if (!std::isfinite(view_proj[q])) return UVL_E_INVAL;
+    if (!lasso_ok(view_proj, poly_xy, npoly, depth, dw, dh, bias, p)) return UVL_E_INVAL;
     if (int32_t s = check_pad(geom, layer, outline, n, k, label)) return s;
     if (n == 0) return UVL_OK;
-    const dim3 grid((unsigned)ceil_div(n, kBlock));
-    hipStream_t s = as_stream(stream);
-    if (layer->dtype == UVL_U8)
-        hipLaunchKernelGGL(k_pad_lasso<uint8_t>, grid, dim3(kBlock), 0, s, geom->pos_x, geom->pos_y, geom->pos_z,
-                           static_cast<uint8_t *>(layer->data), geom->width, geom->height, k, outline, n, p, depth,
-                           label);
-    else
-        hipLaunchKernelGGL(k_pad_lasso<uint16_t>, grid, dim3(kBlock), 0, s, geom->pos_x, geom->pos_y, geom->pos_z,
-                           static_cast<uint16_t *>(layer->data), geom->width, geom->height, k, outline, n, p, depth,
-                           label);
+    with_label_sink(layer, label, [&](auto out) {
+        launch_pad_lasso(geom, outline, n, k, p, depth, out, as_stream(stream));
+    });
+    return launch_status();
+}
+
+extern "C" int32_t uvl_numeric_pad_brush(const uvl_geom *geom, const uvl_numeric *layer, const int32_t *outline,
+                                         int64_t n, int32_t k, const float center[3], float radius, int32_t mode,
+                                         double value, void *stream) {
+    if (!brush_ok(center, radius)) return UVL_E_INVAL;
+    if (int32_t s = check_outline(geom, outline, n, k)) return s;
+    uint32_t bits = 0;
+    if (int32_t s = check_numeric_edit(geom, layer, mode, value, bits)) return s;
+    if (n == 0) return UVL_OK;
+    with_value_sink(layer, bits, mode, [&](auto out) {
+        launch_pad_brush(geom, outline, n, k, center, radius, out, as_stream(stream));
+    });
+    return launch_status();
+}
+
+extern "C" int32_t uvl_numeric_pad_lasso(const uvl_geom *geom, const uvl_numeric *layer, const int32_t *outline,
+                                         int64_t n, int32_t k, const float view_proj[16], const float *poly_xy,
+                                         int32_t npoly, const float *depth, int32_t dw, int32_t dh, float bias,
+                                         int32_t mode, double value, void *stream) {
+    LassoParams p;
+    if (!lasso_ok(view_proj, poly_xy, npoly, depth, dw, dh, bias, p)) return UVL_E_INVAL;
+    if (int32_t s = check_outline(geom, outline, n, k)) return s;
+    uint32_t bits = 0;
+    if (int32_t s = check_numeric_edit(geom, layer, mode, value, bits)) return s;
+    if (n == 0) return UVL_OK;
+    with_value_sink(layer, bits, mode, [&](auto out) {
+        launch_pad_lasso(geom, outline, n, k, p, depth, out, as_stream(stream));
+    });
     return launch_status();
 }

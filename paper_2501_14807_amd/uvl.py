@@ -101,6 +101,8 @@ SIGNATURES = {
     "uvl_numeric_lasso": ([_P, _P, _P, _P, _I32, _P, _I32, _I32, _F32, _I32, _F64, _P], _I32),
     "uvl_numeric_tool": ([_P, _P, _P, _P, _P, _I32, _I32, _P, _I32, _I32, _F32, _I32, _F64, _P], _I32),
     "uvl_numeric_select": ([_P, _F64, _F64, _P, _U32, _P], _I32),
+    "uvl_numeric_pad_brush": ([_P, _P, _P, _I64, _I32, _P, _F32, _I32, _F64, _P], _I32),
+    "uvl_numeric_pad_lasso": ([_P, _P, _P, _I64, _I32, _P, _P, _I32, _P, _I32, _I32, _F32, _I32, _F64, _P], _I32),
     "uvl_numeric_stats": ([_P, _P, _P, _P, _P, _P], _I32),
 }
 
@@ -501,6 +503,26 @@ def pad_lasso(geom: GeometryImage, layer: Layer, outline: Outline, view_proj, po
                                 M.ctypes.data_as(ctypes.c_void_p), P.ctypes.data_as(ctypes.c_void_p), P.size // 2,
                                 _ptr(depth), dw, dh, float(np.float32(bias)), int(label), _stream(stream)),
            "uvl_pad_lasso")
+
+
+def numeric_pad_brush(geom: GeometryImage, layer: NumericLayer, outline: Outline, center, radius: float, mode: int,
+                      value: float = 0.0, stream=None):
+    c = _f32(center, 3)
+    _check(_lib().uvl_numeric_pad_brush(ctypes.byref(geom.c), ctypes.byref(layer.c), _ptr(outline.idx), outline.n,
+                                        outline.k, c.ctypes.data_as(ctypes.c_void_p), float(np.float32(radius)),
+                                        int(mode), float(value), _stream(stream)), "uvl_numeric_pad_brush")
+
+
+def numeric_pad_lasso(geom: GeometryImage, layer: NumericLayer, outline: Outline, view_proj, poly,
+                      depth: torch.Tensor, bias: float, mode: int, value: float = 0.0, stream=None):
+    M = _f32(view_proj, 16)
+    P = _f32(poly).reshape(-1)
+    dh, dw = depth.shape
+    _check(_lib().uvl_numeric_pad_lasso(ctypes.byref(geom.c), ctypes.byref(layer.c), _ptr(outline.idx), outline.n,
+                                        outline.k, M.ctypes.data_as(ctypes.c_void_p),
+                                        P.ctypes.data_as(ctypes.c_void_p), P.size // 2, _ptr(depth), dw, dh,
+                                        float(np.float32(bias)), int(mode), float(value), _stream(stream)),
+           "uvl_numeric_pad_lasso")
 
 
 def layer_op(op: int, dst: Layer, a: Layer, b: Optional[Layer] = None, sel_a: int = 0, sel_b: int = 0,

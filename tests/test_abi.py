@@ -264,3 +264,13 @@ def test_numeric_validation(uvl):
     assert st(region=_layer(uvl, dt=3)) == -3 and st(region=_layer(uvl, h=16)) == -2
     assert st(layer=nl(w=32)) == -2
     assert st() in passed and st(region=_layer(uvl, dt=2)) in passed
+    M = (ctypes.c_float * 16)(*([1.0] * 16))
+    poly = (ctypes.c_float * 6)(0, 0, 1, 0, 0, 1)
+    pb = lambda n=4, k=1, outline=FAKE, mode=uvl.SET, layer=src: L.uvl_numeric_pad_brush(
+        ctypes.byref(g), ctypes.byref(layer), outline, n, k, c, 1.0, mode, 1.0, None)
+    pl = lambda n=4, k=1, npoly=3: L.uvl_numeric_pad_lasso(ctypes.byref(g), ctypes.byref(src), FAKE, n, k, M, poly,
+                                                           npoly, FAKE, 32, 32, 1e-4, uvl.SET, 1.0, None)
+    assert pb(k=9) == -1 and pb(k=-1) == -1 and pb(outline=None) == -1 and pb(n=-1) == -1
+    assert pb(n=64 * 32 + 1) == -2 and pb(mode=5) == -1 and pb(layer=nl(dt=7)) == -1
+    assert pb(layer=nl(dt=uvl.U8)) in passed and pb(n=0, outline=None) in passed
+    assert pl(npoly=2) == -1 and pl(k=9) == -1 and pl() in passed

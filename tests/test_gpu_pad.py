@@ -1,7 +1,8 @@
 """Texture padding on the GPU (uvl_build_outline, uvl_pad_brush,
-uvl_pad_lasso) against the oracle's padding, bit for bit: the outline list
-equals the oracle's outline mask, and layers after edits each followed by
-its padding equal the oracle's (edit, selection mask, padding)."""
+uvl_pad_lasso, uvl_numeric_pad_brush/lasso) against the oracle's padding,
+bit for bit: the outline list equals the oracle's outline mask, and label
+and numeric layers after edits each followed by its padding equal the
+oracle's (edit, selection mask, padding)."""
 
 import numpy as np
 import pytest
@@ -99,3 +100,44 @@ def test_padding_writes_only_the_outline(gpu):
     mask = np.zeros(got.size, bool)
     mask[o1.numpy()] = True
     assert (got[mask] == 7).all() and not got[~mask].any()
+
+
+@pytest.mark.parametrize("k,dt", [(1, 4), (2, 3)])
+def test_numeric_padding_matches_oracle(gpu, orc, k, dt):
+    """Numeric layers (binary16, int32): each edit (every fifth an ERASE)
+    followed by its padding, data bits and mask words against the oracle."""
+    from oracle import numeric as N
+    from paper_2501_14807_amd.model import Model
+    wl = _scan_small()
+    W = H = wl.W
+    m = Model.from_workload(wl).build()
+    og = orc.geometry_image(wl.mesh, W, H)
+    ol = orc.outline(og.tri_id, W, H, k)
+    o = gpu.Outline(m.geom, k)
+    L = gpu.numeric_create(gpu.NumericLayer(W, H, dt))
+    R = N.NumericLayer(W * H, dt)
+    depth_o = {}
+    padded = 0
+    for i, e in enumerate(wl.edits):
+        mode = N.ERASE if i % 5 == 4 else N.SET
+        value = (i + 1) * (0.375 if dt == N.F16 else -3)
+        sel = np.zeros(W * H, np.uint8)
+        if e.kind == "brush":
+            gpu.numeric_brush(m.geom, L, e.centre, e.radius, mode, value)
+            gpu.numeric_pad_brush(m.geom, L, o, e.centre, e.radius, mode, value)
+            orc.brush(og.pos32, sel, e.centre, e.radius, 1)
+            N.brush(og.pos32, R, e.centre, e.radius, mode, value)
+        else:
+            M = wl.cameras[e.camera]
+            d = m.depth_for(e.camera, M)
+            gpu.numeric_lasso(m.geom, L, M, e.poly, d, m.bias, mode, value)
+            gpu.numeric_pad_lasso(m.geom, L, o, M, e.poly, d, m.bias, mode, value)
+            if e.camera not in depth_o:
+                depth_o[e.camera] = orc.depth_map(wl.mesh, M, wl.depth_w, wl.depth_h)
+            orc.lasso(og.pos32, sel, M, e.poly, depth_o[e.camera], m.bias, 1)
+            N.lasso(og.pos32, R, M, e.poly, depth_o[e.camera], m.bias, mode, value)
+        padded += N.pad(ol, sel, W, H, k, R, mode, value)
+    assert padded > 0
+    ut = np.uint16 if dt == N.F16 else np.uint32
+    assert np.array_equal(L.numpy().view(ut), R.data.view(ut))
+    assert np.array_equal(L.mask_words(), R.words)

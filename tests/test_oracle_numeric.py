@@ -138,6 +138,28 @@ def test_brush_set_then_erase(orc):
         assert (L.data != 0).sum() == n                # ERASE keeps the data
 
 
+def test_padding_never_changes_statistics(orc):
+    """Padding writes uncovered texels only, so a numeric layer's statistics
+    are the same before and after it, while the padded texels hold the
+    value and are valid."""
+    W = 128
+    m = synth.plane_grid(5, 5, uv0=(0.2, 0.25), uv1=(0.7, 0.8), A=((8.0, 0.0), (0.0, 8.0), (0.0, 0.0)))
+    g = orc.geometry_image(m, W, W)
+    L = N.NumericLayer(W * W, N.I32)
+    sel = np.zeros(W * W, np.uint8)
+    orc.brush(g.pos32, sel, (2.0, 2.0, 0.0), 1.5, 1)
+    N.brush(g.pos32, L, (2.0, 2.0, 0.0), 1.5, N.SET, -9)
+    before = N.stats(g.tri_id, g.w, L)
+    out = orc.outline(g.tri_id, W, W, 2)
+    n = N.pad(out, sel, W, W, 2, L, N.SET, -9)
+    assert n > 0 and (g.tri_id[L.valid & (sel == 0)] < 0).all()
+    after = N.stats(g.tri_id, g.w, L)
+    assert before.tobytes() == after.tobytes()
+    assert (L.valid.sum() == (sel == 1).sum() + n) and (L.data[L.valid] == -9).all()
+    N.pad(out, sel, W, W, 2, L, N.ERASE)
+    assert L.valid.sum() == (sel == 1).sum()
+
+
 def test_range_selection_band(orc):
     W = 128
     g = _plane(orc, W)
