@@ -178,6 +178,11 @@ bool make_lasso_params(const float view_proj[16], const float *poly, int32_t n, 
     p.ylo_m = ylo - 1e-4f * (1.0f + fabsf(ylo));
     p.yhi_m = yhi + 1e-4f * (1.0f + fabsf(yhi));
     p.xhi_m = xhi + 1e-4f * (1.0f + fabsf(xhi));
+    {
+        float xabs_v = 0.0f;
+        for (int k = 0; k < n; ++k) xabs_v = fmaxf(xabs_v, fabsf(poly[2 * k]));
+        p.xlo_m = xlo - (1e-4f * (1.0f + fabsf(xlo)) + 1e-5f * (2.0f + xabs_v));
+    }
     // tile culling planes (see LassoCull)
     {
         const double m = 2e-3;

@@ -73,8 +73,9 @@ struct LassoParams {
     float bias;
     int32_t dw, dh, n;
     float ylo, yhi, xhi;        // polygon bounds: min y, max y, max x
-    float xlo;                  // polygon min x (tile culling only)
+    float xlo;                  // polygon min x
     float ylo_m, yhi_m, xhi_m;  // the same widened by 1e-4 (1 + |v|), for the reciprocal pre-test
+    float xlo_m;                // xlo widened by 1e-4 (1 + |xlo|) + 1e-5 (2 + max |vertex x|)
     float inv_h;                // slabs per unit of y
     uint64_t slab_edges[kSlabs];
     LassoEdge edge[kMaxPoly];
@@ -102,10 +103,16 @@ __device__ __forceinline__ bool lasso_front(const PT &P, float x, float y, float
     if (c[3] >= 1e-30f) {
         // Pre-test with the hardware reciprocal: x/w and y/w are within 3e-7
         // relative of the exact quotients, far inside the 1e-4 margins, so a
-        // texel rejected here fails the exact tests below as well.
+        // texel rejected here fails the exact tests below as well -- or, left
+        // of xlo_m, lies left of every vertex by more than 1e-5 (2 + max |x|),
+        // where the fp32 crossing test is exact (see lasso_rect_class): it
+        // counts every edge straddling y, an even number for a closed
+        // polygon, so the texel is outside.
         const float r = __builtin_amdgcn_rcpf(c[3]);
         const float ax = c[0] * r, ay = c[1] * r;
-        if (!(ax >= -1.0001f && ax <= 1.0001f && ay >= P.ylo_m && ay <= P.yhi_m && ax <= P.xhi_m)) return false;
+        if (!(ax >= -1.0001f && ax <= 1.0001f && ay >= P.ylo_m && ay <= P.yhi_m && ax <= P.xhi_m &&
+              ax >= P.xlo_m))
+            return false;
     }
     xn = c[0] / c[3];
     yn = c[1] / c[3];
