@@ -484,7 +484,8 @@ def main():
     kern = max(("edit_brush", "edit_lasso"), key=lambda k: stats.get(k, {"total_ms": 0})["total_ms"])
     avg_s = stats[kern]["avg_us"] * 1e-6
     achieved = per_launch[kern] / avg_s / 1e9
-    srcs = ["paper_2501_14807_amd/csrc/edit.hip", "paper_2501_14807_amd/csrc/edit_texel.h"]
+    srcs = ["paper_2501_14807_amd/csrc/edit.hip", "paper_2501_14807_amd/csrc/edit_texel.h",
+            "paper_2501_14807_amd/csrc/sink.h"]
     traffic = traffic_from_profiles(kern, srcs)
     kernels = {}
     for k, s in stats.items():
