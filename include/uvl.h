@@ -16,7 +16,8 @@
  *    HIP launch returns UVL_E_DEVICE.  Nothing aborts the process.
  *  - Device pointers are borrowed: the caller allocates and frees all device
  *    memory and keeps it alive until the work on `stream` has completed.
- *    The library never allocates device memory.
+ *    The library allocates no device memory, except the layer pool
+ *    (uvl_pool_*), whose purpose that is.
  *  - Host arrays (centre, matrix, polygon) are read during the call and may
  *    be freed on return.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
@@ -359,6 +360,52 @@ int32_t uvl_numeric_pad_lasso(const uvl_geom *geom, const uvl_numeric *layer, co
  * Errors: UVL_E_INVAL (pointers, alignment), UVL_E_SHAPE, UVL_E_DTYPE. */
 int32_t uvl_numeric_stats(const uvl_geom *geom, const uvl_numeric *layer, const uvl_layer *region,
                           uvl_numstat *bins_dev, uvl_numstat *bins_host, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Layer pool (§4.2: the Texture Manager sorts textures into texture arrays
+ * by a key joining width, height and data type; sparse textures separate
+ * reserving address space from committing memory).  Per key (width,
+ * height, dtype) a pool reserves one virtual address range of
+ * `slots_per_key` slots, each the layer's size rounded up to the device's
+ * allocation granularity: slot k lives at base + k * stride, the key's
+ * array.  Allocating a layer commits device memory to the lowest free slot;
+ * freeing it unmaps and releases that memory.  Reserved address space costs
+ * no memory.  The pool is the one part of the library that allocates device
+ * memory; its layers are ordinary device memory for every other call (a
+ * numeric layer's mask plane comes from the caller).  Calls on one pool are
+ * serialised by a lock; a pool belongs to the device current at creation.
+ * ------------------------------------------------------------------------ */
+typedef struct uvl_pool uvl_pool;
+
+/* New pool on the current device.  slots_per_key in 1..65536.
+ * Errors: UVL_E_INVAL, UVL_E_UNSUPPORTED (not gfx950, or no virtual memory
+ * management), UVL_E_DEVICE. */
+int32_t uvl_pool_create(int32_t slots_per_key, uvl_pool **out);
+
+/* Commit a layer of width x height values of dtype (uvl_dtype): *data
+ * receives its device address (16-byte aligned; contents undefined, clear
+ * it with uvl_create_layer or uvl_numeric_create), *slot (may be NULL) its
+ * slot in the key's array.  SYNCHRONOUS: the memory is mapped on return.
+ * Errors: UVL_E_INVAL, UVL_E_DTYPE, UVL_E_NOMEM (every slot of the key in
+ * use, address space or device memory exhausted), UVL_E_DEVICE (also when
+ * called with another device current). */
+int32_t uvl_pool_alloc(uvl_pool *pool, int32_t width, int32_t height, int32_t dtype, void **data, int32_t *slot);
+
+/* Release a layer from uvl_pool_alloc.  The caller makes sure no pending
+ * work uses it.  Errors: UVL_E_INVAL (not a committed layer of this pool). */
+int32_t uvl_pool_free(uvl_pool *pool, void *data);
+
+/* The array of a key: base address, slot stride in bytes, slot count.
+ * Errors: UVL_E_INVAL (null, or the key was never allocated). */
+int32_t uvl_pool_array(const uvl_pool *pool, int32_t width, int32_t height, int32_t dtype, void **base,
+                       size_t *stride, int32_t *slots);
+
+/* Bytes of address space reserved, bytes of device memory committed, and
+ * the number of keys. */
+int32_t uvl_pool_stats(const uvl_pool *pool, uint64_t *reserved, uint64_t *committed, int32_t *keys);
+
+/* Release every layer and reservation of the pool, then the pool. */
+int32_t uvl_pool_destroy(uvl_pool *pool);
 
 /* ------------------------------------------------------------------------
  * Batched edit waves.  The paper applies one edit per rendering pass

@@ -430,7 +430,8 @@ __global__ __launch_bounds__(kBlock) void k_stats(const int32_t *__restrict__ tr
     StepData cur, nxt;
     if (s < n) fetch_step<DT>(tri, aw, data, mask, region, n, s, lane, cur);
     for (; s < n; s += stride) {
-        if (s + stride < n) fetch_step<DT>(tri, aw, data, mask, region, n, s + stride, lane, nxt);
+        const bool more = s + stride < n;
+        if (more) fetch_step<DT>(tri, aw, data, mask, region, n, s + stride, lane, nxt);
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             if ((int32_t)cur.tr[k] < 0 || !((cur.m >> k) & 1u)) continue;
@@ -446,7 +447,7 @@ __global__ __launch_bounds__(kBlock) void k_stats(const int32_t *__restrict__ tr
             run.vmin = fmin(run.vmin, x);
             run.vmax = fmax(run.vmax, x);
         }
-        cur = nxt;
+        if (more) cur = nxt;
     }
     put(run);
     __syncthreads();

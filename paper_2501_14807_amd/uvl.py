@@ -104,6 +104,12 @@ SIGNATURES = {
     "uvl_numeric_pad_brush": ([_P, _P, _P, _I64, _I32, _P, _F32, _I32, _F64, _P], _I32),
     "uvl_numeric_pad_lasso": ([_P, _P, _P, _I64, _I32, _P, _P, _I32, _P, _I32, _I32, _F32, _I32, _F64, _P], _I32),
     "uvl_numeric_stats": ([_P, _P, _P, _P, _P, _P], _I32),
+    "uvl_pool_create": ([_I32, _P], _I32),
+    "uvl_pool_alloc": ([_P, _I32, _I32, _I32, _P, _P], _I32),
+    "uvl_pool_free": ([_P, _P], _I32),
+    "uvl_pool_array": ([_P, _I32, _I32, _I32, _P, _P, _P], _I32),
+    "uvl_pool_stats": ([_P, _P, _P, _P], _I32),
+    "uvl_pool_destroy": ([_P], _I32),
 }
 
 EDIT_BRUSH, EDIT_LASSO = 0, 1
@@ -127,6 +133,9 @@ def _lib():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = res
+        # the HIP runtime libuvl links, for host copies of pool layers
+        L.hipMemcpy.argtypes = [_P, _P, _SZ, ctypes.c_int]
+        L.hipMemcpy.restype = ctypes.c_int
         _L = L
     return _L
 
@@ -388,6 +397,84 @@ def edit_tool(geom: GeometryImage, layer: Layer, view_proj, tool, shape: torch.T
     _check(_lib().uvl_edit_tool(ctypes.byref(geom.c), ctypes.byref(layer.c), M.ctypes.data_as(ctypes.c_void_p),
                                 tp.ctypes.data_as(ctypes.c_void_p), _ptr(shape), sw, sh, _ptr(depth), dw, dh,
                                 float(np.float32(bias)), int(label), _stream(stream)), "uvl_edit_tool")
+
+
+class PoolLayer:
+    """A layer committed by a LayerPool: the same descriptor as Layer (so
+    every call that takes a Layer takes it), on pool memory instead of a
+    torch tensor.  Host copies go through the HIP runtime."""
+
+    def __init__(self, pool: "LayerPool", ptr: int, slot: int, width: int, height: int, dtype: int):
+        self.pool, self.ptr, self.slot = pool, ptr, slot
+        self.width, self.height, self.dtype = int(width), int(height), int(dtype)
+        self.c = CLayer(ptr, self.width, self.height, self.dtype)
+        self.addr = ctypes.addressof(self.c)
+
+    @property
+    def n(self) -> int:
+        return self.width * self.height
+
+    def numpy(self) -> np.ndarray:
+        out = np.empty(self.n, _NP_DTYPE[self.dtype])
+        torch.cuda.synchronize()
+        _check_hip(_lib().hipMemcpy(out.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(self.ptr), out.nbytes,
+                                    _HIP_D2H), "hipMemcpy")
+        return out
+
+    def copy_from(self, arr: np.ndarray):
+        a = np.ascontiguousarray(arr, _NP_DTYPE[self.dtype]).reshape(-1)
+        if a.size != self.n:
+            raise ValueError("size")
+        torch.cuda.synchronize()
+        _check_hip(_lib().hipMemcpy(ctypes.c_void_p(self.ptr), a.ctypes.data_as(ctypes.c_void_p), a.nbytes,
+                                    _HIP_H2D), "hipMemcpy")
+
+
+_HIP_H2D, _HIP_D2H = 1, 2
+
+
+def _check_hip(code: int, where: str):
+    if code != 0:
+        raise RuntimeError(f"{where}: hipError {code}")
+
+
+class LayerPool:
+    """Layers committed on demand into per-(width, height, dtype) reserved
+    address ranges (uvl_pool_*): the layers of one key form an array at
+    base + slot * stride."""
+
+    def __init__(self, slots_per_key: int = 64):
+        h = ctypes.c_void_p()
+        _check(_lib().uvl_pool_create(int(slots_per_key), ctypes.byref(h)), "uvl_pool_create")
+        self.h = h
+
+    def alloc(self, width: int, height: int, dtype: int = U8) -> PoolLayer:
+        ptr, slot = ctypes.c_void_p(), ctypes.c_int32()
+        _check(_lib().uvl_pool_alloc(self.h, int(width), int(height), int(dtype), ctypes.byref(ptr),
+                                     ctypes.byref(slot)), "uvl_pool_alloc")
+        return PoolLayer(self, ptr.value, slot.value, width, height, dtype)
+
+    def free(self, layer: PoolLayer):
+        _check(_lib().uvl_pool_free(self.h, ctypes.c_void_p(layer.ptr)), "uvl_pool_free")
+
+    def array(self, width: int, height: int, dtype: int):
+        """(base address, slot stride in bytes, slots) of a key."""
+        base, stride, slots = ctypes.c_void_p(), ctypes.c_size_t(), ctypes.c_int32()
+        _check(_lib().uvl_pool_array(self.h, int(width), int(height), int(dtype), ctypes.byref(base),
+                                     ctypes.byref(stride), ctypes.byref(slots)), "uvl_pool_array")
+        return base.value, stride.value, slots.value
+
+    def stats(self):
+        """(reserved bytes, committed bytes, keys)."""
+        r, c, k = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_int32()
+        _check(_lib().uvl_pool_stats(self.h, ctypes.byref(r), ctypes.byref(c), ctypes.byref(k)), "uvl_pool_stats")
+        return r.value, c.value, k.value
+
+    def close(self):
+        if self.h:
+            torch.cuda.synchronize()
+            _check(_lib().uvl_pool_destroy(self.h), "uvl_pool_destroy")
+            self.h = None
 
 
 def numeric_create(layer: NumericLayer, stream=None) -> NumericLayer:

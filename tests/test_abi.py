@@ -274,3 +274,22 @@ def test_numeric_validation(uvl):
     assert pb(n=64 * 32 + 1) == -2 and pb(mode=5) == -1 and pb(layer=nl(dt=7)) == -1
     assert pb(layer=nl(dt=uvl.U8)) in passed and pb(n=0, outline=None) in passed
     assert pl(npoly=2) == -1 and pl(k=9) == -1 and pl() in passed
+
+
+def test_pool_validation(uvl):
+    """Layer pool: argument errors are caught on the host (creation needs
+    the device: -5 or -6 without one)."""
+    L = uvl.lib()
+    h = ctypes.c_void_p()
+    assert L.uvl_pool_create(0, ctypes.byref(h)) == -1 and L.uvl_pool_create(65537, ctypes.byref(h)) == -1
+    assert L.uvl_pool_create(8, None) == -1
+    assert L.uvl_pool_create(8, ctypes.byref(h)) in (-5, -6, 0)
+    if h.value:
+        L.uvl_pool_destroy(h)
+    p, s = ctypes.c_void_p(), ctypes.c_int32()
+    assert L.uvl_pool_alloc(None, 64, 64, 1, ctypes.byref(p), ctypes.byref(s)) == -1
+    assert L.uvl_pool_free(None, FAKE) == -1
+    r, c, k = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_int32()
+    assert L.uvl_pool_stats(None, ctypes.byref(r), ctypes.byref(c), ctypes.byref(k)) == -1
+    assert L.uvl_pool_array(None, 64, 64, 1, ctypes.byref(p), ctypes.byref(ctypes.c_size_t()), ctypes.byref(s)) == -1
+    assert L.uvl_pool_destroy(None) == -1
