@@ -420,7 +420,11 @@ typedef enum { UVL_EDIT_BRUSH = 0, UVL_EDIT_LASSO = 1 } uvl_edit_kind;
  * device data (as for the single-edit calls); all edits of one layer must
  * name the same geometry image.  Brush: center, radius.  Lasso: view_proj
  * (host float[16]), poly_xy (host float[npoly][2], 3 <= npoly <= 64), depth
- * (device [dh][dw] map rendered with that matrix), bias. */
+ * (device [dh][dw] map rendered with that matrix), bias.  With numeric
+ * non-NULL (and layer NULL) the edit SETs or ERASEs that numeric layer
+ * (mode, value as for uvl_numeric_brush / uvl_numeric_lasso; label ignored):
+ * the result is that of the numeric single-edit calls in array order.
+ * Records without numeric edits leave numeric NULL and the rest 0. */
 typedef struct {
     const uvl_geom *geom;
     const uvl_layer *layer;
@@ -434,6 +438,10 @@ typedef struct {
     int32_t dw, dh;
     float bias;
     const float *depth;
+    const uvl_numeric *numeric;
+    int32_t mode;           /* uvl_value_mode */
+    int32_t reserved;       /* 0 */
+    double value;
 } uvl_edit;
 
 typedef struct uvl_wave uvl_wave;   /* opaque handle */

@@ -9,6 +9,9 @@
 // first that selects it; a wave stops once each of its texels is taken or
 // uncovered), and store each texel's final label once.  The result is
 // bit-identical to applying the edits one launch at a time in order.
+// Numeric layers (§4.2) take the same path: their last selecting edit sets
+// or clears the mask bit, their last selecting SET gives the data, so a
+// texel stays open until a SET selects it.
 //
 // Work decomposition: edits are grouped by target layer into streams (each
 // stream keeps its edits' order); a stream's atlas is cut into 32 x 32-texel
@@ -41,6 +44,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "edit_texel.h"
@@ -62,7 +66,8 @@ constexpr int kWaveGrid = 2048;            // persistent workgroups (256 CUs x 8
 struct WaveStream {
     const float *px, *py, *pz;
     const float *box;   // per-tile position bounds, or null (no culling)
-    void *layer;
+    void *layer;        // label layer, or a numeric layer's data
+    uint32_t *vmask;    // a numeric layer's mask words (null for label layers)
     int64_t mask0;      // first cull-mask word of this stream (running offset)
     int64_t cwave0;     // first cull wave of this stream (one per block of 8 x 8 tiles)
     int64_t list0;      // first live-list entry of this stream
@@ -72,15 +77,15 @@ struct WaveStream {
     int32_t e0, ne;     // edits [e0, e0 + ne)
     int32_t chunks;     // tiles per item
     int32_t cull;       // 1: masks at mask0 (tiles x groups words), 0: no culling
-    int32_t pad;
+    int32_t numeric;    // 1: a numeric layer (edits SET / ERASE with value bits)
 };
 
 struct WaveEdit {
     int32_t kind;
-    uint32_t label;
+    uint32_t label;     // label, or a numeric SET's value bits
     float cx, cy, cz, r2;
     int32_t lasso;      // index into the lasso parameter array
-    int32_t pad;
+    int32_t erase;      // numeric layers: 1 for ERASE
     const float *depth;
 };
 
@@ -150,6 +155,50 @@ __device__ __forceinline__ void wave_store(T *L, int64_t t, const uint32_t val[4
 #pragma unroll
     for (int k = 0; k < 4; ++k)
         if (wr[k] && in[k]) L[t + k] = (T)val[k];
+}
+
+// Numeric layers: value bits where the data is decided (wd), and the mask
+// bits of texels whose mask is decided (wr) set (mset: a SET) or cleared (an
+// ERASE).  With group_word the 8 lanes of a tile row hold one 32-texel mask
+// word: they merge their bits with lane shuffles and one lane updates the
+// word (every lane must be active); a full tile otherwise has 4-aligned t,
+// so a lane's 4 bits share a word; partial tiles update texel by texel.
+template <typename T>
+__device__ __forceinline__ void wave_store_value(T *D, uint32_t *mask, int64_t t, const uint32_t val[4],
+                                                 const bool wd[4], const bool wr[4], const bool mset[4],
+                                                 const bool in[4], bool full, bool group_word) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (wd[k] && in[k]) D[t + k] = (T)val[k];
+    if (!full) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!(wr[k] && in[k])) continue;
+            const int64_t u = t + k;
+            if (mset[k]) atomicOr(mask + (u >> 5), 1u << (u & 31));
+            else atomicAnd(mask + (u >> 5), ~(1u << (u & 31)));
+        }
+        return;
+    }
+    uint32_t set = 0, clr = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        set |= (uint32_t)(wr[k] && mset[k]) << k;
+        clr |= (uint32_t)(wr[k] && !mset[k]) << k;
+    }
+    set <<= (t & 31);
+    clr <<= (t & 31);
+    if (group_word) {
+        set |= __shfl_xor(set, 1, 8);
+        set |= __shfl_xor(set, 2, 8);
+        set |= __shfl_xor(set, 4, 8);
+        clr |= __shfl_xor(clr, 1, 8);
+        clr |= __shfl_xor(clr, 2, 8);
+        clr |= __shfl_xor(clr, 4, 8);
+        if ((t & 31) != 0) return;
+    }
+    if (clr) atomicAnd(mask + (t >> 5), ~clr);
+    if (set) atomicOr(mask + (t >> 5), set);
 }
 
 // Last stream s (of n) with key(s) <= v; keys are non-decreasing.
@@ -347,46 +396,80 @@ __global__ __launch_bounds__(kBlock) void k_wave(char *__restrict__ ws, const ui
             // live edits from the last to the first: a texel takes the
             // label of the first edit (in this order) that selects it, i.e.
             // of its last selecting edit, and a wave stops once each of its
-            // texels is taken or uncovered (NaN position)
-            uint32_t val[4] = {0, 0, 0, 0};
-            bool wr[4] = {false, false, false, false};
+            // texels is taken or uncovered (NaN position).  In a numeric
+            // layer that edit decides the mask bit (SET: valid, ERASE:
+            // invalid), while the data is the value of the last selecting
+            // SET, so a texel stays open until a SET selects it.
             const bool cov[4] = {X.x == X.x, X.y == X.y, X.z == X.z, X.w == X.w};
-            bool open = true;
-            for (int g = groups - 1; g >= 0 && open; --g) {
-                uint64_t lm = cull ? tm[g] : ~0ull;
-                const uint64_t ins = cull ? tim[g] : 0ull;   // lassos containing the whole tile
-                const int base = g * 64;
-                const int lim = S.ne - base < 64 ? S.ne - base : 64;
-                if (lim < 64) lm &= (1ull << lim) - 1;
-                while (lm) {
-                    const int b = 63 - __builtin_clzll(lm);
-                    lm &= ~(1ull << b);
-                    const UVL_CONST WaveEdit &E = edits[S.e0 + base + b];
-                    bool sel[4];
-                    if (E.kind == UVL_EDIT_BRUSH) {
-                        const BrushParams B{E.cx, E.cy, E.cz, E.r2};
-                        sel[0] = brush_texel(B, X.x, Y.x, Z.x);
-                        sel[1] = brush_texel(B, X.y, Y.y, Z.y);
-                        sel[2] = brush_texel(B, X.z, Y.z, Z.z);
-                        sel[3] = brush_texel(B, X.w, Y.w, Z.w);
-                    } else {
-                        lasso_quad(lassos[E.lasso], E.depth, X, Y, Z, sel, ((ins >> b) & 1) != 0);
-                    }
-                    bool pending = false;
+            auto tile = [&](auto numeric_tag) {
+                constexpr bool kNum = decltype(numeric_tag)::value;
+                uint32_t val[4] = {0, 0, 0, 0};
+                bool wr[4] = {false, false, false, false};
+                bool wd[4] = {false, false, false, false}, mset[4] = {false, false, false, false};
+                bool open = true;
+                for (int g = groups - 1; g >= 0 && open; --g) {
+                    uint64_t lm = cull ? tm[g] : ~0ull;
+                    const uint64_t ins = cull ? tim[g] : 0ull;   // lassos containing the whole tile
+                    const int base = g * 64;
+                    const int lim = S.ne - base < 64 ? S.ne - base : 64;
+                    if (lim < 64) lm &= (1ull << lim) - 1;
+                    while (lm) {
+                        const int b = 63 - __builtin_clzll(lm);
+                        lm &= ~(1ull << b);
+                        const UVL_CONST WaveEdit &E = edits[S.e0 + base + b];
+                        bool sel[4];
+                        if (E.kind == UVL_EDIT_BRUSH) {
+                            const BrushParams B{E.cx, E.cy, E.cz, E.r2};
+                            sel[0] = brush_texel(B, X.x, Y.x, Z.x);
+                            sel[1] = brush_texel(B, X.y, Y.y, Z.y);
+                            sel[2] = brush_texel(B, X.z, Y.z, Z.z);
+                            sel[3] = brush_texel(B, X.w, Y.w, Z.w);
+                        } else {
+                            lasso_quad(lassos[E.lasso], E.depth, X, Y, Z, sel, ((ins >> b) & 1) != 0);
+                        }
+                        bool pending = false;
+                        if constexpr (kNum) {
+                            const bool set = E.erase == 0;
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        val[k] = sel[k] && !wr[k] ? E.label : val[k];
-                        wr[k] = wr[k] || sel[k];
-                        pending = pending || (cov[k] && !wr[k]);
-                    }
-                    if (__builtin_amdgcn_ballot_w64(pending) == 0) {
-                        open = false;
-                        break;
+                            for (int k = 0; k < 4; ++k) {
+                                mset[k] = sel[k] && !wr[k] ? set : mset[k];
+                                wr[k] = wr[k] || sel[k];
+                                val[k] = sel[k] && set && !wd[k] ? E.label : val[k];
+                                wd[k] = wd[k] || (sel[k] && set);
+                                pending = pending || (cov[k] && !wd[k]);
+                            }
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) {
+                                val[k] = sel[k] && !wr[k] ? E.label : val[k];
+                                wr[k] = wr[k] || sel[k];
+                                pending = pending || (cov[k] && !wr[k]);
+                            }
+                        }
+                        if (__builtin_amdgcn_ballot_w64(pending) == 0) {
+                            open = false;
+                            break;
+                        }
                     }
                 }
-            }
-            if (S.dtype == UVL_U8) wave_store<uint8_t>(static_cast<uint8_t *>(S.layer), t, val, wr, in, full);
-            else wave_store<uint16_t>(static_cast<uint16_t *>(S.layer), t, val, wr, in, full);
+                if constexpr (kNum) {
+                    const bool group_word = full && (W & 31) == 0;
+                    if (S.dtype == UVL_U8)
+                        wave_store_value<uint8_t>(static_cast<uint8_t *>(S.layer), S.vmask, t, val, wd, wr, mset, in,
+                                                  full, group_word);
+                    else if (S.dtype == UVL_U16 || S.dtype == UVL_F16)
+                        wave_store_value<uint16_t>(static_cast<uint16_t *>(S.layer), S.vmask, t, val, wd, wr, mset,
+                                                   in, full, group_word);
+                    else
+                        wave_store_value<uint32_t>(static_cast<uint32_t *>(S.layer), S.vmask, t, val, wd, wr, mset,
+                                                   in, full, group_word);
+                } else {
+                    if (S.dtype == UVL_U8) wave_store<uint8_t>(static_cast<uint8_t *>(S.layer), t, val, wr, in, full);
+                    else wave_store<uint16_t>(static_cast<uint16_t *>(S.layer), t, val, wr, in, full);
+                }
+            };
+            if (S.numeric) tile(std::true_type{});
+            else tile(std::false_type{});
         }
     }
 }
@@ -501,14 +584,27 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
     std::vector<int32_t> stream_of(n);
     std::vector<const void *> keys;
     std::vector<std::vector<int32_t>> members;
+    std::vector<uint32_t> bits(n, 0);       // label, or a numeric SET's value bits
     int32_t nl = 0;
     for (int32_t i = 0; i < n; ++i) {
         const uvl_edit &e = edits[i];
-        if (!e.geom || !e.layer) return UVL_E_INVAL;
-        if (!geom_pos_ok(e.geom) || !layer_ok(e.layer)) return UVL_E_INVAL;
-        if (!dtype_ok(e.layer->dtype)) return UVL_E_DTYPE;
-        if (e.label > dtype_max(e.layer->dtype)) return UVL_E_DTYPE;
-        if (e.layer->width != e.geom->width || e.layer->height != e.geom->height) return UVL_E_SHAPE;
+        const bool num = e.numeric != nullptr;
+        if (!e.geom || num == (e.layer != nullptr)) return UVL_E_INVAL;   // exactly one target
+        if (!geom_pos_ok(e.geom)) return UVL_E_INVAL;
+        if (num) {
+            if (!numeric_ok(e.numeric) || (e.mode != UVL_SET && e.mode != UVL_ERASE)) return UVL_E_INVAL;
+            if (e.mode == UVL_SET)
+                if (int32_t st = encode_value(e.numeric->dtype, e.value, bits[i])) return st;
+        } else {
+            if (!layer_ok(e.layer)) return UVL_E_INVAL;
+            if (!dtype_ok(e.layer->dtype)) return UVL_E_DTYPE;
+            if (e.label > dtype_max(e.layer->dtype)) return UVL_E_DTYPE;
+            bits[i] = e.label;
+        }
+        const int32_t tw = num ? e.numeric->width : e.layer->width, th = num ? e.numeric->height : e.layer->height;
+        const int32_t tdt = num ? e.numeric->dtype : e.layer->dtype;
+        const void *target = num ? e.numeric->data : e.layer->data;
+        if (tw != e.geom->width || th != e.geom->height) return UVL_E_SHAPE;
         if (e.kind == UVL_EDIT_BRUSH) {
             if (!(e.radius >= 0.0f) || !std::isfinite(e.radius)) return UVL_E_INVAL;
             if (!std::isfinite(e.center[0]) || !std::isfinite(e.center[1]) || !std::isfinite(e.center[2]))
@@ -520,15 +616,17 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
             return UVL_E_INVAL;
         }
         size_t k = 0;
-        while (k < keys.size() && keys[k] != e.layer->data) ++k;
+        while (k < keys.size() && keys[k] != target) ++k;
         if (k == keys.size()) {
-            keys.push_back(e.layer->data);
+            keys.push_back(target);
             members.emplace_back();
         } else {
-            // every edit of one layer must read the same positions
+            // every edit of one layer must read the same positions and
+            // describe the layer alike
             const uvl_edit &f = edits[members[k][0]];
-            if (f.geom->pos_x != e.geom->pos_x || f.layer->dtype != e.layer->dtype || f.layer->width != e.layer->width ||
-                f.layer->height != e.layer->height)
+            const bool fnum = f.numeric != nullptr;
+            if (f.geom->pos_x != e.geom->pos_x || fnum != num || f.geom->width != tw || f.geom->height != th ||
+                (fnum ? f.numeric->dtype != tdt || f.numeric->mask != e.numeric->mask : f.layer->dtype != tdt))
                 return UVL_E_INVAL;
         }
         members[k].push_back(i);
@@ -550,13 +648,14 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
         s.py = f.geom->pos_y;
         s.pz = f.geom->pos_z;
         s.box = f.geom->tile_box;
-        s.layer = f.layer->data;
-        s.W = f.layer->width;
-        s.H = f.layer->height;
+        s.numeric = f.numeric ? 1 : 0;
+        s.layer = f.numeric ? f.numeric->data : f.layer->data;
+        s.vmask = f.numeric ? f.numeric->mask : nullptr;
+        s.W = f.geom->width;
+        s.H = f.geom->height;
         s.tiles_x = (int32_t)ceil_div(s.W, UVL_TILE_SIDE);
         s.ntiles = s.tiles_x * (int32_t)ceil_div(s.H, UVL_TILE_SIDE);
-        s.dtype = f.layer->dtype;
-        s.pad = 0;
+        s.dtype = f.numeric ? f.numeric->dtype : f.layer->dtype;
         int ch = chunks_override > 0 ? chunks_override : w->tuned_chunks[log2_class((int64_t)s.W * s.H)];
         if (ch <= 0) ch = 4;
         s.chunks = std::min(std::max(ch, 1), kMaxChunks);
@@ -579,8 +678,8 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
             const uvl_edit &e = edits[i];
             WaveEdit &d = E[ei++];
             d.kind = e.kind;
-            d.label = e.label;
-            d.pad = 0;
+            d.label = bits[i];
+            d.erase = e.numeric && e.mode == UVL_ERASE ? 1 : 0;
             if (e.kind == UVL_EDIT_BRUSH) {
                 d.cx = e.center[0];
                 d.cy = e.center[1];
@@ -637,8 +736,8 @@ extern "C" int32_t uvl_wave_tune(uvl_wave *w, const uvl_edit *edits, int32_t n, 
     // size classes present in the wave
     std::vector<int> classes;
     for (int32_t i = 0; i < n; ++i) {
-        if (!edits[i].layer) return UVL_E_INVAL;
-        const int c = log2_class((int64_t)edits[i].layer->width * edits[i].layer->height);
+        if (!edits[i].geom) return UVL_E_INVAL;
+        const int c = log2_class((int64_t)edits[i].geom->width * edits[i].geom->height);
         if (std::find(classes.begin(), classes.end(), c) == classes.end()) classes.push_back(c);
     }
     hipEvent_t a, b;
@@ -651,7 +750,7 @@ extern "C" int32_t uvl_wave_tune(uvl_wave *w, const uvl_edit *edits, int32_t n, 
     for (int c : classes) {
         std::vector<uvl_edit> sub;
         for (int32_t i = 0; i < n; ++i)
-            if (log2_class((int64_t)edits[i].layer->width * edits[i].layer->height) == c) sub.push_back(edits[i]);
+            if (log2_class((int64_t)edits[i].geom->width * edits[i].geom->height) == c) sub.push_back(edits[i]);
         float best = INFINITY;
         int best_ch = 4;
         for (int ch : {1, 2, 4, 8}) {

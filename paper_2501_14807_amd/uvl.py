@@ -120,7 +120,8 @@ class CEdit(ctypes.Structure):
                 ("label", ctypes.c_uint32), ("center", ctypes.c_float * 3), ("radius", ctypes.c_float),
                 ("view_proj", ctypes.c_void_p), ("poly_xy", ctypes.c_void_p), ("npoly", ctypes.c_int32),
                 ("dw", ctypes.c_int32), ("dh", ctypes.c_int32), ("bias", ctypes.c_float),
-                ("depth", ctypes.c_void_p)]
+                ("depth", ctypes.c_void_p), ("numeric", ctypes.c_void_p), ("mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("value", ctypes.c_double)]
 
 
 def _lib():
@@ -661,7 +662,7 @@ def area_query(geom: GeometryImage, layers: Sequence[Layer], bins: Optional[torc
 # filled one tuple per edit and handed to the library without a copy
 EDIT_DTYPE = np.dtype({"names": [f[0] for f in CEdit._fields_],
                        "formats": ["<u8", "<u8", "<i4", "<u4", ("<f4", (3,)), "<f4", "<u8", "<u8", "<i4", "<i4",
-                                   "<i4", "<f4", "<u8"],
+                                   "<i4", "<f4", "<u8", "<u8", "<i4", "<i4", "<f8"],
                        "offsets": [getattr(CEdit, f[0]).offset for f in CEdit._fields_],
                        "itemsize": ctypes.sizeof(CEdit)})
 
@@ -690,7 +691,8 @@ class EditBatch:
     def brush(self, geom: GeometryImage, layer: Layer, center, radius: float, label: int):
         c = _f32(center, 3)
         i = self._slot()
-        self._a[i] = (geom.addr, layer.addr, EDIT_BRUSH, int(label), c, np.float32(radius), 0, 0, 0, 0, 0, 0.0, 0)
+        self._a[i] = (geom.addr, layer.addr, EDIT_BRUSH, int(label), c, np.float32(radius), 0, 0, 0, 0, 0, 0.0, 0,
+                      0, 0, 0, 0.0)
         self._keep.append((geom, layer))
 
     def lasso(self, geom: GeometryImage, layer: Layer, view_proj, poly, depth: torch.Tensor, bias: float,
@@ -700,7 +702,26 @@ class EditBatch:
         dh, dw = depth.shape
         i = self._slot()
         self._a[i] = (geom.addr, layer.addr, EDIT_LASSO, int(label), (0.0, 0.0, 0.0), 0.0, _addr(M), _addr(P),
-                      P.size // 2, dw, dh, np.float32(bias), depth.data_ptr())
+                      P.size // 2, dw, dh, np.float32(bias), depth.data_ptr(), 0, 0, 0, 0.0)
+        self._nl += 1
+        self._keep.append((geom, layer, M, P, depth))
+
+    def numeric_brush(self, geom: GeometryImage, layer: "NumericLayer", center, radius: float, mode: int,
+                      value: float = 0.0):
+        c = _f32(center, 3)
+        i = self._slot()
+        self._a[i] = (geom.addr, 0, EDIT_BRUSH, 0, c, np.float32(radius), 0, 0, 0, 0, 0, 0.0, 0,
+                      ctypes.addressof(layer.c), int(mode), 0, float(value))
+        self._keep.append((geom, layer))
+
+    def numeric_lasso(self, geom: GeometryImage, layer: "NumericLayer", view_proj, poly, depth: torch.Tensor,
+                      bias: float, mode: int, value: float = 0.0):
+        M = _f32(view_proj, 16)
+        P = _f32(poly).reshape(-1)
+        dh, dw = depth.shape
+        i = self._slot()
+        self._a[i] = (geom.addr, 0, EDIT_LASSO, 0, (0.0, 0.0, 0.0), 0.0, _addr(M), _addr(P), P.size // 2, dw, dh,
+                      np.float32(bias), depth.data_ptr(), ctypes.addressof(layer.c), int(mode), 0, float(value))
         self._nl += 1
         self._keep.append((geom, layer, M, P, depth))
 

@@ -175,6 +175,20 @@ def test_edit_records_match_the_c_struct():
     r1.view_proj, r1.poly_xy, r1.npoly = keep[2].ctypes.data, keep[3].ctypes.data, 3
     r1.dw, r1.dh, r1.bias, r1.depth = 64, 48, np.float32(1e-4), d.data_ptr()
     assert raw == bytes(r0) + bytes(r1)
+    # numeric edits: the layer slot is empty and the numeric descriptor,
+    # mode and value fill the trailing fields
+    nl = uvl.CNumeric(0x3000, 0x4000, 8, 8, uvl.F16)
+
+    class FakeNum:
+        c = nl
+
+    b.numeric_brush(g, FakeNum(), (1.0, 2.0, 3.0), 0.5, uvl.ERASE, -2.25)
+    raw = ctypes.string_at(b.array() + 2 * ctypes.sizeof(uvl.CEdit), ctypes.sizeof(uvl.CEdit))
+    r2 = uvl.CEdit()
+    r2.geom, r2.kind = 0x1000, uvl.EDIT_BRUSH
+    r2.center[0], r2.center[1], r2.center[2], r2.radius = 1.0, 2.0, 3.0, 0.5
+    r2.numeric, r2.mode, r2.value = ctypes.addressof(nl), uvl.ERASE, -2.25
+    assert raw == bytes(r2)
 
 
 def test_padding_validation(uvl):

@@ -1,6 +1,6 @@
 """Batched edit waves: one persistent launch == the edits applied one launch
 at a time, bit for bit, for every tile size, across models, layers, dtypes
-and ragged atlases; and against the CPU oracle."""
+and ragged atlases (label and numeric layers); and against the CPU oracle."""
 
 import numpy as np
 import pytest
@@ -333,3 +333,87 @@ def test_wave_adversarial_polygons(gpu):
             wave.submit(b1)
             assert np.array_equal(m.layers[0].numpy(), one), (ci, k)
         wave.close()
+
+
+def _numeric_edits(m, wl, edits, dtypes, seed):
+    """(edit, numeric layer index, mode, value) with every fourth an ERASE."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i, e in enumerate(edits):
+        k = int(rng.integers(0, len(dtypes)))
+        gpu_mode = 1 if i % 4 == 3 else 0
+        dt = dtypes[k]
+        value = {1: 200 - i % 50, 2: 40000 + i, 3: -1000 * i - 7, 4: 0.375 * i - 3.0, 5: 0.1 * i}[dt]
+        out.append((e, k, gpu_mode, value))
+    return out
+
+
+def _apply_numeric_plain(gpu, m, wl, items, layers):
+    for e, k, mode, value in items:
+        if e.kind == "brush":
+            gpu.numeric_brush(m.geom, layers[k], e.centre, e.radius, mode, value)
+        else:
+            M = wl.cameras[e.camera]
+            gpu.numeric_lasso(m.geom, layers[k], M, e.poly, m.depth_for(e.camera, M), m.bias, mode, value)
+
+
+def _add_numeric_batch(gpu, batch, m, wl, items, layers):
+    """Numeric edits into a batch; each camera gets its own depth map, kept
+    alive by the batch (the model's small depth cache would recycle them
+    before the wave runs)."""
+    import torch
+    maps = {}
+    for e, k, mode, value in items:
+        if e.kind == "brush":
+            batch.numeric_brush(m.geom, layers[k], e.centre, e.radius, mode, value)
+        else:
+            M = wl.cameras[e.camera]
+            if e.camera not in maps:
+                d = torch.empty((m.depth_h, m.depth_w), dtype=torch.float32, device="cuda")
+                gpu.render_depth(m.mesh, M, d, m.depth_ws)
+                maps[e.camera] = d
+            batch.numeric_lasso(m.geom, layers[k], M, e.poly, maps[e.camera], m.bias, mode, value)
+
+
+def test_wave_numeric_layers_equal_plain(gpu):
+    """Numeric layers in waves (SET and ERASE, every dtype, widths a multiple
+    of 32 and not), mixed with label layers in the same waves: data bits and
+    mask words identical to the numeric single-edit calls in order."""
+    import torch
+    from paper_2501_14807_amd.model import Model
+    tiny = synth.tiny_workload()
+    scan = synth.scan_workload(n_brush=30, n_lasso=30, n_ops=0, W=1024, n_charts=4, nx=64, ny=32, depth=512)
+    # widths 1024 (a multiple of 32), 396 (of 4 only) and 407 (neither)
+    setups = [(Model.from_workload(scan).build(), scan),
+              (Model(tiny.mesh, 396, 200, [gpu.U8], depth_w=128, depth_h=96).build(), tiny),
+              (Model(tiny.mesh, 37 * 11, 53 * 5, [gpu.U8], depth_w=128, depth_h=96).build(), tiny)]
+    for seed, (m, wl) in enumerate(setups):
+        W, H = m.geom.width, m.geom.height
+        kinds = [gpu.U8, gpu.U16, gpu.I32, gpu.F16, gpu.F32]
+        ref = [gpu.numeric_create(gpu.NumericLayer(W, H, dt)) for dt in kinds]
+        got = [gpu.numeric_create(gpu.NumericLayer(W, H, dt)) for dt in kinds]
+        items = _numeric_edits(m, wl, wl.edits, kinds, seed)
+        _apply_numeric_plain(gpu, m, wl, items, ref)
+        label_edits = [e for e in wl.edits[:20] if e.layer < len(m.layers)]
+        m.clear_layers()
+        m.apply_all(label_edits, wl.cameras)
+        lab_ref = [l.numpy().copy() for l in m.layers]
+        n = len(items) + 20
+        for chunks in (1, 4):
+            for L in got:
+                gpu.numeric_create(L)
+            m.clear_layers()
+            wave = gpu.Wave(max_edits=n, max_lassos=n)
+            batch = gpu.EditBatch()
+            m.add_to_batch(batch, label_edits, wl.cameras)
+            _add_numeric_batch(gpu, batch, m, wl, items, got)
+            wave.submit(batch, tile_chunks=chunks)
+            torch.cuda.synchronize()
+            for dt, r, g in zip(kinds, ref, got):
+                assert r.valid().any() and not r.valid().all(), (seed, dt)
+                assert np.array_equal(g.mask_words(), r.mask_words()), (seed, chunks, dt)
+                ut = {1: np.uint8, 2: np.uint16, 4: np.uint32}[r.numpy().dtype.itemsize]
+                assert np.array_equal(g.numpy().view(ut), r.numpy().view(ut)), (seed, chunks, dt)
+            for k, l in enumerate(m.layers):
+                assert np.array_equal(l.numpy(), lab_ref[k]), (seed, chunks, k)
+            wave.close()
