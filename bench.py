@@ -1,6 +1,6 @@
 """Benchmark of the texture-layer hot path on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload scan|tiny] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--workload scan|max|tiny] [--no-cpu-baseline]
 
 Workload (default): the scan-scale model -- 64 displaced 256x128-vertex charts
 (4,145,280 triangles) shelf-packed into an 8192^2 atlas, 8 u8 + 1 u16 layers,
@@ -53,7 +53,9 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", default="scan", choices=["scan", "tiny"])
+    p.add_argument("--workload", default="scan", choices=["scan", "tiny", "max"],
+                   help="scan: the 8192^2 scan-scale model (default); max: the 16384^2 model, 10,000 edits, "
+                        "also applied as waves of 256; tiny: the vessel")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-rows", type=int, default=64, help="atlas rows in the oracle's timed sample")
     p.add_argument("--cpu-edits", type=int, default=200, help="edits in the oracle's timed sample")
@@ -70,6 +72,10 @@ def make_workload(name):
     import synth
     if name == "tiny":
         return synth.tiny_workload(), "vessel 128^2 vertices (32,258 tris), 512^2 atlas, 1 u8 layer, 64 edits"
+    if name == "max":
+        return synth.max_workload(), ("max model: 256 displaced 128x128 charts (8,258,048 tris), 16384^2 atlas, "
+                                      "32 u8 layers, 5000 brush + 5000 lasso (2048^2 depth) + 80 layer ops + "
+                                      "per-label area (one fused pass per 8 layers)")
     wl = synth.scan_workload()
     return wl, ("scan-scale: 64 displaced 256x128 charts (4,145,280 tris), 8192^2 atlas, 8 u8 + 1 u16 layers, "
                 "1000 brush + 1000 lasso (2048^2 depth) + 256 layer ops + per-label area")
@@ -376,6 +382,53 @@ def bench_numeric(m, wl, uvl, torch, n_edits=100, reps=10):
             "select_us": sel_us, "select_gbps": N * 4.125 / (sel_us * 1e-6) / 1e9}
 
 
+def bench_radius(m, wl, uvl, torch, reps=20):
+    """Brush time against radius (the paper's edit cost does not depend on
+    the tool size): one centre from the workload, radii 0.01 .. 0.2."""
+    e = next(x for x in wl.edits if x.kind == "brush")
+    lay = m.layers[e.layer]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = []
+    for r in (0.01, 0.02, 0.05, 0.1, 0.2):
+        uvl.edit_brush(m.geom, lay, e.centre, r, 1)
+        e0.record()
+        for _ in range(reps):
+            uvl.edit_brush(m.geom, lay, e.centre, r, 1)
+        e1.record()
+        torch.cuda.synchronize()
+        out.append({"radius": r, "us": e0.elapsed_time(e1) * 1e3 / reps})
+    us = [x["us"] for x in out]
+    return {"sweep": out, "max_over_min": max(us) / min(us)}
+
+
+def bench_max_waves(m, wl, uvl, torch, per_wave=256):
+    """The max model's edits again as waves of `per_wave` edits (one launch
+    each), against the layers of the timed plain step (edits, then layer
+    operations)."""
+    ref = [l.numpy().copy() for l in m.layers]
+    for l in m.layers:
+        uvl.create_layer(l)
+    wave = uvl.Wave(per_wave, per_wave, max_cull_words=1 << 24)
+    batches = []
+    for i in range(0, len(wl.edits), per_wave):
+        b = uvl.EditBatch(per_wave)
+        m.add_to_batch(b, wl.edits[i:i + per_wave], wl.cameras)
+        batches.append(b)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for b in batches:
+        wave.submit(b)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t)
+    for o in wl.ops:          # the step's layer operations, untimed, before comparing
+        m.apply_op(o)
+    same = all(np.array_equal(l.numpy(), r) for l, r in zip(m.layers, ref))
+    wave.close()
+    return {"edits": len(wl.edits), "per_wave": per_wave, "waves": len(batches), "ms": ms,
+            "edits_per_s": len(wl.edits) / (ms * 1e-3), "identical_to_plain": same,
+            "note": "edits only (depth maps rendered before timing); compared after the step's layer operations"}
+
+
 def copy_bandwidth(torch, nbytes=2 << 30, reps=10):
     """Achievable HBM bandwidth of a plain device-to-device copy (read + write)."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -486,7 +539,8 @@ def main():
     achieved = per_launch[kern] / avg_s / 1e9
     srcs = ["paper_2501_14807_amd/csrc/edit.hip", "paper_2501_14807_amd/csrc/edit_texel.h",
             "paper_2501_14807_amd/csrc/sink.h"]
-    traffic = traffic_from_profiles(kern, srcs)
+    # the committed counter summary was taken on the scan-scale workload
+    traffic = traffic_from_profiles(kern, srcs) if args.workload == "scan" else None
     kernels = {}
     for k, s in stats.items():
         ent = dict(s)
@@ -498,25 +552,33 @@ def main():
     if "area_query" in stats:
         ab = N * (4 + sum(layer_bytes))
         kernels["area_query"]["gbps"] = ab / (stats["area_query"]["avg_us"] * 1e-6) / 1e9
-    tool = bench_tool(m, wl, uvl, torch)
-    log(f"screen-space tool: {tool['tool_us']:.1f} us per edit ({tool['gbps']:.0f} GB/s)")
-    padding = bench_padding(m, wl, uvl, torch)
-    log(f"padding: {padding['outline_texels']} outline texels, brush {padding['pad_brush_us']:.1f} us, "
-        f"lasso {padding['pad_lasso_us']:.1f} us per edit")
-    numeric = bench_numeric(m, wl, uvl, torch)
-    log(f"numeric f32: lasso SET {numeric['lasso_set_us']:.1f} us (label {numeric['label_lasso_us']:.1f} us), "
-        + ", ".join(f"stats[{k}] {v['us']:.1f} us {v['gbps']:.0f} GB/s" for k, v in numeric["stats"].items())
-        + f", select {numeric['select_us']:.1f} us")
+    tool = padding = numeric = radius = max_waves = None
+    if args.workload == "max":
+        max_waves = bench_max_waves(m, wl, uvl, torch)
+        log(f"max model as waves of 256: {max_waves['ms']:.1f} ms for {max_waves['edits']} edits "
+            f"(identical: {max_waves['identical_to_plain']})")
+    else:
+        tool = bench_tool(m, wl, uvl, torch)
+        log(f"screen-space tool: {tool['tool_us']:.1f} us per edit ({tool['gbps']:.0f} GB/s)")
+        padding = bench_padding(m, wl, uvl, torch)
+        log(f"padding: {padding['outline_texels']} outline texels, brush {padding['pad_brush_us']:.1f} us, "
+            f"lasso {padding['pad_lasso_us']:.1f} us per edit")
+        numeric = bench_numeric(m, wl, uvl, torch)
+        log(f"numeric f32: lasso SET {numeric['lasso_set_us']:.1f} us (label {numeric['label_lasso_us']:.1f} us), "
+            + ", ".join(f"stats[{k}] {v['us']:.1f} us {v['gbps']:.0f} GB/s" for k, v in numeric["stats"].items())
+            + f", select {numeric['select_us']:.1f} us")
+        radius = bench_radius(m, wl, uvl, torch)
+        log("brush time by radius: " + ", ".join(f"{x['radius']}: {x['us']:.1f} us" for x in radius["sweep"]))
     copy_gbps = copy_bandwidth(torch)
     log(f"device copy bandwidth {copy_gbps:.0f} GB/s")
     batched = None
-    if args.batch_models > 0:
+    if args.batch_models > 0 and args.workload != "max":
         del m
         torch.cuda.empty_cache()
         batched = bench_batched(args.batch_models, 2, torch, uvl)
         torch.cuda.empty_cache()
     serving = None
-    if args.serve_models > 0:
+    if args.serve_models > 0 and args.workload != "max":
         serving = bench_serving(args.serve_models, args.serve_requests, args.serve_slo_ms, torch, uvl)
 
     out = {
@@ -544,6 +606,8 @@ def main():
         "tool": tool,
         "padding": padding,
         "numeric": numeric,
+        "radius_sweep": radius,
+        "max_waves": max_waves,
         "batched": batched,
         "serving": serving,
     }
