@@ -537,7 +537,7 @@ def traffic_from_profiles(kernel_key, src_files):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (--gpus {args.gpus} requested)",
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (--gpus {args.gpus} requested)",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
