@@ -349,14 +349,15 @@ int32_t uvl_numeric_pad_lasso(const uvl_geom *geom, const uvl_numeric *layer, co
                               void *stream);
 
 /* Zonal statistics of a numeric layer (Table 1 gives the surface area one
- * texel stands for; weighting values by it gives area-weighted means, area
- * wsum / area_w).  Counted texels: covered (tri_id >= 0) with the mask bit
- * set.  They are grouped by the value of the label layer `region` (u8: 256
+ * texel stands for; weighting values by it gives the area-weighted mean
+ * wsum / area_w of a group).  Counted texels: covered (tri_id >= 0) with
+ * the mask bit set.  They are grouped by the value of the label layer `region` (u8: 256
  * groups, u16: 65536), or form one group when region is NULL.  bins_dev:
  * device uvl_numstat[groups], 8-byte aligned, overwritten.  If bins_host is
  * non-NULL the call is SYNCHRONOUS and copies the groups there; otherwise
  * it is asynchronous.  wsum is within (count + 1) * 2^-53 * sum |area_w v|
- * of the exact sum.
+ * of the exact sum.  A NaN value (edits never store one; the caller's own
+ * writes can) leaves its group's wsum, vmin and vmax unspecified.
  * Errors: UVL_E_INVAL (pointers, alignment), UVL_E_SHAPE, UVL_E_DTYPE. */
 int32_t uvl_numeric_stats(const uvl_geom *geom, const uvl_numeric *layer, const uvl_layer *region,
                           uvl_numstat *bins_dev, uvl_numstat *bins_host, void *stream);
