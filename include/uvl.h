@@ -415,13 +415,16 @@ int32_t uvl_pool_destroy(uvl_pool *pool);
  * the texel's stored position, so the result of a wave is bit-identical to
  * calling uvl_edit_brush / uvl_edit_lasso once per edit in array order.
  * ------------------------------------------------------------------------ */
-typedef enum { UVL_EDIT_BRUSH = 0, UVL_EDIT_LASSO = 1 } uvl_edit_kind;
+typedef enum { UVL_EDIT_BRUSH = 0, UVL_EDIT_LASSO = 1, UVL_EDIT_TOOL = 2 } uvl_edit_kind;
 
 /* One edit of a wave.  geom and layer are host pointers to descriptors of
  * device data (as for the single-edit calls); all edits of one layer must
  * name the same geometry image.  Brush: center, radius.  Lasso: view_proj
  * (host float[16]), poly_xy (host float[npoly][2], 3 <= npoly <= 64), depth
- * (device [dh][dw] map rendered with that matrix), bias.  With numeric
+ * (device [dh][dw] map rendered with that matrix), bias.  Tool (the paper's
+screen-space tool, as uvl_edit_tool): view_proj, depth, dw, dh, bias as for
+a lasso, tool (host double[6]), shape (device u8 [sh][sw]); tools count
+towards the wave's lasso capacity.  With numeric
  * non-NULL (and layer NULL) the edit SETs or ERASEs that numeric layer
  * (mode, value as for uvl_numeric_brush / uvl_numeric_lasso; label ignored):
  * the result is that of the numeric single-edit calls in array order.
@@ -443,6 +446,9 @@ typedef struct {
     int32_t mode;           /* uvl_value_mode */
     int32_t reserved;       /* 0 */
     double value;
+    const double *tool;     /* tool edits: {Ww, Wh, Tpx, Tpy, Tw, Th} */
+    const uint8_t *shape;
+    int32_t sw, sh;
 } uvl_edit;
 
 typedef struct uvl_wave uvl_wave;   /* opaque handle */

@@ -21,6 +21,7 @@
 
 #include "edit_texel.h"
 #include "sink.h"
+#include "tool_texel.h"
 #include "uvl_internal.h"
 
 namespace uvl {
@@ -28,46 +29,6 @@ namespace {
 
 constexpr int kChunk = kBlock * 4;
 constexpr int kTile = 4 * kChunk;
-constexpr int kMaxShape = 4096;
-
-struct ToolParams {
-    float M[16];
-    float ax, bx, ay, by;                  // s = fmaf(xn, ax, bx), t = fmaf(yn, ay, by)
-    float xlo_m, xhi_m, ylo_m, yhi_m;      // NDC range with s, t in [0, 1] and in the frustum, widened
-    int32_t sw, sh, dw, dh;
-    float bias;
-};
-
-__device__ __forceinline__ bool tool_texel(const ToolParams &P, const uint8_t *__restrict__ shape,
-                                           const float *__restrict__ depth, float x, float y, float z) {
-    float c[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        c[k] = __builtin_fmaf(P.M[4 * k + 2], z, __builtin_fmaf(P.M[4 * k + 1], y, __builtin_fmaf(P.M[4 * k + 0], x, P.M[4 * k + 3])));
-    if (!(c[3] > 0.0f)) return false;
-    if (c[3] >= 1e-30f) {
-        // reciprocal pre-test: within 3e-7 relative of the exact quotients,
-        // far inside the margins of the bounds
-        const float r = __builtin_amdgcn_rcpf(c[3]);
-        const float ax = c[0] * r, ay = c[1] * r;
-        if (!(ax >= P.xlo_m && ax <= P.xhi_m && ay >= P.ylo_m && ay <= P.yhi_m)) return false;
-    }
-    const float xn = c[0] / c[3], yn = c[1] / c[3], zn = c[2] / c[3];
-    if (!(xn >= -1.0f && xn <= 1.0f && yn >= -1.0f && yn <= 1.0f && zn >= -1.0f && zn <= 1.0f)) return false;
-    const float s = __builtin_fmaf(xn, P.ax, P.bx), t = __builtin_fmaf(yn, P.ay, P.by);
-    if (!(s >= 0.0f && s <= 1.0f && t >= 0.0f && t <= 1.0f)) return false;
-    int sx = (int)floorf(s * (float)P.sw), sy = (int)floorf(t * (float)P.sh);
-    sx = sx > P.sw - 1 ? P.sw - 1 : sx;
-    sy = sy > P.sh - 1 ? P.sh - 1 : sy;
-    if (!shape[(int64_t)sy * P.sw + sx]) return false;
-    int ix = (int)floorf(__builtin_fmaf(xn, 0.5f, 0.5f) * (float)P.dw);
-    int iy = (int)floorf(__builtin_fmaf(yn, 0.5f, 0.5f) * (float)P.dh);
-    ix = ix > P.dw - 1 ? P.dw - 1 : ix;
-    iy = iy > P.dh - 1 ? P.dh - 1 : iy;
-    const float d = __builtin_fmaf(zn, 0.5f, 0.5f);
-    return d <= depth[(int64_t)iy * P.dw + ix] + P.bias;
-}
-
 template <typename Sink>
 __global__ __launch_bounds__(kBlock) void k_tool(const float *__restrict__ px, const float *__restrict__ py,
                                                  const float *__restrict__ pz, Sink out, int64_t n, ToolParams p,
@@ -98,10 +59,12 @@ __global__ __launch_bounds__(kBlock) void k_tool(const float *__restrict__ px, c
     }
 }
 
+}  // namespace
+
 // The NDC range of one axis where the tool coordinate a x + b lies in
 // [0, 1], clipped to the frustum and widened for the reciprocal pre-test
 // (1e-4 relative, plus the rounding of a x + b near 1 seen in x).
-void tool_range(double a, double b, float &lo, float &hi) {
+static void tool_range(double a, double b, float &lo, float &hi) {
     double x0 = -b / a, x1 = (1.0 - b) / a;
     x0 = fmax(x0, -1.0);
     x1 = fmin(x1, 1.0);
@@ -110,17 +73,9 @@ void tool_range(double a, double b, float &lo, float &hi) {
     hi = (float)(x1 + m);
 }
 
-}  // namespace
-}  // namespace uvl
-
-using namespace uvl;
-
-namespace {
-
-// Tool arguments shared by the label and numeric calls.
-bool tool_args(const float view_proj[16], const double tool[6], const uint8_t *shape, int32_t sw, int32_t sh,
-               const float *depth, int32_t dw, int32_t dh, float bias, ToolParams &p) {
-    if (!view_proj || !tool || !shape || !depth) return false;
+bool make_tool_params(const float view_proj[16], const double tool[6], int32_t sw, int32_t sh, int32_t dw,
+                      int32_t dh, float bias, ToolParams &p) {
+    if (!view_proj || !tool) return false;
     for (int k = 0; k < 16; ++k)
         if (!std::isfinite(view_proj[k])) return false;
     for (int k = 0; k < 6; ++k)
@@ -146,6 +101,12 @@ bool tool_args(const float view_proj[16], const double tool[6], const uint8_t *s
     return true;
 }
 
+}  // namespace uvl
+
+using namespace uvl;
+
+namespace {
+
 template <typename Sink>
 void launch_tool(const uvl_geom *geom, const ToolParams &p, const uint8_t *shape, const float *depth, const Sink &out,
                  hipStream_t s) {
@@ -161,7 +122,7 @@ extern "C" int32_t uvl_edit_tool(const uvl_geom *geom, const uvl_layer *layer, c
                                  const float *depth, int32_t dw, int32_t dh, float bias, uint32_t label,
                                  void *stream) {
     ToolParams p;
-    if (!tool_args(view_proj, tool, shape, sw, sh, depth, dw, dh, bias, p)) return UVL_E_INVAL;
+    if (!shape || !depth || !make_tool_params(view_proj, tool, sw, sh, dw, dh, bias, p)) return UVL_E_INVAL;
     if (!geom_pos_ok(geom) || !layer_ok(layer)) return UVL_E_INVAL;
     if (!dtype_ok(layer->dtype) || label > dtype_max(layer->dtype)) return UVL_E_DTYPE;
     if (layer->width != geom->width || layer->height != geom->height) return UVL_E_SHAPE;
@@ -175,7 +136,7 @@ extern "C" int32_t uvl_numeric_tool(const uvl_geom *geom, const uvl_numeric *lay
                                     const float *depth, int32_t dw, int32_t dh, float bias, int32_t mode,
                                     double value, void *stream) {
     ToolParams p;
-    if (!tool_args(view_proj, tool, shape, sw, sh, depth, dw, dh, bias, p)) return UVL_E_INVAL;
+    if (!shape || !depth || !make_tool_params(view_proj, tool, sw, sh, dw, dh, bias, p)) return UVL_E_INVAL;
     uint32_t bits = 0;
     if (int32_t s = check_numeric_edit(geom, layer, mode, value, bits)) return s;
     with_value_sink(layer, bits, mode, [&](auto out) { launch_tool(geom, p, shape, depth, out, as_stream(stream)); });

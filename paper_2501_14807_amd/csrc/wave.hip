@@ -48,6 +48,7 @@
 #include <vector>
 
 #include "edit_texel.h"
+#include "tool_texel.h"
 #include "uvl_internal.h"
 
 namespace uvl {
@@ -84,9 +85,10 @@ struct WaveEdit {
     int32_t kind;
     uint32_t label;     // label, or a numeric SET's value bits
     float cx, cy, cz, r2;
-    int32_t lasso;      // index into the lasso parameter array
+    int32_t lasso;      // index into the lasso (and, for tools, tool) parameter arrays
     int32_t erase;      // numeric layers: 1 for ERASE
     const float *depth;
+    const uint8_t *shape;   // tools: the shape texture
 };
 
 // Byte offsets, within the workspace, of the regions of one packed wave.
@@ -95,7 +97,7 @@ struct WaveHeader {
     int32_t pad;
     int64_t total_cull_waves;
     int64_t total_items;     // written by k_wave_plan
-    uint64_t off_streams, off_live_n, off_item0, off_edits, off_lassos;
+    uint64_t off_streams, off_live_n, off_item0, off_edits, off_lassos, off_tools;
     unsigned int counter;
     unsigned int pad2[3];
 };
@@ -104,14 +106,17 @@ size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Offsets of the descriptor regions for ns streams, n edits, nl lassos:
 // header | streams | live counts (uint32 per stream) | item starts (int64 per
-// stream + 1) | edits | lassos.
+// stream + 1) | edits | lassos | tools.  A tool edit takes the lasso slot
+// of its index for a rectangle at its square's widened NDC range (used by
+// the tile culling only) and the tool slot of the same index.
 void descriptor_offsets(int64_t ns, int64_t n, int64_t nl, WaveHeader &h, size_t &end) {
     h.off_streams = 256;
     h.off_live_n = al256(h.off_streams + sizeof(WaveStream) * (size_t)ns);
     h.off_item0 = al256(h.off_live_n + sizeof(uint32_t) * (size_t)ns);
     h.off_edits = al256(h.off_item0 + sizeof(int64_t) * (size_t)(ns + 1));
     h.off_lassos = al256(h.off_edits + sizeof(WaveEdit) * (size_t)n);
-    end = h.off_lassos + sizeof(LassoParams) * (size_t)nl;
+    h.off_tools = al256(h.off_lassos + sizeof(LassoParams) * (size_t)nl);
+    end = h.off_tools + sizeof(ToolParams) * (size_t)nl;
 }
 
 // Workspace layout: descriptor (at most `masks` bytes) | cull masks (uint64
@@ -269,7 +274,8 @@ __global__ __launch_bounds__(kBlock) void k_wave_cull(char *__restrict__ ws, uin
                 const int cls = brush ? (brush_culls(B, box) ? kTileCulled : kTileLive)
                                       : lasso_tile(lassos[E.lasso], box, E.depth);
                 m |= (uint64_t)(cls != kTileCulled) << k;
-                im |= (uint64_t)(cls == kTileInside) << k;
+                // a tool's shape can still exclude texels of a tile inside its square
+                im |= (uint64_t)(cls == kTileInside && E.kind == UVL_EDIT_LASSO) << k;
             }
             if (in && (groups > 1 || m != 0)) {
                 masks[S.mask0 + ti * groups + g] = m;
@@ -338,6 +344,7 @@ __global__ __launch_bounds__(kBlock) void k_wave(char *__restrict__ ws, const ui
     const UVL_CONST WaveStream *streams = (const UVL_CONST WaveStream *)(ws + chdr->off_streams);
     const UVL_CONST WaveEdit *edits = (const UVL_CONST WaveEdit *)(ws + chdr->off_edits);
     const UVL_CONST LassoParams *lassos = (const UVL_CONST LassoParams *)(ws + chdr->off_lassos);
+    const UVL_CONST ToolParams *tools = (const UVL_CONST ToolParams *)(ws + chdr->off_tools);
     const UVL_CONST uint32_t *live_n = (const UVL_CONST uint32_t *)(ws + chdr->off_live_n);
     const UVL_CONST int64_t *item0 = (const UVL_CONST int64_t *)(ws + chdr->off_item0);
     const UVL_CONST uint64_t *masks = (const UVL_CONST uint64_t *)masks_in;
@@ -424,8 +431,14 @@ __global__ __launch_bounds__(kBlock) void k_wave(char *__restrict__ ws, const ui
                             sel[1] = brush_texel(B, X.y, Y.y, Z.y);
                             sel[2] = brush_texel(B, X.z, Y.z, Z.z);
                             sel[3] = brush_texel(B, X.w, Y.w, Z.w);
-                        } else {
+                        } else if (E.kind == UVL_EDIT_LASSO) {
                             lasso_quad(lassos[E.lasso], E.depth, X, Y, Z, sel, ((ins >> b) & 1) != 0);
+                        } else {
+                            const UVL_CONST ToolParams &T = tools[E.lasso];
+                            sel[0] = tool_texel(T, E.shape, E.depth, X.x, Y.x, Z.x);
+                            sel[1] = tool_texel(T, E.shape, E.depth, X.y, Y.y, Z.y);
+                            sel[2] = tool_texel(T, E.shape, E.depth, X.z, Y.z, Z.z);
+                            sel[3] = tool_texel(T, E.shape, E.depth, X.w, Y.w, Z.w);
                         }
                         bool pending = false;
                         if constexpr (kNum) {
@@ -609,8 +622,9 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
             if (!(e.radius >= 0.0f) || !std::isfinite(e.radius)) return UVL_E_INVAL;
             if (!std::isfinite(e.center[0]) || !std::isfinite(e.center[1]) || !std::isfinite(e.center[2]))
                 return UVL_E_INVAL;
-        } else if (e.kind == UVL_EDIT_LASSO) {
+        } else if (e.kind == UVL_EDIT_LASSO || e.kind == UVL_EDIT_TOOL) {
             if (!e.depth || !e.view_proj || e.dw > kMaxDepthSide || e.dh > kMaxDepthSide) return UVL_E_INVAL;
+            if (e.kind == UVL_EDIT_TOOL && (!e.tool || !e.shape)) return UVL_E_INVAL;
             if (++nl > w->max_lassos) return UVL_E_NOMEM;
         } else {
             return UVL_E_INVAL;
@@ -639,6 +653,7 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
     uint32_t *live_n = reinterpret_cast<uint32_t *>(st + hdr->off_live_n);
     WaveEdit *E = reinterpret_cast<WaveEdit *>(st + hdr->off_edits);
     LassoParams *P = reinterpret_cast<LassoParams *>(st + hdr->off_lassos);
+    ToolParams *TP = reinterpret_cast<ToolParams *>(st + hdr->off_tools);
     int64_t words = 0, cwaves = 0;
     int32_t ei = 0, li = 0;
     for (size_t k = 0; k < keys.size(); ++k) {
@@ -687,14 +702,25 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
                 d.r2 = e.radius * e.radius;
                 d.lasso = -1;
                 d.depth = nullptr;
-            } else {
+            } else if (e.kind == UVL_EDIT_LASSO) {
                 if (!make_lasso_params(e.view_proj, e.poly_xy, e.npoly, e.dw, e.dh, e.bias, P[li])) return UVL_E_INVAL;
                 for (int q = 0; q < 16; ++q)
                     if (!std::isfinite(e.view_proj[q])) return UVL_E_INVAL;
                 d.cx = d.cy = d.cz = d.r2 = 0.0f;
                 d.lasso = li++;
                 d.depth = e.depth;
+            } else {
+                // the tool itself, and for culling a rectangle holding every
+                // texel it can select: its square's NDC range, widened
+                ToolParams &T = TP[li];
+                if (!make_tool_params(e.view_proj, e.tool, e.sw, e.sh, e.dw, e.dh, e.bias, T)) return UVL_E_INVAL;
+                const float rect[8] = {T.xlo_m, T.ylo_m, T.xhi_m, T.ylo_m, T.xhi_m, T.yhi_m, T.xlo_m, T.yhi_m};
+                if (!make_lasso_params(e.view_proj, rect, 4, e.dw, e.dh, e.bias, P[li])) return UVL_E_INVAL;
+                d.cx = d.cy = d.cz = d.r2 = 0.0f;
+                d.lasso = li++;
+                d.depth = e.depth;
             }
+            d.shape = e.kind == UVL_EDIT_TOOL ? e.shape : nullptr;
         }
     }
     hdr->nstreams = (int32_t)keys.size();

@@ -112,7 +112,7 @@ SIGNATURES = {
     "uvl_pool_destroy": ([_P], _I32),
 }
 
-EDIT_BRUSH, EDIT_LASSO = 0, 1
+EDIT_BRUSH, EDIT_LASSO, EDIT_TOOL = 0, 1, 2
 
 
 class CEdit(ctypes.Structure):
@@ -121,7 +121,8 @@ class CEdit(ctypes.Structure):
                 ("view_proj", ctypes.c_void_p), ("poly_xy", ctypes.c_void_p), ("npoly", ctypes.c_int32),
                 ("dw", ctypes.c_int32), ("dh", ctypes.c_int32), ("bias", ctypes.c_float),
                 ("depth", ctypes.c_void_p), ("numeric", ctypes.c_void_p), ("mode", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("value", ctypes.c_double)]
+                ("reserved", ctypes.c_int32), ("value", ctypes.c_double), ("tool", ctypes.c_void_p),
+                ("shape", ctypes.c_void_p), ("sw", ctypes.c_int32), ("sh", ctypes.c_int32)]
 
 
 def _lib():
@@ -662,7 +663,7 @@ def area_query(geom: GeometryImage, layers: Sequence[Layer], bins: Optional[torc
 # filled one tuple per edit and handed to the library without a copy
 EDIT_DTYPE = np.dtype({"names": [f[0] for f in CEdit._fields_],
                        "formats": ["<u8", "<u8", "<i4", "<u4", ("<f4", (3,)), "<f4", "<u8", "<u8", "<i4", "<i4",
-                                   "<i4", "<f4", "<u8", "<u8", "<i4", "<i4", "<f8"],
+                                   "<i4", "<f4", "<u8", "<u8", "<i4", "<i4", "<f8", "<u8", "<u8", "<i4", "<i4"],
                        "offsets": [getattr(CEdit, f[0]).offset for f in CEdit._fields_],
                        "itemsize": ctypes.sizeof(CEdit)})
 
@@ -692,7 +693,7 @@ class EditBatch:
         c = _f32(center, 3)
         i = self._slot()
         self._a[i] = (geom.addr, layer.addr, EDIT_BRUSH, int(label), c, np.float32(radius), 0, 0, 0, 0, 0, 0.0, 0,
-                      0, 0, 0, 0.0)
+                      0, 0, 0, 0.0, 0, 0, 0, 0)
         self._keep.append((geom, layer))
 
     def lasso(self, geom: GeometryImage, layer: Layer, view_proj, poly, depth: torch.Tensor, bias: float,
@@ -702,7 +703,7 @@ class EditBatch:
         dh, dw = depth.shape
         i = self._slot()
         self._a[i] = (geom.addr, layer.addr, EDIT_LASSO, int(label), (0.0, 0.0, 0.0), 0.0, _addr(M), _addr(P),
-                      P.size // 2, dw, dh, np.float32(bias), depth.data_ptr(), 0, 0, 0, 0.0)
+                      P.size // 2, dw, dh, np.float32(bias), depth.data_ptr(), 0, 0, 0, 0.0, 0, 0, 0, 0)
         self._nl += 1
         self._keep.append((geom, layer, M, P, depth))
 
@@ -711,7 +712,7 @@ class EditBatch:
         c = _f32(center, 3)
         i = self._slot()
         self._a[i] = (geom.addr, 0, EDIT_BRUSH, 0, c, np.float32(radius), 0, 0, 0, 0, 0, 0.0, 0,
-                      ctypes.addressof(layer.c), int(mode), 0, float(value))
+                      ctypes.addressof(layer.c), int(mode), 0, float(value), 0, 0, 0, 0)
         self._keep.append((geom, layer))
 
     def numeric_lasso(self, geom: GeometryImage, layer: "NumericLayer", view_proj, poly, depth: torch.Tensor,
@@ -721,9 +722,33 @@ class EditBatch:
         dh, dw = depth.shape
         i = self._slot()
         self._a[i] = (geom.addr, 0, EDIT_LASSO, 0, (0.0, 0.0, 0.0), 0.0, _addr(M), _addr(P), P.size // 2, dw, dh,
-                      np.float32(bias), depth.data_ptr(), ctypes.addressof(layer.c), int(mode), 0, float(value))
+                      np.float32(bias), depth.data_ptr(), ctypes.addressof(layer.c), int(mode), 0, float(value),
+                      0, 0, 0, 0)
         self._nl += 1
         self._keep.append((geom, layer, M, P, depth))
+
+    def _tool(self, geom, layer_addr, numeric_addr, label, mode, value, view_proj, tool, shape, depth, bias, keep):
+        M = _f32(view_proj, 16)
+        tp = np.ascontiguousarray(np.asarray(tool, dtype=np.float64))
+        if tp.size != 6 or shape.dtype != torch.uint8 or shape.dim() != 2 or not shape.is_contiguous():
+            raise ValueError("tool needs 6 numbers and a contiguous uint8 [sh, sw] shape")
+        sh, sw = shape.shape
+        dh, dw = depth.shape
+        i = self._slot()
+        self._a[i] = (geom.addr, layer_addr, EDIT_TOOL, int(label), (0.0, 0.0, 0.0), 0.0, _addr(M), 0, 0, dw, dh,
+                      np.float32(bias), depth.data_ptr(), numeric_addr, int(mode), 0, float(value), _addr(tp),
+                      shape.data_ptr(), sw, sh)
+        self._nl += 1
+        self._keep.append((geom, keep, M, tp, shape, depth))
+
+    def tool(self, geom: GeometryImage, layer: Layer, view_proj, tool, shape: torch.Tensor, depth: torch.Tensor,
+             bias: float, label: int):
+        """The paper's screen-space tool (as edit_tool) in the batch."""
+        self._tool(geom, layer.addr, 0, label, 0, 0.0, view_proj, tool, shape, depth, bias, layer)
+
+    def numeric_tool(self, geom: GeometryImage, layer: "NumericLayer", view_proj, tool, shape: torch.Tensor,
+                     depth: torch.Tensor, bias: float, mode: int, value: float = 0.0):
+        self._tool(geom, 0, ctypes.addressof(layer.c), 0, mode, value, view_proj, tool, shape, depth, bias, layer)
 
     def __len__(self):
         return self._n

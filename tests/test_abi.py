@@ -189,6 +189,16 @@ def test_edit_records_match_the_c_struct():
     r2.center[0], r2.center[1], r2.center[2], r2.radius = 1.0, 2.0, 3.0, 0.5
     r2.numeric, r2.mode, r2.value = ctypes.addressof(nl), uvl.ERASE, -2.25
     assert raw == bytes(r2)
+    # a tool edit: its parameters, shape and sizes in the trailing fields
+    shape = torch.ones((5, 7), dtype=torch.uint8)
+    b.tool(g, lay, M, (640, 480, 320, 240, 100, 90), shape, d, 1e-4, 11)
+    raw = ctypes.string_at(b.array() + 3 * ctypes.sizeof(uvl.CEdit), ctypes.sizeof(uvl.CEdit))
+    keep = b._keep[3]
+    r3 = uvl.CEdit()
+    r3.geom, r3.layer, r3.kind, r3.label = 0x1000, 0x2000, uvl.EDIT_TOOL, 11
+    r3.view_proj, r3.dw, r3.dh, r3.bias, r3.depth = keep[2].ctypes.data, 64, 48, np.float32(1e-4), d.data_ptr()
+    r3.tool, r3.shape, r3.sw, r3.sh = keep[3].ctypes.data, shape.data_ptr(), 7, 5
+    assert raw == bytes(r3) and list(keep[3]) == [640, 480, 320, 240, 100, 90]
 
 
 def test_padding_validation(uvl):

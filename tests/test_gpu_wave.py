@@ -417,3 +417,90 @@ def test_wave_numeric_layers_equal_plain(gpu):
             for k, l in enumerate(m.layers):
                 assert np.array_equal(l.numpy(), lab_ref[k]), (seed, chunks, k)
             wave.close()
+
+
+def test_wave_tools_equal_plain(gpu):
+    """The paper's screen-space tool in waves, beside brushes and lassos, on
+    a label and a numeric layer: identical to uvl_edit_tool /
+    uvl_numeric_tool launched one by one in order, with tile culling (the
+    tool's square as a rectangle) and without, at two tile sizes."""
+    import torch
+    from paper_2501_14807_amd.model import Model
+    wl = synth.scan_workload(n_brush=20, n_lasso=20, n_ops=0, W=1024, n_charts=4, nx=64, ny=32, depth=512)
+    m = Model.from_workload(wl).build()
+    W, H = wl.W, wl.H
+    n = 64
+    yy, xx = np.mgrid[0:n, 0:n]
+    disk = torch.from_numpy(((((xx + 0.5) / n - 0.5) ** 2 + ((yy + 0.5) / n - 0.5) ** 2) <= 0.25)
+                            .astype(np.uint8)).cuda().contiguous()
+    rng = np.random.default_rng(41)
+    maps = {}
+
+    def depth(cam):
+        if cam not in maps:
+            d = torch.empty((m.depth_h, m.depth_w), dtype=torch.float32, device="cuda")
+            gpu.render_depth(m.mesh, wl.cameras[cam], d, m.depth_ws)
+            maps[cam] = d
+        return maps[cam]
+
+    ops = []          # (kind, args) in order
+    for i, e in enumerate(wl.edits):
+        label = 1 + i % 200
+        if e.kind == "brush":
+            ops.append(("brush", e, label))
+        else:
+            ops.append(("lasso", e, label))
+            Ww, Wh = 1024.0, 1024.0
+            t = (Ww, Wh, float(rng.uniform(-100, 1100)), float(rng.uniform(-100, 1100)),
+                 float(rng.uniform(40, 600)), float(rng.uniform(40, 600)))
+            ops.append(("tool", (e.camera, t), label + 1))
+    ops.append(("tool", (wl.edits[1].camera, (512.0, 512.0, 256.0, 256.0, 512.0, 512.0)), 250))
+    lab = m.layers[0]
+    num = gpu.NumericLayer(W, H, gpu.F32)
+
+    def plain():
+        gpu.create_layer(lab)
+        gpu.numeric_create(num)
+        for kind, a, label in ops:
+            if kind == "brush":
+                gpu.edit_brush(m.geom, lab, a.centre, a.radius, label)
+                gpu.numeric_brush(m.geom, num, a.centre, a.radius, gpu.SET, label * 0.5)
+            elif kind == "lasso":
+                M = wl.cameras[a.camera]
+                gpu.edit_lasso(m.geom, lab, M, a.poly, depth(a.camera), m.bias, label)
+                gpu.numeric_lasso(m.geom, num, M, a.poly, depth(a.camera), m.bias, gpu.ERASE)
+            else:
+                cam, t = a
+                gpu.edit_tool(m.geom, lab, wl.cameras[cam], t, disk, depth(cam), m.bias, label)
+                gpu.numeric_tool(m.geom, num, wl.cameras[cam], t, disk, depth(cam), m.bias, gpu.SET, -label)
+        torch.cuda.synchronize()
+        return lab.numpy().copy(), num.numpy().copy(), num.mask_words().copy()
+
+    ref = plain()
+    assert ref[0].any() and ref[2].any()
+    for words in (1 << 20, 0):
+        wave = gpu.Wave(max_edits=2 * len(ops), max_lassos=2 * len(ops), max_cull_words=words)
+        for chunks in (1, 4):
+            gpu.create_layer(lab)
+            gpu.numeric_create(num)
+            batch = gpu.EditBatch()
+            for kind, a, label in ops:
+                if kind == "brush":
+                    batch.brush(m.geom, lab, a.centre, a.radius, label)
+                    batch.numeric_brush(m.geom, num, a.centre, a.radius, gpu.SET, label * 0.5)
+                elif kind == "lasso":
+                    M = wl.cameras[a.camera]
+                    batch.lasso(m.geom, lab, M, a.poly, depth(a.camera), m.bias, label)
+                    batch.numeric_lasso(m.geom, num, M, a.poly, depth(a.camera), m.bias, gpu.ERASE)
+                else:
+                    cam, t = a
+                    batch.tool(m.geom, lab, wl.cameras[cam], t, disk, depth(cam), m.bias, label)
+                    batch.numeric_tool(m.geom, num, wl.cameras[cam], t, disk, depth(cam), m.bias, gpu.SET, -label)
+            wave.submit(batch, tile_chunks=chunks)
+            torch.cuda.synchronize()
+            assert np.array_equal(lab.numpy(), ref[0]), (words, chunks)
+            assert np.array_equal(num.numpy().view(np.uint32), ref[1].view(np.uint32)), (words, chunks)
+            assert np.array_equal(num.mask_words(), ref[2]), (words, chunks)
+            if words:
+                assert wave.visited_tiles() < 2 * (W // 32) * (H // 32)   # culling skipped tiles
+        wave.close()
