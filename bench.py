@@ -316,8 +316,9 @@ def bench_tool(m, wl, uvl, torch, n_edits=100):
 
 def bench_padding(m, wl, uvl, torch, n_edits=200):
     """Texture padding (§4.3.2) on the workload's model: the outline list
-    (radius 1, built once per model) and the padding pass after each of the
-    first n_edits edits (the paper's per-edit cost is editing + padding)."""
+    (radius 1, built once per model), the padding pass after each of the
+    first n_edits edits (the paper's per-edit cost is editing + padding), and
+    those edits as one wave without and with its padding."""
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -338,9 +339,23 @@ def bench_padding(m, wl, uvl, torch, n_edits=200):
         e1.record()
         torch.cuda.synchronize()
         per[e.kind].append(e0.elapsed_time(e1) * 1e3)
+    # the same edits as one wave, without and with its padding
+    wave = uvl.Wave(n_edits, n_edits)
+    batch = uvl.EditBatch(n_edits)
+    m.add_to_batch(batch, wl.edits[:n_edits], wl.cameras)
+    wave_ms = {}
+    for name, outlines in (("plain", None), ("padded", [(m.geom, o)])):
+        wave.submit(batch, outlines=outlines)
+        e0.record()
+        wave.submit(batch, outlines=outlines)
+        e1.record()
+        torch.cuda.synchronize()
+        wave_ms[name] = e0.elapsed_time(e1)
+    wave.close()
     return {"outline_texels": o.n, "outline_build_ms": build_ms, "edits": n_edits,
             "pad_brush_us": float(np.mean(per["brush"])) if per["brush"] else None,
-            "pad_lasso_us": float(np.mean(per["lasso"])) if per["lasso"] else None}
+            "pad_lasso_us": float(np.mean(per["lasso"])) if per["lasso"] else None,
+            "wave_ms": wave_ms["plain"], "padded_wave_ms": wave_ms["padded"]}
 
 
 def bench_numeric(m, wl, uvl, torch, n_edits=100, reps=10):
@@ -605,7 +620,8 @@ def main():
         log(f"screen-space tool: {tool['tool_us']:.1f} us per edit ({tool['gbps']:.0f} GB/s)")
         padding = bench_padding(m, wl, uvl, torch)
         log(f"padding: {padding['outline_texels']} outline texels, brush {padding['pad_brush_us']:.1f} us, "
-            f"lasso {padding['pad_lasso_us']:.1f} us per edit")
+            f"lasso {padding['pad_lasso_us']:.1f} us per edit; a {padding['edits']}-edit wave "
+            f"{padding['wave_ms']:.2f} ms, padded {padding['padded_wave_ms']:.2f} ms")
         numeric = bench_numeric(m, wl, uvl, torch)
         log(f"numeric f32: lasso SET {numeric['lasso_set_us']:.1f} us (label {numeric['label_lasso_us']:.1f} us), "
             + ", ".join(f"stats[{k}] {v['us']:.1f} us {v['gbps']:.0f} GB/s" for k, v in numeric["stats"].items())

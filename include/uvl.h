@@ -486,6 +486,30 @@ int32_t uvl_wave_create(int32_t max_edits, int32_t max_lassos, int64_t max_cull_
  * handle's capacity. */
 int32_t uvl_wave_submit(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t tile_chunks, void *stream);
 
+/* Texture padding in a wave (§4.3.2).  One entry per geometry image to pad
+ * around: its outline list from uvl_build_outline (n texel indices) and the
+ * padding radius k (0..8). */
+typedef struct {
+    const uvl_geom *geom;
+    const int32_t *outline;
+    int64_t n;
+    int32_t k;
+    int32_t reserved;       /* 0 */
+} uvl_wave_outline;
+
+/* uvl_wave_submit, then padding: every layer whose edits read a geometry
+ * image listed in outlines[0..noutlines) is padded after its edits, with the
+ * result of padding after each edit in order (uvl_pad_brush / uvl_pad_lasso
+ * and their numeric forms; a tool edit pads by the same rule with the tool's
+ * predicate).  Padding writes uncovered texels only and edits covered ones,
+ * so the padding of all of a layer's edits can follow them: an outline
+ * texel takes the label (or the numeric decisions) of the last edit that
+ * selects a covered texel of its (2k+1)^2 window.  Edits a tile test has
+ * culled around the window are skipped.
+ * Errors: as uvl_wave_submit, plus UVL_E_INVAL for a bad outline entry. */
+int32_t uvl_wave_submit_padded(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t tile_chunks,
+                               const uvl_wave_outline *outlines, int32_t noutlines, void *stream);
+
 /* Autotune the tile size per atlas size class (power of two of the texel
  * count) present in edits: each of 1, 2, 4, 8 chunks is timed on the class's
  * edits (applying a wave again leaves the layers unchanged, so the layers

@@ -69,6 +69,9 @@ struct WaveStream {
     const float *box;   // per-tile position bounds, or null (no culling)
     void *layer;        // label layer, or a numeric layer's data
     uint32_t *vmask;    // a numeric layer's mask words (null for label layers)
+    const int32_t *outline;  // padding: outline texel indices (null: no padding)
+    int64_t out0;       // first padding index of this stream (running offset)
+    int64_t nout;       // outline entries
     int64_t mask0;      // first cull-mask word of this stream (running offset)
     int64_t cwave0;     // first cull wave of this stream (one per block of 8 x 8 tiles)
     int64_t list0;      // first live-list entry of this stream
@@ -79,6 +82,8 @@ struct WaveStream {
     int32_t chunks;     // tiles per item
     int32_t cull;       // 1: masks at mask0 (tiles x groups words), 0: no culling
     int32_t numeric;    // 1: a numeric layer (edits SET / ERASE with value bits)
+    int32_t padk;       // padding radius
+    int32_t pad3;
 };
 
 struct WaveEdit {
@@ -97,6 +102,7 @@ struct WaveHeader {
     int32_t pad;
     int64_t total_cull_waves;
     int64_t total_items;     // written by k_wave_plan
+    int64_t total_out;       // outline entries to pad, over all streams
     uint64_t off_streams, off_live_n, off_item0, off_edits, off_lassos, off_tools;
     unsigned int counter;
     unsigned int pad2[3];
@@ -487,6 +493,97 @@ __global__ __launch_bounds__(kBlock) void k_wave(char *__restrict__ ws, const ui
     }
 }
 
+// Padding after a wave (§4.3.2): a lane per outline entry, over all streams
+// with an outline.  The outline texel takes the decision of the last edit
+// that selects a covered texel of its (2k+1)^2 window: its label, or in a
+// numeric layer its mask bit (SET / ERASE) and, from the last such SET, its
+// data.  Candidate edits are those live in the tiles the window touches
+// (every edit without culling); mask words of tiles the cull pass found dead
+// may be stale, which only adds candidates, each evaluated exactly.
+constexpr int kPadGrid = 1024;
+constexpr int kMaxPadRadius = 8;
+
+__global__ __launch_bounds__(kBlock) void k_wave_pad(char *__restrict__ ws, const uint64_t *__restrict__ masks_in) {
+    const UVL_CONST WaveHeader *chdr = (const UVL_CONST WaveHeader *)ws;
+    const UVL_CONST WaveStream *streams = (const UVL_CONST WaveStream *)(ws + chdr->off_streams);
+    const UVL_CONST WaveEdit *edits = (const UVL_CONST WaveEdit *)(ws + chdr->off_edits);
+    const UVL_CONST LassoParams *lassos = (const UVL_CONST LassoParams *)(ws + chdr->off_lassos);
+    const UVL_CONST ToolParams *tools = (const UVL_CONST ToolParams *)(ws + chdr->off_tools);
+    const int32_t nstreams = chdr->nstreams;
+    const int64_t total = chdr->total_out;
+    for (int64_t gi = (int64_t)blockIdx.x * kBlock + threadIdx.x; gi < total; gi += (int64_t)gridDim.x * kBlock) {
+        const int si = last_le(nstreams, gi, [&](int k) { return streams[k].out0; });
+        const UVL_CONST WaveStream &S = streams[si];
+        const int32_t t = S.outline[gi - S.out0];
+        const int W = S.W, H = S.H, k = S.padk;
+        if (t < 0 || (int64_t)t >= (int64_t)W * H) continue;   // not a texel index: ignored
+        const int i = t % W, j = t / W;
+        const int u0 = i - k < 0 ? 0 : i - k, u1 = i + k > W - 1 ? W - 1 : i + k;
+        const int v0 = j - k < 0 ? 0 : j - k, v1 = j + k > H - 1 ? H - 1 : j + k;
+        const int groups = (S.ne + 63) >> 6;
+        const int tx0 = u0 / UVL_TILE_SIDE, tx1 = u1 / UVL_TILE_SIDE;
+        const int ty0 = v0 / UVL_TILE_SIDE, ty1 = v1 / UVL_TILE_SIDE;
+        bool wr = false, wd = false, mset = false;
+        uint32_t val = 0;
+        for (int g = groups - 1; g >= 0 && !wd; --g) {
+            uint64_t lm = S.cull ? 0ull : ~0ull;
+            if (S.cull)
+                for (int ty = ty0; ty <= ty1; ++ty)
+                    for (int tx = tx0; tx <= tx1; ++tx)
+                        lm |= masks_in[S.mask0 + ((int64_t)ty * S.tiles_x + tx) * groups + g];
+            const int lim = S.ne - 64 * g < 64 ? S.ne - 64 * g : 64;
+            if (lim < 64) lm &= (1ull << lim) - 1;
+            while (lm && !wd) {
+                const int b = 63 - __builtin_clzll(lm);
+                lm &= ~(1ull << b);
+                const UVL_CONST WaveEdit &E = edits[S.e0 + 64 * g + b];
+                bool hit = false;
+                for (int v = v0; v <= v1 && !hit; ++v)
+                    for (int u = u0; u <= u1; ++u) {
+                        const int64_t q = (int64_t)v * W + u;
+                        const float x = S.px[q];
+                        if (x != x) continue;   // uncovered (NaN position): never edited
+                        const float y = S.py[q], z = S.pz[q];
+                        if (E.kind == UVL_EDIT_BRUSH) hit = brush_texel(BrushParams{E.cx, E.cy, E.cz, E.r2}, x, y, z);
+                        else if (E.kind == UVL_EDIT_LASSO) hit = lasso_texel(lassos[E.lasso], E.depth, x, y, z);
+                        else hit = tool_texel(tools[E.lasso], E.shape, E.depth, x, y, z);
+                        if (hit) break;
+                    }
+                if (!hit) continue;
+                if (!S.numeric) {
+                    val = E.label;
+                    wr = wd = true;
+                } else {
+                    const bool set = E.erase == 0;
+                    if (!wr) {
+                        wr = true;
+                        mset = set;
+                    }
+                    if (set) {
+                        wd = true;
+                        val = E.label;
+                    }
+                }
+            }
+        }
+        if (!S.numeric) {
+            if (!wr) continue;
+            if (S.dtype == UVL_U8) static_cast<uint8_t *>(S.layer)[t] = (uint8_t)val;
+            else static_cast<uint16_t *>(S.layer)[t] = (uint16_t)val;
+            continue;
+        }
+        if (wd) {
+            if (S.dtype == UVL_U8) static_cast<uint8_t *>(S.layer)[t] = (uint8_t)val;
+            else if (S.dtype == UVL_U16 || S.dtype == UVL_F16) static_cast<uint16_t *>(S.layer)[t] = (uint16_t)val;
+            else static_cast<uint32_t *>(S.layer)[t] = val;
+        }
+        if (wr) {
+            if (mset) atomicOr(S.vmask + (t >> 5), 1u << (t & 31));
+            else atomicAnd(S.vmask + (t >> 5), ~(1u << (t & 31)));
+        }
+    }
+}
+
 }  // namespace
 }  // namespace uvl
 
@@ -592,7 +689,8 @@ int log2_class(int64_t n) {
 
 // Validate and pack a wave into the staging buffer.  chunks_override > 0
 // forces that tile size for every stream.
-int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_override, size_t &bytes) {
+int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_override, const uvl_wave_outline *outlines,
+             int32_t noutlines, size_t &bytes) {
     // streams: one per distinct layer, in order of first appearance
     std::vector<int32_t> stream_of(n);
     std::vector<const void *> keys;
@@ -654,7 +752,7 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
     WaveEdit *E = reinterpret_cast<WaveEdit *>(st + hdr->off_edits);
     LassoParams *P = reinterpret_cast<LassoParams *>(st + hdr->off_lassos);
     ToolParams *TP = reinterpret_cast<ToolParams *>(st + hdr->off_tools);
-    int64_t words = 0, cwaves = 0;
+    int64_t words = 0, cwaves = 0, nout_total = 0;
     int32_t ei = 0, li = 0;
     for (size_t k = 0; k < keys.size(); ++k) {
         const uvl_edit &f = edits[members[k][0]];
@@ -687,6 +785,21 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
             cwaves += ceil_div(s.tiles_x, 8) * ceil_div(s.ntiles / s.tiles_x, 8);   // blocks of 8 x 8 tiles
         }
         live_n[k] = 0;
+        // padding: the outline of this stream's geometry image, if listed
+        s.outline = nullptr;
+        s.nout = 0;
+        s.padk = 0;
+        s.pad3 = 0;
+        s.out0 = nout_total;
+        for (int32_t q = 0; q < noutlines; ++q) {
+            const uvl_wave_outline &o = outlines[q];
+            if (!o.geom || o.geom->pos_x != f.geom->pos_x) continue;
+            s.outline = o.outline;
+            s.nout = o.n;
+            s.padk = o.k;
+            nout_total += o.n;
+            break;
+        }
         s.e0 = ei;
         s.ne = (int32_t)members[k].size();
         for (int32_t i : members[k]) {
@@ -727,6 +840,7 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
     hdr->pad = 0;
     hdr->total_cull_waves = cwaves;
     hdr->total_items = 0;
+    hdr->total_out = nout_total;
     hdr->counter = 0;
     bytes = end;
     return UVL_OK;
@@ -734,8 +848,18 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
 
 }  // namespace
 
-extern "C" int32_t uvl_wave_submit(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t tile_chunks, void *stream) {
+namespace {
+
+int32_t submit(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t tile_chunks, const uvl_wave_outline *outlines,
+               int32_t noutlines, void *stream) {
     if (!w || (!edits && n > 0) || n < 0 || tile_chunks < 0 || tile_chunks > kMaxChunks) return UVL_E_INVAL;
+    if (noutlines < 0 || (noutlines > 0 && !outlines)) return UVL_E_INVAL;
+    for (int32_t q = 0; q < noutlines; ++q) {
+        const uvl_wave_outline &o = outlines[q];
+        if (!o.geom || !geom_pos_ok(o.geom) || o.n < 0 || (o.n > 0 && !o.outline) || o.k < 0 || o.k > kMaxPadRadius ||
+            o.n > (int64_t)o.geom->width * o.geom->height)
+            return UVL_E_INVAL;
+    }
     if (n > w->max_edits) return UVL_E_NOMEM;
     if (n == 0) return UVL_OK;
     std::lock_guard<std::mutex> lock(w->mu);
@@ -746,14 +870,32 @@ extern "C" int32_t uvl_wave_submit(uvl_wave *w, const uvl_edit *edits, int32_t n
     w->pending[k] = false;
     w->staging = w->ring[k];
     size_t bytes = 0;
-    if (int32_t st = pack(w, edits, n, tile_chunks, bytes)) return st;
+    if (int32_t st = pack(w, edits, n, tile_chunks, outlines, noutlines, bytes)) return st;
+    const int64_t total_out = reinterpret_cast<const WaveHeader *>(w->staging)->total_out;
     hipStream_t s = as_stream(stream);
     if (hipMemcpyAsync(w->ws, w->staging, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return UVL_E_DEVICE;
     if (hipEventRecord(w->copied[k], s) != hipSuccess) return UVL_E_DEVICE;
     w->pending[k] = true;
     w->next = (k + 1) % kStaging;
     if (hipGraphLaunch(w->exec, s) != hipSuccess) return UVL_E_DEVICE;
+    if (total_out > 0) {
+        const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total_out, kBlock), kPadGrid);
+        hipLaunchKernelGGL(k_wave_pad, dim3(grid), dim3(kBlock), 0, s, w->ws,
+                           reinterpret_cast<const uint64_t *>(w->ws + w->lay.masks));
+        if (hipGetLastError() != hipSuccess) return UVL_E_DEVICE;
+    }
     return UVL_OK;
+}
+
+}  // namespace
+
+extern "C" int32_t uvl_wave_submit(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t tile_chunks, void *stream) {
+    return submit(w, edits, n, tile_chunks, nullptr, 0, stream);
+}
+
+extern "C" int32_t uvl_wave_submit_padded(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t tile_chunks,
+                                          const uvl_wave_outline *outlines, int32_t noutlines, void *stream) {
+    return submit(w, edits, n, tile_chunks, outlines, noutlines, stream);
 }
 
 extern "C" int32_t uvl_wave_tune(uvl_wave *w, const uvl_edit *edits, int32_t n, void *stream) {

@@ -87,6 +87,7 @@ SIGNATURES = {
     "uvl_wave_workspace_bytes": ([_I32, _I32, _I64], _SZ),
     "uvl_wave_create": ([_I32, _I32, _I64, _P, _SZ, _P], _I32),
     "uvl_wave_submit": ([_P, _P, _I32, _I32, _P], _I32),
+    "uvl_wave_submit_padded": ([_P, _P, _I32, _I32, _P, _I32, _P], _I32),
     "uvl_wave_tune": ([_P, _P, _I32, _P], _I32),
     "uvl_wave_tuned_chunks": ([_P, _I64], _I32),
     "uvl_wave_visited_tiles": ([_P, _P, _P], _I32),
@@ -113,6 +114,11 @@ SIGNATURES = {
 }
 
 EDIT_BRUSH, EDIT_LASSO, EDIT_TOOL = 0, 1, 2
+
+
+class CWaveOutline(ctypes.Structure):
+    _fields_ = [("geom", ctypes.c_void_p), ("outline", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("k", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class CEdit(ctypes.Structure):
@@ -776,10 +782,18 @@ class Wave:
                                  ctypes.byref(self.h)), "uvl_wave_create")
         self.max_edits, self.max_lassos = int(max_edits), int(max_lassos)
 
-    def submit(self, batch: EditBatch, tile_chunks: int = 0, stream=None):
+    def submit(self, batch: EditBatch, tile_chunks: int = 0, stream=None, outlines=None):
+        """Apply the batch; outlines = [(GeometryImage, Outline), ...] also pads
+        the layers of those geometry images (uvl_wave_submit_padded)."""
         arr = batch.array()
-        _check(_lib().uvl_wave_submit(self.h, arr, len(batch), int(tile_chunks), _stream(stream)),
-               "uvl_wave_submit")
+        if not outlines:
+            _check(_lib().uvl_wave_submit(self.h, arr, len(batch), int(tile_chunks), _stream(stream)),
+                   "uvl_wave_submit")
+            return
+        ol = (CWaveOutline * len(outlines))(*[CWaveOutline(ctypes.addressof(g.c), o.idx.data_ptr(), o.n, o.k, 0)
+                                               for g, o in outlines])
+        _check(_lib().uvl_wave_submit_padded(self.h, arr, len(batch), int(tile_chunks), ol, len(outlines),
+                                             _stream(stream)), "uvl_wave_submit_padded")
 
     def tune(self, batch: EditBatch, stream=None):
         arr = batch.array()

@@ -141,3 +141,120 @@ def test_numeric_padding_matches_oracle(gpu, orc, k, dt):
     ut = np.uint16 if dt == N.F16 else np.uint32
     assert np.array_equal(L.numpy().view(ut), R.data.view(ut))
     assert np.array_equal(L.mask_words(), R.words)
+
+
+def test_padded_waves_equal_edit_then_pad(gpu, orc):
+    """Waves with padding: label and numeric layers end as after each edit
+    followed by its padding, one launch each, in order (k = 1 and 2, tile
+    culling on and off); tools pad by the same rule (checked against the
+    oracle's padding of the tool's selection)."""
+    import torch
+    from oracle import numeric as N
+    from paper_2501_14807_amd.model import Model
+    wl = _scan_small()
+    W = H = wl.W
+    m = Model.from_workload(wl).build()
+    maps = {}
+
+    def depth(cam):
+        if cam not in maps:
+            d = torch.empty((m.depth_h, m.depth_w), dtype=torch.float32, device="cuda")
+            gpu.render_depth(m.mesh, wl.cameras[cam], d, m.depth_ws)
+            maps[cam] = d
+        return maps[cam]
+
+    edits = wl.edits[:40]
+    for k in (1, 2):
+        o = gpu.Outline(m.geom, k)
+        lab = m.layers[0]
+        num = gpu.NumericLayer(W, H, gpu.I32)
+        # reference: edit, then its padding, one by one
+        gpu.create_layer(lab)
+        gpu.numeric_create(num)
+        for i, e in enumerate(edits):
+            mode = gpu.ERASE if i % 5 == 4 else gpu.SET
+            label = 1 + i % 200
+            if e.kind == "brush":
+                gpu.edit_brush(m.geom, lab, e.centre, e.radius, label)
+                gpu.pad_brush(m.geom, lab, o, e.centre, e.radius, label)
+                gpu.numeric_brush(m.geom, num, e.centre, e.radius, mode, -i)
+                gpu.numeric_pad_brush(m.geom, num, o, e.centre, e.radius, mode, -i)
+            else:
+                M = wl.cameras[e.camera]
+                gpu.edit_lasso(m.geom, lab, M, e.poly, depth(e.camera), m.bias, label)
+                gpu.pad_lasso(m.geom, lab, o, M, e.poly, depth(e.camera), m.bias, label)
+                gpu.numeric_lasso(m.geom, num, M, e.poly, depth(e.camera), m.bias, mode, -i)
+                gpu.numeric_pad_lasso(m.geom, num, o, M, e.poly, depth(e.camera), m.bias, mode, -i)
+        torch.cuda.synchronize()
+        ref = (lab.numpy().copy(), num.numpy().copy(), num.mask_words().copy())
+        assert ref[0].any()
+        for words in (1 << 20, 0):
+            wave = gpu.Wave(max_edits=2 * len(edits), max_lassos=2 * len(edits), max_cull_words=words)
+            gpu.create_layer(lab)
+            gpu.numeric_create(num)
+            batch = gpu.EditBatch()
+            for i, e in enumerate(edits):
+                mode = gpu.ERASE if i % 5 == 4 else gpu.SET
+                label = 1 + i % 200
+                if e.kind == "brush":
+                    batch.brush(m.geom, lab, e.centre, e.radius, label)
+                    batch.numeric_brush(m.geom, num, e.centre, e.radius, mode, -i)
+                else:
+                    M = wl.cameras[e.camera]
+                    batch.lasso(m.geom, lab, M, e.poly, depth(e.camera), m.bias, label)
+                    batch.numeric_lasso(m.geom, num, M, e.poly, depth(e.camera), m.bias, mode, -i)
+            wave.submit(batch, outlines=[(m.geom, o)])
+            torch.cuda.synchronize()
+            assert np.array_equal(lab.numpy(), ref[0]), (k, words)
+            assert np.array_equal(num.numpy(), ref[1]), (k, words)
+            assert np.array_equal(num.mask_words(), ref[2]), (k, words)
+            wave.close()
+    # tools: one padded wave of three tools against the oracle
+    og = orc.geometry_image(wl.mesh, W, H)
+    ol = orc.outline(og.tri_id, W, H, 1)
+    o = gpu.Outline(m.geom, 1)
+    n = 64
+    yy, xx = np.mgrid[0:n, 0:n]
+    disk_np = ((((xx + 0.5) / n - 0.5) ** 2 + ((yy + 0.5) / n - 0.5) ** 2) <= 0.25).astype(np.uint8)
+    disk = torch.from_numpy(disk_np).cuda().contiguous()
+    cam = [e for e in wl.edits if e.kind == "lasso"][0].camera
+    M = wl.cameras[cam]
+    od = orc.depth_map(wl.mesh, M, wl.depth_w, wl.depth_h)
+    tools = [(1024.0, 1024.0, 300.0, 500.0, 400.0, 300.0), (1024.0, 1024.0, 700.0, 450.0, 250.0, 250.0),
+             (1024.0, 1024.0, 512.0, 512.0, 1024.0, 1024.0)]
+    lab = m.layers[0]
+    gpu.create_layer(lab)
+    ref = np.zeros(W * H, np.uint8)
+    batch = gpu.EditBatch()
+    for q, t in enumerate(tools):
+        batch.tool(m.geom, lab, M, t, disk, depth(cam), m.bias, 10 + q)
+        sel = np.zeros(W * H, np.uint8)
+        orc.tool(og.pos32, sel, M, t, disk_np, od, m.bias, 1)
+        orc.tool(og.pos32, ref, M, t, disk_np, od, m.bias, 10 + q)
+        orc.pad(ol, sel, W, H, 1, ref, 10 + q)
+    wave = gpu.Wave(max_edits=8, max_lassos=8)
+    wave.submit(batch, outlines=[(m.geom, o)])
+    torch.cuda.synchronize()
+    assert (ref[ol == 1] != 0).any()
+    assert np.array_equal(lab.numpy(), ref)
+    wave.close()
+
+
+def test_padded_wave_rejects_bad_outlines(gpu):
+    import ctypes
+    from paper_2501_14807_amd.model import Model
+    wl = _scan_small()
+    m = Model.from_workload(wl).build()
+    o = gpu.Outline(m.geom, 1)
+    wave = gpu.Wave(max_edits=4, max_lassos=4)
+    batch = gpu.EditBatch()
+    e = [x for x in wl.edits if x.kind == "brush"][0]
+    batch.brush(m.geom, m.layers[0], e.centre, e.radius, 3)
+    L = gpu.lib()
+    for idx, n, k in ((o.idx.data_ptr(), o.n, 9), (o.idx.data_ptr(), -1, 1), (None, 5, 1),
+                      (o.idx.data_ptr(), m.geom.n + 1, 1)):
+        ol = gpu.CWaveOutline(ctypes.addressof(m.geom.c), idx, n, k, 0)
+        rc = L.uvl_wave_submit_padded(wave.h, batch.array(), len(batch), 0, ctypes.byref(ol), 1, None)
+        assert rc == -1, (n, k)
+    assert L.uvl_wave_submit_padded(wave.h, batch.array(), len(batch), 0, None, 1, None) == -1
+    wave.close()
