@@ -149,11 +149,15 @@ class GpuExecutor(Executor):
     """The HIP library behind the server: models resident as Model objects,
     edits through waves (batched) or single launches (plain)."""
 
-    def __init__(self, models, cameras, max_wave_edits=4096, lut_slots=32):
+    def __init__(self, models, cameras, max_wave_edits=4096, lut_slots=32, pad_k=None):
         import torch
         from . import uvl
         self.torch, self.uvl = torch, uvl
         self.models = models                  # list of Model
+        # texture padding (§4.3.2) after every edit when pad_k is set: one
+        # outline per model, padded inside the waves (batched) or after each
+        # edit launch (plain)
+        self.outlines = None if pad_k is None else [uvl.Outline(m.geom, int(pad_k)) for m in models]
         self.models_resident = set(range(len(models)))
         self.cameras = cameras                # per model: list of view-proj matrices
         self.depth: Dict[tuple, object] = {}  # (model, camera) -> resident depth map
@@ -199,18 +203,26 @@ class GpuExecutor(Executor):
             else:
                 batch.lasso(m.geom, layer, self.cameras[r.model][e.camera], e.poly, self._depth(r.model, e.camera),
                             m.bias, e.label)
-        self.wave.submit(batch)
+        outlines = None
+        if self.outlines is not None:
+            outlines = [(self.models[mi].geom, self.outlines[mi]) for mi in sorted({r.model for r in reqs})]
+        self.wave.submit(batch, outlines=outlines)
         self._keep.append(batch)
 
     def launch_single(self, r):
         m = self.models[r.model]
+        o = None if self.outlines is None else self.outlines[r.model]
         if r.kind == "brush":
             e = r.edit
             self.uvl.edit_brush(m.geom, m.layers[e.layer], e.centre, e.radius, e.label)
+            if o is not None:
+                self.uvl.pad_brush(m.geom, m.layers[e.layer], o, e.centre, e.radius, e.label)
         elif r.kind == "lasso":
             e = r.edit
-            self.uvl.edit_lasso(m.geom, m.layers[e.layer], self.cameras[r.model][e.camera], e.poly,
-                                self._depth(r.model, e.camera), m.bias, e.label)
+            M, d = self.cameras[r.model][e.camera], self._depth(r.model, e.camera)
+            self.uvl.edit_lasso(m.geom, m.layers[e.layer], M, e.poly, d, m.bias, e.label)
+            if o is not None:
+                self.uvl.pad_lasso(m.geom, m.layers[e.layer], o, M, e.poly, d, m.bias, e.label)
         elif r.kind == "algebra":
             o = r.op
             lut = None

@@ -1,6 +1,7 @@
 """Serving on the GPU: each request's result is the same alone and in the
 mix (continuous batching vs plain one-launch-per-request vs each model's
-requests applied on their own), bit for bit."""
+requests applied on their own), bit for bit, with and without texture
+padding."""
 
 import numpy as np
 import pytest
@@ -44,12 +45,12 @@ def _requests(stream, only=None):
     return out
 
 
-def _run(gpu, models, cams, reqs, mode):
+def _run(gpu, models, cams, reqs, mode, pad_k=None):
     import torch
     from paper_2501_14807_amd.serve import GpuExecutor, Server
     for m in models:
         m.clear_layers()
-    ex = GpuExecutor(models, cams, max_wave_edits=1024)
+    ex = GpuExecutor(models, cams, max_wave_edits=1024, pad_k=pad_k)
     st = Server(ex, len(models), 1 << 40).run(reqs, mode)
     torch.cuda.synchronize()
     layers = [[l.numpy().copy() for l in m.layers] for m in models]
@@ -77,3 +78,23 @@ def test_alone_equals_mix(gpu):
             assert np.array_equal(x, y)
         for k, v in areas.items():
             assert np.array_equal(v, area_b[k])
+
+
+def test_padded_serving_batched_equals_plain(gpu):
+    """With texture padding after every edit: continuous batching (padding
+    inside the waves) gives the layers of plain serving (an edit launch and
+    its padding launch per request), and the areas of unpadded serving
+    (padding writes uncovered texels only)."""
+    models, cams, stream = _setup(gpu)
+    st_b, lay_b, area_b = _run(gpu, models, cams, _requests(stream), "batched", pad_k=1)
+    st_p, lay_p, area_p = _run(gpu, models, cams, _requests(stream), "plain", pad_k=1)
+    _, lay_u, area_u = _run(gpu, models, cams, _requests(stream), "plain")
+    assert st_b.failed == st_p.failed == 0 and st_b.rounds < st_b.n
+    padded_somewhere = False
+    for a, b, u in zip(lay_b, lay_p, lay_u):
+        for x, y, z in zip(a, b, u):
+            assert np.array_equal(x, y)
+            padded_somewhere = padded_somewhere or not np.array_equal(x, z)
+    assert padded_somewhere
+    for k in area_b:
+        assert np.array_equal(area_b[k], area_p[k]) and np.array_equal(area_b[k], area_u[k]), k
