@@ -1,5 +1,6 @@
-// Batched edit waves for libuvl: many models' pending brush and lasso edits
-// applied by one persistent-kernel launch.
+// Batched edit waves for libuvl: many models' pending brush, lasso and
+// screen-space tool edits applied by one persistent-kernel launch, and
+// optionally their texture padding by one more.
 //
 // The paper applies one edit per rendering pass (§4.3.1).  Each edit's
 // selection is a pure function of the texel's stored position, and the last
