@@ -618,14 +618,16 @@ def main():
     else:
         tool = bench_tool(m, wl, uvl, torch)
         log(f"screen-space tool: {tool['tool_us']:.1f} us per edit ({tool['gbps']:.0f} GB/s)")
-        padding = bench_padding(m, wl, uvl, torch)
-        log(f"padding: {padding['outline_texels']} outline texels, brush {padding['pad_brush_us']:.1f} us, "
-            f"lasso {padding['pad_lasso_us']:.1f} us per edit; a {padding['edits']}-edit wave "
-            f"{padding['wave_ms']:.2f} ms, padded {padding['padded_wave_ms']:.2f} ms")
+        # the statistics group by the model's label layers as the step and the
+        # tool left them (the padding section rewrites them with a wave)
         numeric = bench_numeric(m, wl, uvl, torch)
         log(f"numeric f32: lasso SET {numeric['lasso_set_us']:.1f} us (label {numeric['label_lasso_us']:.1f} us), "
             + ", ".join(f"stats[{k}] {v['us']:.1f} us {v['gbps']:.0f} GB/s" for k, v in numeric["stats"].items())
             + f", select {numeric['select_us']:.1f} us")
+        padding = bench_padding(m, wl, uvl, torch)
+        log(f"padding: {padding['outline_texels']} outline texels, brush {padding['pad_brush_us']:.1f} us, "
+            f"lasso {padding['pad_lasso_us']:.1f} us per edit; a {padding['edits']}-edit wave "
+            f"{padding['wave_ms']:.2f} ms, padded {padding['padded_wave_ms']:.2f} ms")
         radius = bench_radius(m, wl, uvl, torch)
         log("brush time by radius: " + ", ".join(f"{x['radius']}: {x['us']:.1f} us" for x in radius["sweep"]))
     copy_gbps = copy_bandwidth(torch)
