@@ -23,6 +23,10 @@ waited `max_wait_s`, so that a busy device gets fewer, larger waves.
 
 Plain mode: every request is launched on arrival, one launch per request.
 
+Texture padding (§4.3.2), when the executor is given a radius: batched
+rounds pad inside their waves, plain mode launches each edit's padding after
+it; both leave the layers of edit-then-pad in arrival order.
+
 Latency of a request = completion time observed on the host (its round's
 event) - arrival time.  The executor is pluggable: GpuExecutor drives the HIP
 library; SimExecutor (host only, simulated durations, injectable failures)
