@@ -261,9 +261,21 @@ __global__ __launch_bounds__(kBlock) void k_geom_attr(const float *__restrict__ 
             wmax = w_tri[t];
         }
     }
+    // One atomic per workgroup at most: atomics on one address from every
+    // wave of a 64M-texel image serialise and would dominate the kernel.
+    __shared__ double s_w[kBlock / 64];
     wmax = wave_max(wmax);
-    if ((threadIdx.x & 63) == 0 && wmax > 0.0)
-        atomicMax(&ctr->max_w_bits, (unsigned long long)__double_as_longlong(wmax));
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = wmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 1; k < kBlock / 64; ++k) wmax = fmax(wmax, s_w[k]);
+        const unsigned long long b = (unsigned long long)__double_as_longlong(wmax);
+        // The counter only grows, so any value read is a lower bound of its
+        // final value and a weight not above it needs no atomic.
+        if (wmax > 0.0 && b > __atomic_load_n(&ctr->max_w_bits, __ATOMIC_RELAXED))
+            atomicMax(&ctr->max_w_bits, b);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_geom_quant(const int32_t *__restrict__ owner,
