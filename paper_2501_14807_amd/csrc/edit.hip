@@ -183,6 +183,11 @@ bool make_lasso_params(const float view_proj[16], const float *poly, int32_t n, 
         for (int k = 0; k < n; ++k) xabs_v = fmaxf(xabs_v, fabsf(poly[2 * k]));
         p.xlo_m = xlo - (1e-4f * (1.0f + fabsf(xlo)) + 1e-5f * (2.0f + xabs_v));
     }
+    // the frustum bound of the exact test, widened alike, joins each side
+    p.xlo_m = fmaxf(p.xlo_m, -1.0001f);
+    p.xhi_m = fminf(p.xhi_m, 1.0001f);
+    p.ylo_m = fmaxf(p.ylo_m, -1.0001f);
+    p.yhi_m = fminf(p.yhi_m, 1.0001f);
     // tile culling planes (see LassoCull)
     {
         const double m = 2e-3;

@@ -74,8 +74,9 @@ struct LassoParams {
     int32_t dw, dh, n;
     float ylo, yhi, xhi;        // polygon bounds: min y, max y, max x
     float xlo;                  // polygon min x
-    float ylo_m, yhi_m, xhi_m;  // the same widened by 1e-4 (1 + |v|), for the reciprocal pre-test
-    float xlo_m;                // xlo widened by 1e-4 (1 + |xlo|) + 1e-5 (2 + max |vertex x|)
+    float ylo_m, yhi_m, xhi_m;  // the same widened by 1e-4 (1 + |v|), for the pre-test, and clamped
+                                // to the frustum [-1, 1] widened by 1e-4
+    float xlo_m;                // xlo widened by 1e-4 (1 + |xlo|) + 1e-5 (2 + max |vertex x|), clamped alike
     float inv_h;                // slabs per unit of y
     uint64_t slab_edges[kSlabs];
     LassoEdge edge[kMaxPoly];
@@ -101,17 +102,19 @@ __device__ __forceinline__ bool lasso_front(const PT &P, float x, float y, float
     cw = c[3];
     if (!(c[3] > 0.0f)) return false;
     if (c[3] >= 1e-30f) {
-        // Pre-test with the hardware reciprocal: x/w and y/w are within 3e-7
-        // relative of the exact quotients, far inside the 1e-4 margins, so a
-        // texel rejected here fails the exact tests below as well -- or, left
-        // of xlo_m, lies left of every vertex by more than 1e-5 (2 + max |x|),
-        // where the fp32 crossing test is exact (see lasso_rect_class): it
-        // counts every edge straddling y, an even number for a closed
-        // polygon, so the texel is outside.
-        const float r = __builtin_amdgcn_rcpf(c[3]);
-        const float ax = c[0] * r, ay = c[1] * r;
-        if (!(ax >= -1.0001f && ax <= 1.0001f && ay >= P.ylo_m && ay <= P.yhi_m && ax <= P.xhi_m &&
-              ax >= P.xlo_m))
+        // Pre-test without a division: for w > 0, x / w >= a iff x >= a w.
+        // The rounded product a w is within 6e-8 relative of the exact one
+        // (or 1.2e-38 absolute if it underflows, 1.2e-8 of x / w at most for
+        // w >= 1e-30), far inside the 1e-4 margins, so a texel rejected here
+        // fails the exact tests below as well -- or, left of xlo_m, lies left
+        // of every vertex by more than 1e-5 (2 + max |x|), where the fp32
+        // crossing test is exact (see lasso_rect_class): it counts every edge
+        // straddling y, an even number for a closed polygon, so the texel is
+        // outside.  Each bound is the larger (smaller) of two such margins,
+        // and rounding is monotone, so the joined test rejects a texel only
+        // where one of the two would.
+        if (!(c[0] >= P.xlo_m * c[3] && c[0] <= P.xhi_m * c[3] && c[1] >= P.ylo_m * c[3] &&
+              c[1] <= P.yhi_m * c[3]))
             return false;
     }
     xn = c[0] / c[3];
