@@ -91,13 +91,15 @@ struct LassoParams {
 // polygon.
 // PT is LassoParams, possibly qualified with the constant address space so
 // that a parameter block in global memory is read with scalar loads.
+// mc[k] is M[4k + 3], the constant term of row k, passed apart so that a
+// caller can hold it in a vector register (see lasso_quad_index).
 template <class PT>
-__device__ __forceinline__ bool lasso_front(const PT &P, float x, float y, float z, float &xn, float &yn,
-                                            float &cz, float &cw) {
+__device__ __forceinline__ bool lasso_front(const PT &P, const float mc[4], float x, float y, float z, float &xn,
+                                            float &yn, float &cz, float &cw) {
     float c[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-        c[k] = __builtin_fmaf(P.M[4 * k + 2], z, __builtin_fmaf(P.M[4 * k + 1], y, __builtin_fmaf(P.M[4 * k + 0], x, P.M[4 * k + 3])));
+        c[k] = __builtin_fmaf(P.M[4 * k + 2], z, __builtin_fmaf(P.M[4 * k + 1], y, __builtin_fmaf(P.M[4 * k + 0], x, mc[k])));
     cz = c[2];
     cw = c[3];
     if (!(c[3] > 0.0f)) return false;
@@ -174,7 +176,8 @@ template <class PT>
 __device__ __forceinline__ bool lasso_texel(const PT &P, const float *__restrict__ depth, float x, float y,
                                             float z) {
     float xn, yn, cz, cw;
-    if (!lasso_front(P, x, y, z, xn, yn, cz, cw)) return false;
+    const float mc[4] = {P.M[3], P.M[7], P.M[11], P.M[15]};
+    if (!lasso_front(P, mc, x, y, z, xn, yn, cz, cw)) return false;
     uint64_t m = P.slab_edges[lasso_slab(P, yn)];
     bool inside = false;
     while (m) {
@@ -248,11 +251,17 @@ __device__ __forceinline__ void lasso_quad_index(const PT &P, const float4 &X, c
     bool cand[4], inside[4];
     unsigned smin = kSlabs, smax = 0;
     float xmin = INFINITY;
+    // The constant terms of M in vector registers, once per call: a VALU
+    // instruction reads at most one scalar register on this target, so
+    // fma(M0, x, M3) with both in scalar registers costs a move per texel.
+    float mc[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) asm("v_mov_b32 %0, %1" : "=v"(mc[k]) : "s"(P.M[4 * k + 3]));
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         xn[k] = 0.0f;
         yn[k] = 0.0f;
-        cand[k] = lasso_front(P, xs[k], ys[k], zs[k], xn[k], yn[k], cz[k], cw[k]);
+        cand[k] = lasso_front(P, mc, xs[k], ys[k], zs[k], xn[k], yn[k], cz[k], cw[k]);
         inside[k] = false;
         if (cand[k]) {
             const unsigned s = (unsigned)lasso_slab(P, yn[k]);
