@@ -295,6 +295,66 @@ def test_lasso_adversarial_polygons(gpu, orc):
             assert np.array_equal(lay.numpy(), ref), (ci, k)
 
 
+def _ndc64(M, pos):
+    """NDC x, y and clip w of positions [3][n] (float64 evaluation of the
+    fp32 rows: within an ulp or two of the edit kernels' values)."""
+    M = np.asarray(M, np.float64).reshape(4, 4)
+    p = np.asarray(pos, np.float64)
+    c = [M[r, 0] * p[0] + M[r, 1] * p[1] + M[r, 2] * p[2] + M[r, 3] for r in range(4)]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return c[0] / c[3], c[1] / c[3], c[3]
+
+
+def test_lasso_pretest_margins(gpu, orc):
+    """Sides through texels' own NDC positions, sides on and beyond the
+    frustum, and a camera whose w = 0 plane cuts the mesh (texels with tiny
+    positive w): the screen-range pre-test must not reject any texel that the
+    exact predicate selects, so every result equals the oracle's."""
+    import torch
+    wl = synth.tiny_workload()
+    W = 384
+    dm, g = _geom_gpu(gpu, wl.mesh, W, W)
+    og = orc.geometry_image(wl.mesh, W, W)
+    pos = og.pos32
+    cov = np.nonzero(~np.isnan(pos[0]))[0]
+    rng = np.random.default_rng(33)
+    M0 = np.asarray(wl.cameras[1], np.float32).reshape(4, 4)
+    # the same camera with its w row shifted so that w = 0 crosses the mesh
+    w0 = _ndc64(M0, pos[:, cov])[2]
+    Mcut = M0.copy()
+    Mcut[3, 3] = np.float32(M0[3, 3] - np.median(w0))
+    Mcut[2] = Mcut[3] * np.float32(0.5)      # NDC z = 0.5 however small w gets
+    d = torch.empty((256, 256), dtype=torch.float32, device="cuda")
+    selected = 0
+    for M in (M0, Mcut):
+        xn, yn, w = _ndc64(M, pos[:, cov])
+        ok = np.nonzero((w > 0) & (np.abs(xn) < 0.95) & (np.abs(yn) < 0.95))[0]
+        assert ok.size > 100
+        polys = []
+        for _ in range(12):
+            i, j = rng.choice(ok, 2)
+            x0, x1 = sorted([xn[i], xn[j]])
+            y0, y1 = sorted([yn[i], yn[j]])
+            polys.append([[x0, y0], [x1, y0], [x1, y1], [x0, y1]])
+            polys.append([[-1.0, y0], [x1, y0], [x1, 1.0], [-1.0, 1.0]])       # sides on the frustum
+            polys.append([[x0, -1.7], [2.5, -1.7], [2.5, y1], [x0, y1]])       # sides beyond it
+        polys.append([[-1.0, -1.0], [1.0, -1.0], [1.0, 1.0], [-1.0, 1.0]])
+        polys.append([[-40.0, -40.0], [40.0, -40.0], [0.0, 40.0]])
+        gpu.render_depth(dm, M, d)
+        od = orc.depth_map(wl.mesh, M, 256, 256)
+        for k, poly in enumerate(polys):
+            poly = np.asarray(poly, np.float32)
+            for bias in (1.0, 1e-4):
+                lay = gpu.create_layer(gpu.Layer(W, W, gpu.U8))
+                gpu.edit_lasso(g, lay, M, poly, d, bias, 1 + k)
+                ref = np.zeros(W * W, np.uint8)
+                orc.lasso(pos, ref, M, poly, od, bias, 1 + k)
+                got = lay.numpy()
+                assert np.array_equal(got, ref), (k, bias, poly.tolist())
+                selected += int((ref != 0).sum())
+    assert selected > 10000
+
+
 # ---------------------------------------------------------------------------
 # layer algebra
 
