@@ -232,3 +232,82 @@ def test_lasso_square_on_facing_plane(orc):
     assert y.min() > -0.4 * s - texel and y.max() < 0.0 + texel
     area = orc.area(g, L)[5]
     assert abs(area / (0.4 * s * 0.4 * s) - 1) < 2e-2
+
+
+def _tiling(rng):
+    """Polygons that tile [-1, 1]^2 exactly: 8 x 8 cells of side 1/4, each a
+    square, a square with a repeated collinear vertex, two triangles on a
+    random diagonal, a fan of four triangles around its centre, or an L-shaped
+    hexagon plus the square it leaves.  Every coordinate is a multiple of
+    1/16, so every difference and product in the crossing test is exact in
+    fp32.  Vertex order is reversed and rotated at random."""
+    q = 0.25
+    tiles = []
+    for cy in range(8):
+        for cx in range(8):
+            x0, y0 = -1 + cx * q, -1 + cy * q
+            x1, y1 = x0 + q, y0 + q
+            xm, ym = x0 + q / 2, y0 + q / 2
+            kind = rng.integers(5)
+            if kind == 0:
+                polys = [[(x0, y0), (x1, y0), (x1, y1), (x0, y1)]]
+            elif kind == 1:
+                polys = [[(x0, y0), (xm, y0), (x1, y0), (x1, y1), (x0, y1)]]
+            elif kind == 2:
+                if rng.integers(2):
+                    polys = [[(x0, y0), (x1, y0), (x1, y1)], [(x0, y0), (x1, y1), (x0, y1)]]
+                else:
+                    polys = [[(x0, y0), (x1, y0), (x0, y1)], [(x1, y0), (x1, y1), (x0, y1)]]
+            elif kind == 3:
+                c = [(x0, y0), (x1, y0), (x1, y1), (x0, y1)]
+                polys = [[c[k], c[(k + 1) % 4], (xm, ym)] for k in range(4)]
+            else:
+                polys = [[(x0, y0), (x1, y0), (x1, ym), (xm, ym), (xm, y1), (x0, y1)],
+                         [(xm, ym), (x1, ym), (x1, y1), (xm, y1)]]
+            for p in polys:
+                if rng.integers(2):
+                    p = p[::-1]
+                r = int(rng.integers(len(p)))
+                tiles.append(np.array(p[r:] + p[:r], np.float32))
+    return tiles
+
+
+def test_point_in_polygon_boundary_rule_tiles_exactly_once(orc):
+    # The crossing rule is half-open: a point on an edge or vertex belongs to
+    # the polygon reached by moving it right by e and up by d, with
+    # 0 < d << e infinitesimal.  So where polygons tile a region, every point
+    # of the region -- on shared edges, on horizontal edges, at shared
+    # vertices, at T-junctions -- is inside exactly one of them.  A > slipped
+    # to >= on one side of the straddle test, or a <= in the crossing test,
+    # puts such points in zero or two tiles.
+    rng = np.random.default_rng(2501)
+    tiles = _tiling(rng)
+    boxes = [(t[:, 0].min(), t[:, 0].max(), t[:, 1].min(), t[:, 1].max()) for t in tiles]
+    g = np.arange(-16, 16, dtype=np.float64) / 16.0            # every vertex and edge point of the grid
+    fine = rng.integers(-64, 64, size=(600, 2)) / 64.0        # points on diagonals and inside cells
+    pts = [(x, y) for y in g for x in g] + [tuple(p) for p in fine]
+    for x, y in pts:
+        hits = 0
+        for t, (bx0, bx1, by0, by1) in zip(tiles, boxes):
+            if bx0 <= x <= bx1 and by0 <= y <= by1:
+                hits += orc.point_in_polygon(x, y, t)
+        assert hits == 1, (x, y, hits)
+
+
+def test_point_in_polygon_boundary_convention(orc):
+    # The edges that hold their points are the ones the rule above gives: for
+    # an axis-aligned square the lower and left edges and the lower-left
+    # corner belong to it, the upper and right ones and the other corners do
+    # not (either winding).
+    sq = np.array([[0.0, 0.0], [0.5, 0.0], [0.5, 0.5], [0.0, 0.5]], np.float32)
+    for poly in (sq, sq[::-1].copy()):
+        inside = [(0.0, 0.0), (0.25, 0.0), (0.0, 0.25), (0.25, 0.25)]
+        outside = [(0.5, 0.0), (0.5, 0.5), (0.0, 0.5), (0.25, 0.5), (0.5, 0.25)]
+        for x, y in inside:
+            assert orc.point_in_polygon(x, y, poly), (x, y)
+        for x, y in outside:
+            assert not orc.point_in_polygon(x, y, poly), (x, y)
+    # a point on a slanted edge belongs to the polygon on the edge's right
+    lower = np.array([[0.0, 0.0], [0.5, 0.0], [0.5, 0.5]], np.float32)
+    upper = np.array([[0.0, 0.0], [0.5, 0.5], [0.0, 0.5]], np.float32)
+    assert orc.point_in_polygon(0.25, 0.25, lower) and not orc.point_in_polygon(0.25, 0.25, upper)
