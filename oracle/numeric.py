@@ -29,7 +29,16 @@ here (the paper gives the textures, not the operations on numeric layers):
     bit is set, grouped by the value of a label layer (one group when there
     is none): count, surface area, area-weighted sum of values, minimum and
     maximum.  Table 1 gives the surface area one texel stands for; the
-    weighted sum over the area is the area-weighted mean.
+    weighted sum over the area is the area-weighted mean;
+  - operations between two numeric layers of one dtype, texel by texel
+    (operating with quantitative information, §4.2): a result validity r
+    (AND / OR / XOR of the operands' mask bits; both valid for MIN, MAX and
+    ADD); where r holds, the data become the value (mask operations: a's
+    value if a is valid, else b's; MIN: a if a <= b else b; MAX: a if
+    a >= b else b; ADD: the sum rounded once to the dtype -- integers
+    exactly, binary32 by its own addition, binary16 from the exact sum --
+    with results beyond the dtype's finite range taking its extreme finite
+    value); where r does not hold, the data stay and the bit is cleared.
 
 Pins (tests/test_oracle_numeric.py): binary16 bit patterns fixed by the
 IEEE 754 format (normal, subnormal, ties, overflow) and numpy's independent
@@ -48,6 +57,7 @@ from . import brush as _brush, lasso as _lasso, pad as _pad, tool as _tool
 
 U8, U16, I32, F16, F32 = 1, 2, 3, 4, 5
 SET, ERASE = 0, 1
+NUM_AND, NUM_OR, NUM_XOR, NUM_MIN, NUM_MAX, NUM_ADD = 0, 1, 2, 3, 4, 5
 
 NP_DTYPE = {U8: np.uint8, U16: np.uint16, I32: np.int32, F16: np.float16, F32: np.float32}
 INT_RANGE = {U8: (0, 255), U16: (0, 65535), I32: (-2 ** 31, 2 ** 31 - 1)}
@@ -209,3 +219,53 @@ def stats(tri_id: np.ndarray, w: np.ndarray, layer: NumericLayer, region=None) -
         out[lab[grp[0]]] = (grp.size, math.fsum(wb), math.fsum(wb * vb), vb.min(), vb.max(),
                             math.fsum(np.abs(wb * vb)), math.fsum(np.abs(vb)))
     return out
+
+
+FLOAT_MAX = {F16: 65504.0, F32: float(np.finfo(np.float32).max)}
+
+
+def _add(xa: np.ndarray, xb: np.ndarray, dtype: int) -> np.ndarray:
+    """Saturating sum in the dtype: integers exact, then clipped to the
+    range; binary32 by its own (correctly rounded) addition; binary16 from
+    the exact sum (in fp64) rounded once; float results beyond the largest
+    finite value take it, with their sign."""
+    if dtype in INT_RANGE:
+        lo, hi = INT_RANGE[dtype]
+        return np.clip(xa.astype(np.int64) + xb.astype(np.int64), lo, hi).astype(NP_DTYPE[dtype])
+    with np.errstate(over="ignore", invalid="ignore"):
+        if dtype == F32:
+            s = xa.astype(np.float32) + xb.astype(np.float32)
+        else:
+            s = (xa.astype(np.float64) + xb.astype(np.float64)).astype(np.float16)
+    m = FLOAT_MAX[dtype]
+    return np.where(np.isinf(s), np.copysign(m, s), s).astype(NP_DTYPE[dtype])
+
+
+def combine(op: int, dst: NumericLayer, a: NumericLayer, b: NumericLayer) -> int:
+    """dst = a op b texel by texel (dst may be a or b); returns the number
+    of valid result texels."""
+    if not (a.dtype == b.dtype == dst.dtype):
+        raise ValueError("dtypes differ")
+    va, vb = a.valid.copy(), b.valid.copy()
+    xa, xb = a.data.copy(), b.data.copy()
+    if op == NUM_AND:
+        r = va & vb
+    elif op == NUM_OR:
+        r = va | vb
+    elif op == NUM_XOR:
+        r = va ^ vb
+    elif op in (NUM_MIN, NUM_MAX, NUM_ADD):
+        r = va & vb
+    else:
+        raise ValueError("op")
+    if op in (NUM_AND, NUM_OR, NUM_XOR):
+        val = np.where(va, xa, xb)
+    elif op == NUM_MIN:
+        val = np.where(xa <= xb, xa, xb)
+    elif op == NUM_MAX:
+        val = np.where(xa >= xb, xa, xb)
+    else:
+        val = _add(xa, xb, a.dtype)
+    dst.data[r] = val[r]
+    dst.valid[:] = r
+    return int(r.sum())

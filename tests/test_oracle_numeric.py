@@ -175,3 +175,122 @@ def test_range_selection_band(orc):
     assert N.select(L, 2.0, 1.0, dst, 6) == 0
     L.valid[:W * W // 2] = False
     assert N.select(L, 0.0, 1.0, dst, 7) == n // 2
+
+
+# ---------------------------------------------------------------------------
+# operations between numeric layers
+
+
+def _layer(dtype, data, valid):
+    L = N.NumericLayer(len(data), dtype)
+    L.data[:] = np.asarray(data).astype(N.NP_DTYPE[dtype])
+    L.valid[:] = np.asarray(valid, bool)
+    return L
+
+
+def test_mask_operations_inclusion_exclusion_and_data_source():
+    # validity is set algebra on the masks: |A or B| = |A| + |B| - |A and B|,
+    # A xor B = (A or B) minus (A and B), A and A = A, A xor A = nothing; a
+    # valid result holds a's value where a is valid and b's elsewhere, and
+    # texels left invalid keep dst's data
+    rng = np.random.default_rng(11)
+    n = 4099
+    va, vb = rng.random(n) < 0.4, rng.random(n) < 0.6
+    a = _layer(N.I32, rng.integers(-1000, 1000, n), va)
+    b = _layer(N.I32, rng.integers(-1000, 1000, n), vb)
+    out = {}
+    for op in (N.NUM_AND, N.NUM_OR, N.NUM_XOR):
+        d = _layer(N.I32, np.full(n, 77), np.ones(n, bool))
+        out[op] = (N.combine(op, d, a, b), d)
+    n_and, n_or, n_xor = out[N.NUM_AND][0], out[N.NUM_OR][0], out[N.NUM_XOR][0]
+    assert n_or == va.sum() + vb.sum() - n_and
+    assert n_xor == n_or - n_and
+    d_or = out[N.NUM_OR][1]
+    assert (d_or.data[va] == a.data[va]).all()
+    assert (d_or.data[vb & ~va] == b.data[vb & ~va]).all()
+    assert (d_or.data[~(va | vb)] == 77).all() and not d_or.valid[~(va | vb)].any()
+    same = _layer(N.I32, a.data, va)
+    assert N.combine(N.NUM_AND, same, same, same) == va.sum() and (same.valid == va).all()
+    assert N.combine(N.NUM_XOR, same, same, same) == 0 and not same.valid.any()
+
+
+@pytest.mark.parametrize("dtype", [N.U8, N.U16, N.I32, N.F16, N.F32])
+def test_min_max_sum_identity_and_idempotence(dtype):
+    # min(a, b) + max(a, b) = a + b and min <= max, each one of the two;
+    # MIN(A, A) = MAX(A, A) = A
+    rng = np.random.default_rng(dtype)
+    n = 3000
+    if dtype in N.INT_RANGE:
+        lo, hi = N.INT_RANGE[dtype]
+        xa, xb = rng.integers(lo, hi, n, endpoint=True), rng.integers(lo, hi, n, endpoint=True)
+    else:
+        xa = rng.normal(0, 100, n).astype(N.NP_DTYPE[dtype])
+        xb = rng.normal(0, 100, n).astype(N.NP_DTYPE[dtype])
+    v = rng.random(n) < 0.8
+    a, b = _layer(dtype, xa, v), _layer(dtype, xb, np.ones(n, bool))
+    mn, mx = _layer(dtype, np.zeros(n), v), _layer(dtype, np.zeros(n), v)
+    N.combine(N.NUM_MIN, mn, a, b)
+    N.combine(N.NUM_MAX, mx, a, b)
+    A, B = a.data.astype(np.float64)[v], b.data.astype(np.float64)[v]
+    lo_, hi_ = mn.data.astype(np.float64)[v], mx.data.astype(np.float64)[v]
+    assert (lo_ + hi_ == A + B).all() and (lo_ <= hi_).all()
+    assert ((lo_ == A) | (lo_ == B)).all()
+    assert (mn.valid == v).all() and (mx.valid == v).all()
+    c = _layer(dtype, a.data, v)
+    N.combine(N.NUM_MIN, c, c, c)
+    assert np.array_equal(c.data, a.data) and (c.valid == v).all()
+
+
+def test_integer_sums_saturate_at_the_range():
+    # u8 over every pair: the sum where it fits, 255 exactly when a + b >= 255
+    x = np.repeat(np.arange(256), 256)
+    y = np.tile(np.arange(256), 256)
+    a, b = _layer(N.U8, x, np.ones(x.size, bool)), _layer(N.U8, y, np.ones(x.size, bool))
+    d = _layer(N.U8, np.zeros(x.size), np.zeros(x.size, bool))
+    N.combine(N.NUM_ADD, d, a, b)
+    fits = x + y <= 255
+    assert (d.data[fits].astype(np.int64) == (x + y)[fits]).all()
+    assert (d.data[~fits] == 255).all()
+    # the adding order does not matter and 0 is neutral
+    d2 = _layer(N.U8, np.zeros(x.size), np.zeros(x.size, bool))
+    N.combine(N.NUM_ADD, d2, b, a)
+    assert np.array_equal(d.data, d2.data)
+    big = 2 ** 31 - 1
+    a = _layer(N.I32, [big, -big - 1, 5, -7], np.ones(4, bool))
+    b = _layer(N.I32, [5, -1, -big - 1, big], np.ones(4, bool))
+    d = _layer(N.I32, np.zeros(4), np.zeros(4, bool))
+    N.combine(N.NUM_ADD, d, a, b)
+    assert d.data.tolist() == [big, -big - 1, 5 - big - 1, big - 7]
+
+
+def test_float_sums_round_once():
+    rng = np.random.default_rng(5)
+    # binary16: the exact sum rounded by the format's own rule (f16_bits,
+    # pinned above by IEEE bit patterns), ties and subnormals included
+    raw = rng.integers(0, 0x7C00, (2, 20000)).astype(np.uint16)      # finite positives
+    raw[:, ::2] |= 0x8000                                             # and negatives
+    h = raw.view(np.float16)
+    a, b = _layer(N.F16, h[0], np.ones(h.shape[1], bool)), _layer(N.F16, h[1], np.ones(h.shape[1], bool))
+    d = _layer(N.F16, np.zeros(h.shape[1]), np.zeros(h.shape[1], bool))
+    N.combine(N.NUM_ADD, d, a, b)
+    for k in range(h.shape[1]):
+        s = float(h[0, k]) + float(h[1, k])          # exact in fp64
+        try:
+            want = N.f16_bits(s)
+        except OverflowError:
+            want = 0x7BFF | (0x8000 if s < 0 else 0)  # saturates at the largest finite value
+        assert d.data.view(np.uint16)[k] == want, (h[0, k], h[1, k])
+    # binary32: operands in [1, 2^20] have an exact double sum, whose
+    # nearest binary32 is the correctly rounded sum
+    fa = rng.uniform(1, 2 ** 20, 20000).astype(np.float32)
+    fb = rng.uniform(1, 2 ** 20, 20000).astype(np.float32)
+    a, b = _layer(N.F32, fa, np.ones(fa.size, bool)), _layer(N.F32, fb, np.ones(fa.size, bool))
+    d = _layer(N.F32, np.zeros(fa.size), np.zeros(fa.size, bool))
+    N.combine(N.NUM_ADD, d, a, b)
+    exact = fa.astype(np.float64) + fb.astype(np.float64)
+    assert np.array_equal(d.data, exact.astype(np.float32))
+    top = np.finfo(np.float32).max
+    a, b = _layer(N.F32, [top, -top], [1, 1]), _layer(N.F32, [top, -top], [1, 1])
+    d = _layer(N.F32, [0, 0], [0, 0])
+    N.combine(N.NUM_ADD, d, a, b)
+    assert d.data.tolist() == [top, -top]
