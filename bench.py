@@ -567,7 +567,6 @@ def main():
     wl, desc = make_workload(args.workload)
     log(f"workload generated in {time.perf_counter() - t:.1f} s: {desc}")
     m = Model.from_workload(wl)
-    m.upload_luts(wl.ops)
     N = wl.W * wl.H
     T = Timer(torch)
     for k in range(args.warmup):

@@ -119,6 +119,18 @@ typedef struct {
     int32_t dtype;          /* uvl_dtype */
 } uvl_layer;
 
+/* Planes of a geometry image, for uvl_geom_bytes: tri_id, pos_x/y/z and
+ * area_w always, these besides. */
+#define UVL_GEOM_NRM      1u   /* nrm_x, nrm_y, nrm_z */
+#define UVL_GEOM_BARY     2u   /* bary1, bary2 */
+#define UVL_GEOM_TILE_BOX 4u   /* tile_box */
+
+/* Device bytes of the planes of a width x height geometry image: each plane
+ * of N = width*height elements rounded up to a multiple of 256 bytes (so
+ * that planes cut from one buffer stay aligned), plus the planes named by
+ * plane_flags.  0 for a size outside [1, 32768] or an unknown flag. */
+size_t uvl_geom_bytes(int32_t width, int32_t height, uint32_t plane_flags);
+
 /* Text for a status code (static storage). */
 const char *uvl_status_str(int32_t status);
 
@@ -199,12 +211,15 @@ int32_t uvl_edit_lasso(const uvl_geom *geom, const uvl_layer *layer, const float
 /* Layer algebra (§3.4.2: logic operations between layers; §4.2: database
  * layers hold unsigned keys).  Operand predicate P_X = (sel_X == 0 ?
  * X != 0 : X == sel_X).  AND / OR / XOR: dst = (P_a op P_b) ? out_label : 0.
- * REMAP: dst = a ? lut[a] : 0, lut a DEVICE array of 256 (a is u8) or 65536
- * (a is u16) uint16 entries, each of which must fit dst's dtype (wider
- * entries are truncated to dst's width); b, sel_a, sel_b, out_label are
- * ignored.  dst may alias a or b; all three must have the same size; their
- * dtypes may differ.  Errors: UVL_E_INVAL, UVL_E_SHAPE, UVL_E_DTYPE
- * (out_label does not fit dst). */
+ * REMAP: dst = lut[a], lut a HOST array of 256 (a is u8) or 65536 (a is
+ * u16) uint16 entries with lut[0] == 0 (the null key stays null) and every
+ * entry within dst's dtype; it is read during the call and may be freed on
+ * return (a 65536-entry table is staged through a ring of 16 library-owned
+ * slots; a call that finds its slot still in use by an earlier REMAP waits
+ * for that REMAP to finish).  b, sel_a, sel_b, out_label are ignored by
+ * REMAP.  dst may alias a or b; all three must have the same size; their
+ * dtypes may differ.  Errors: UVL_E_INVAL (null pointers, lut[0] != 0),
+ * UVL_E_SHAPE, UVL_E_DTYPE (out_label or a table entry does not fit dst). */
 int32_t uvl_layer_op(int32_t op, const uvl_layer *dst, const uvl_layer *a, const uvl_layer *b,
                      uint32_t sel_a, uint32_t sel_b, uint32_t out_label, const uint16_t *lut,
                      void *stream);
@@ -392,8 +407,11 @@ int32_t uvl_pool_create(int32_t slots_per_key, uvl_pool **out);
  * called with another device current). */
 int32_t uvl_pool_alloc(uvl_pool *pool, int32_t width, int32_t height, int32_t dtype, void **data, int32_t *slot);
 
-/* Release a layer from uvl_pool_alloc.  The caller makes sure no pending
- * work uses it.  Errors: UVL_E_INVAL (not a committed layer of this pool). */
+/* Release a layer from uvl_pool_alloc.  SYNCHRONOUS: waits for all work
+ * queued on the pool's device (every stream) before the memory is unmapped,
+ * so no queued kernel can still touch it.  Errors: UVL_E_INVAL (not a
+ * committed layer of this pool), UVL_E_DEVICE (another device current, or
+ * HIP fails; if the unmap itself fails the layer stays committed). */
 int32_t uvl_pool_free(uvl_pool *pool, void *data);
 
 /* The array of a key: base address, slot stride in bytes, slot count.
@@ -405,7 +423,9 @@ int32_t uvl_pool_array(const uvl_pool *pool, int32_t width, int32_t height, int3
  * the number of keys. */
 int32_t uvl_pool_stats(const uvl_pool *pool, uint64_t *reserved, uint64_t *committed, int32_t *keys);
 
-/* Release every layer and reservation of the pool, then the pool. */
+/* Release every layer and reservation of the pool, then the pool (waits for
+ * the pool's device first, as uvl_pool_free; call it with that device
+ * current). */
 int32_t uvl_pool_destroy(uvl_pool *pool);
 
 /* ------------------------------------------------------------------------

@@ -177,6 +177,8 @@ def layer_op(op: int, dst: np.ndarray, a: np.ndarray, b=None, sel_a: int = 0, se
     if op == REMAP:
         if lutc is None or lutc.shape[0] != (256 if a.dtype == np.uint8 else 65536) or lutc[0] != 0:
             raise ValueError("REMAP needs a lut of 256 / 65536 entries with lut[0] == 0")
+        if dst.dtype == np.uint8 and int(lutc.max()) > 255:
+            raise ValueError("REMAP table entries must fit the destination")
     rc = lib().orc_layer_op(op, _p(dst), _dtype_code(dst), _p(a), _dtype_code(a), _p(b),
                             _dtype_code(b), dst.size, sel_a, sel_b, out_label, _p(lutc))
     if rc != 0:

@@ -4,9 +4,20 @@
 // One streaming pass, 16 texels per thread: 16-byte vector loads of each u8
 // operand (two for u16), the predicate combination in registers, one vector
 // store.  dst may alias a or b: every thread reads its texels before it
-// writes them and no two threads share a texel.  REMAP with a u8 operand
-// stages the 256-entry table in LDS; a u16 operand gathers from the 128 KiB
-// table, which stays resident in L2.
+// writes them and no two threads share a texel.
+//
+// REMAP tables come from the host and are checked there (entry 0 maps the
+// null key to itself, every entry fits dst) before anything is enqueued.  A
+// 256-entry table (u8 operand) travels in the kernel arguments and is staged
+// in LDS.  A 65536-entry table (u16 operand) is copied into a pinned host
+// slot and from there, on the caller's stream, into a slot of a static
+// device ring the kernel gathers from (128 KiB, resident in L2); an event
+// after the kernel frees the slot, and a call that finds its slot still in
+// use waits for that event.
+#include <string.h>
+
+#include <mutex>
+
 #include "uvl_internal.h"
 
 namespace uvl {
@@ -81,28 +92,82 @@ __global__ __launch_bounds__(kBlock) void k_logic(Td *dst, const Ta *a, const Tb
     }
 }
 
+struct Lut256 {
+    uint16_t v[256];
+};
+
 template <typename Td, typename Ta>
-__global__ __launch_bounds__(kBlock) void k_remap(Td *dst, const Ta *a, int64_t n, const uint16_t *__restrict__ lut) {
-    __shared__ uint16_t s_lut[256];
-    constexpr bool kSmall = sizeof(Ta) == 1;
-    if (kSmall) {
-        s_lut[threadIdx.x] = lut[threadIdx.x];
-        __syncthreads();
-    }
-    auto map = [&](uint32_t v) -> uint32_t {
-        const uint32_t r = kSmall ? s_lut[v & 0xffu] : lut[v];
-        return v == 0 ? 0u : r;
-    };
+__device__ __forceinline__ void remap_body(Td *dst, const Ta *a, int64_t n, const uint16_t *tab) {
     const int64_t t0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kPer;
     if (t0 + kPer <= n) {
         uint32_t va[kPer], vd[kPer];
         load16<Ta>(a + t0, va);
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) vd[k] = map(va[k]);
+        for (int k = 0; k < kPer; ++k) vd[k] = tab[va[k]];
         store16<Td>(dst + t0, vd);
     } else {
-        for (int64_t t = t0; t < n; ++t) dst[t] = (Td)map(a[t]);
+        for (int64_t t = t0; t < n; ++t) dst[t] = (Td)tab[a[t]];
     }
+}
+
+// u8 operand: the table arrives by value and is staged in LDS.
+template <typename Td>
+__global__ __launch_bounds__(kBlock) void k_remap8(Td *dst, const uint8_t *a, int64_t n, Lut256 lut) {
+    __shared__ uint16_t s_lut[256];
+    s_lut[threadIdx.x] = lut.v[threadIdx.x];
+    __syncthreads();
+    remap_body<Td, uint8_t>(dst, a, n, s_lut);
+}
+
+// u16 operand: gathers from the table in device memory.
+template <typename Td>
+__global__ __launch_bounds__(kBlock) void k_remap16(Td *dst, const uint16_t *a, int64_t n,
+                                                    const uint16_t *__restrict__ lut) {
+    remap_body<Td, uint16_t>(dst, a, n, lut);
+}
+
+// Ring of 65536-entry tables: the device side is a static array (no
+// allocation), addressed through hipGetSymbolAddress on each device.
+constexpr int kRemapSlots = 16;
+constexpr size_t kRemapEntries = 65536;
+__device__ __align__(256) uint16_t g_remap_ring[kRemapSlots * kRemapEntries];
+
+struct RemapRing {
+    bool ready = false;
+    uint16_t *dev = nullptr;        // device address of g_remap_ring on this device
+    uint16_t *host = nullptr;       // pinned staging, kRemapSlots tables
+    hipEvent_t ev[kRemapSlots] = {};
+    bool pending[kRemapSlots] = {};
+    int next = 0;
+};
+
+std::mutex g_ring_mu;
+RemapRing g_ring[64];
+
+// The ring of the current device, set up on first use (called locked).
+int32_t ring_for_device(RemapRing *&out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return UVL_E_DEVICE;
+    RemapRing &r = g_ring[dev];
+    if (!r.ready) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_remap_ring)) != hipSuccess || !p) return UVL_E_DEVICE;
+        void *h = nullptr;
+        if (hipHostMalloc(&h, kRemapSlots * kRemapEntries * sizeof(uint16_t), hipHostMallocDefault) != hipSuccess)
+            return UVL_E_DEVICE;
+        for (int k = 0; k < kRemapSlots; ++k) {
+            if (hipEventCreateWithFlags(&r.ev[k], hipEventDisableTiming) != hipSuccess) {
+                for (int q = 0; q < k; ++q) (void)hipEventDestroy(r.ev[q]);
+                (void)hipHostFree(h);
+                return UVL_E_DEVICE;
+            }
+        }
+        r.dev = static_cast<uint16_t *>(p);
+        r.host = static_cast<uint16_t *>(h);
+        r.ready = true;
+    }
+    out = &r;
+    return UVL_OK;
 }
 
 template <typename Td, typename Ta, typename Tb>
@@ -117,10 +182,46 @@ void launch_logic(int op, void *d, const void *a, const void *b, int64_t n, uint
     else hipLaunchKernelGGL((k_logic<Td, Ta, Tb, UVL_XOR>), grid, block, 0, s, D, A, B, n, sa, sb, out);
 }
 
-template <typename Td, typename Ta>
-void launch_remap(void *d, const void *a, int64_t n, const uint16_t *lut, hipStream_t s) {
+// Table check: the null key maps to itself and every entry fits dst.
+int32_t check_lut(const uint16_t *lut, size_t n, uint32_t dst_max) {
+    if (lut[0] != 0) return UVL_E_INVAL;
+    uint32_t mx = 0;
+    for (size_t k = 0; k < n; ++k) mx = lut[k] > mx ? lut[k] : mx;
+    return mx > dst_max ? UVL_E_DTYPE : UVL_OK;
+}
+
+int32_t launch_remap(const uvl_layer *dst, const uvl_layer *a, const uint16_t *lut, hipStream_t s) {
+    const int64_t n = (int64_t)dst->width * dst->height;
     const dim3 grid((unsigned)ceil_div(n, (int64_t)kBlock * kPer)), block(kBlock);
-    hipLaunchKernelGGL((k_remap<Td, Ta>), grid, block, 0, s, static_cast<Td *>(d), static_cast<const Ta *>(a), n, lut);
+    const bool d8 = dst->dtype == UVL_U8;
+    if (a->dtype == UVL_U8) {
+        Lut256 L;
+        memcpy(L.v, lut, sizeof(L.v));
+        const uint8_t *A = static_cast<const uint8_t *>(a->data);
+        if (d8) hipLaunchKernelGGL(k_remap8<uint8_t>, grid, block, 0, s, static_cast<uint8_t *>(dst->data), A, n, L);
+        else hipLaunchKernelGGL(k_remap8<uint16_t>, grid, block, 0, s, static_cast<uint16_t *>(dst->data), A, n, L);
+        return launch_status();
+    }
+    std::lock_guard<std::mutex> lock(g_ring_mu);
+    RemapRing *r = nullptr;
+    if (int32_t st = ring_for_device(r)) return st;
+    const int k = r->next;
+    if (r->pending[k]) {
+        if (hipEventSynchronize(r->ev[k]) != hipSuccess) return UVL_E_DEVICE;
+        r->pending[k] = false;
+    }
+    uint16_t *h = r->host + (size_t)k * kRemapEntries, *d = r->dev + (size_t)k * kRemapEntries;
+    memcpy(h, lut, kRemapEntries * sizeof(uint16_t));
+    if (hipMemcpyAsync(d, h, kRemapEntries * sizeof(uint16_t), hipMemcpyHostToDevice, s) != hipSuccess)
+        return UVL_E_DEVICE;
+    const uint16_t *A = static_cast<const uint16_t *>(a->data);
+    if (d8) hipLaunchKernelGGL(k_remap16<uint8_t>, grid, block, 0, s, static_cast<uint8_t *>(dst->data), A, n, d);
+    else hipLaunchKernelGGL(k_remap16<uint16_t>, grid, block, 0, s, static_cast<uint16_t *>(dst->data), A, n, d);
+    if (launch_status() != UVL_OK) return UVL_E_DEVICE;
+    if (hipEventRecord(r->ev[k], s) != hipSuccess) return UVL_E_DEVICE;
+    r->pending[k] = true;
+    r->next = (k + 1) % kRemapSlots;
+    return UVL_OK;
 }
 
 }  // namespace
@@ -140,12 +241,9 @@ extern "C" int32_t uvl_layer_op(int32_t op, const uvl_layer *dst, const uvl_laye
     const bool d8 = dst->dtype == UVL_U8, a8 = a->dtype == UVL_U8;
     if (op == UVL_REMAP) {
         if (!lut) return UVL_E_INVAL;
+        if (int32_t st = check_lut(lut, a8 ? 256 : kRemapEntries, dtype_max(dst->dtype))) return st;
         if (int32_t st = device_ok()) return st;
-        if (d8 && a8) launch_remap<uint8_t, uint8_t>(dst->data, a->data, n, lut, s);
-        else if (d8) launch_remap<uint8_t, uint16_t>(dst->data, a->data, n, lut, s);
-        else if (a8) launch_remap<uint16_t, uint8_t>(dst->data, a->data, n, lut, s);
-        else launch_remap<uint16_t, uint16_t>(dst->data, a->data, n, lut, s);
-        return launch_status();
+        return launch_remap(dst, a, lut, s);
     }
     if (!layer_ok(b)) return UVL_E_INVAL;
     if (!dtype_ok(b->dtype)) return UVL_E_DTYPE;

@@ -51,13 +51,16 @@ bool key_ok(int32_t w, int32_t h, int32_t dt) {
     return w >= 1 && h >= 1 && w <= kMaxSide && h <= kMaxSide && dt >= UVL_U8 && dt <= UVL_F32;
 }
 
-// Unmap and release slot k of a slab (committed); false if HIP fails.
+// Unmap and release slot k of a slab (committed); false if HIP fails.  A
+// slot whose unmap fails stays committed and in use (its mapping is still
+// there); once unmapped, the slot is free again even if releasing the
+// physical memory fails.
 bool release_slot(uvl_pool *p, uvl_pool::Slab &s, int k) {
-    const bool ok = hipMemUnmap(s.base + (size_t)k * s.stride, s.stride) == hipSuccess;
+    if (hipMemUnmap(s.base + (size_t)k * s.stride, s.stride) != hipSuccess) return false;
     const bool rel = hipMemRelease(s.handle[k]) == hipSuccess;
     s.used[k] = false;
     p->committed -= s.stride;
-    return ok && rel;
+    return rel;
 }
 
 }  // namespace
@@ -147,6 +150,11 @@ extern "C" int32_t uvl_pool_free(uvl_pool *p, void *data) {
         const size_t off = (size_t)(c - s.base);
         const int k = (int)(off / s.stride);
         if (off % s.stride || !s.used[k]) return UVL_E_INVAL;
+        // Unmapping is not ordered against queued kernels: wait for every
+        // stream of the pool's device before the memory goes away.
+        int cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess || cur != p->device) return UVL_E_DEVICE;
+        if (hipDeviceSynchronize() != hipSuccess) return UVL_E_DEVICE;
         return release_slot(p, s, k) ? UVL_OK : UVL_E_DEVICE;
     }
     return UVL_E_INVAL;
@@ -180,6 +188,8 @@ extern "C" int32_t uvl_pool_destroy(uvl_pool *p) {
     bool ok = true;
     {
         std::lock_guard<std::mutex> lock(p->mu);
+        int cur = 0;
+        ok = hipGetDevice(&cur) == hipSuccess && cur == p->device && hipDeviceSynchronize() == hipSuccess;
         for (auto &kv : p->keys) {
             uvl_pool::Slab &s = kv.second;
             for (int k = 0; k < p->slots; ++k)

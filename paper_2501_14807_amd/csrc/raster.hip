@@ -455,6 +455,20 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 using namespace uvl;
 
+extern "C" size_t uvl_geom_bytes(int32_t width, int32_t height, uint32_t flags) {
+    if (width < 1 || height < 1 || width > kMaxSide || height > kMaxSide) return 0;
+    if (flags & ~(uint32_t)(UVL_GEOM_NRM | UVL_GEOM_BARY | UVL_GEOM_TILE_BOX)) return 0;
+    const size_t n = (size_t)width * height;
+    const size_t plane = align256(n * 4);        // every plane holds 4-byte elements
+    size_t planes = 5;                            // tri_id, pos x/y/z, area_w
+    if (flags & UVL_GEOM_NRM) planes += 3;
+    if (flags & UVL_GEOM_BARY) planes += 2;
+    size_t bytes = planes * plane;
+    if (flags & UVL_GEOM_TILE_BOX)
+        bytes += align256((size_t)ceil_div(width, UVL_TILE_SIDE) * ceil_div(height, UVL_TILE_SIDE) * 6 * sizeof(float));
+    return bytes;
+}
+
 extern "C" size_t uvl_build_workspace_bytes(int64_t nt) {
     if (nt < 0) return 0;
     return 256 + align256((size_t)nt * sizeof(double)) + align256((size_t)nt * sizeof(unsigned));

@@ -35,7 +35,6 @@ class Model:
         self.depth_ws = uvl.depth_workspace(self.mesh)
         self._depth: "OrderedDict[int, torch.Tensor]" = OrderedDict()
         self._depth_cap = max(1, depth_cache)
-        self._luts = {}
         self.bins = torch.empty(uvl.nbins(self.layers), dtype=torch.int64, device=device)
 
     @classmethod
@@ -107,20 +106,9 @@ class Model:
             uvl.render_depth(self.mesh, cameras[cam], d, self.depth_ws)
 
     # -- layer algebra ---------------------------------------------------------
-    def upload_luts(self, ops):
-        for o in ops:
-            if o.lut is not None and id(o) not in self._luts:
-                self._luts[id(o)] = torch.from_numpy(np.ascontiguousarray(o.lut, dtype=np.uint16)).to(
-                    self.device)
-
     def apply_op(self, o):
-        lut = None
-        if o.lut is not None:
-            if id(o) not in self._luts:
-                self.upload_luts([o])
-            lut = self._luts[id(o)]
         b = None if o.op == uvl.REMAP else self.layers[o.b]
-        uvl.layer_op(o.op, self.layers[o.dst], self.layers[o.a], b, o.sel_a, o.sel_b, o.out_label, lut)
+        uvl.layer_op(o.op, self.layers[o.dst], self.layers[o.a], b, o.sel_a, o.sel_b, o.out_label, o.lut)
 
     # -- queries -------------------------------------------------------------
     def areas(self, sync: bool = True, layers: Optional[Sequence[int]] = None):

@@ -153,7 +153,7 @@ class GpuExecutor(Executor):
     """The HIP library behind the server: models resident as Model objects,
     edits through waves (batched) or single launches (plain)."""
 
-    def __init__(self, models, cameras, max_wave_edits=4096, lut_slots=32, pad_k=None):
+    def __init__(self, models, cameras, max_wave_edits=4096, pad_k=None):
         import torch
         from . import uvl
         self.torch, self.uvl = torch, uvl
@@ -168,12 +168,6 @@ class GpuExecutor(Executor):
         self.wave = uvl.Wave(max_wave_edits, max_wave_edits)
         self.max_wave_edits = max_wave_edits
         self._keep = []                       # host arrays of launched batches until their round ends
-        # remap tables go up through a ring of pinned slots (an upload from
-        # pageable memory would wait for the whole device queue)
-        self._lut_host = torch.empty((lut_slots, 65536), dtype=torch.uint16, pin_memory=True)
-        self._lut_dev = torch.empty((lut_slots, 65536), dtype=torch.uint16, device="cuda")
-        self._lut_ev = [None] * lut_slots
-        self._lut_next = 0
 
     def footprint(self, model):
         m = self.models[model]
@@ -229,21 +223,8 @@ class GpuExecutor(Executor):
                 self.uvl.pad_lasso(m.geom, m.layers[e.layer], o, M, e.poly, d, m.bias, e.label)
         elif r.kind == "algebra":
             o = r.op
-            lut = None
-            if o.lut is not None:
-                k = self._lut_next
-                self._lut_next = (k + 1) % len(self._lut_ev)
-                if self._lut_ev[k] is not None:
-                    self._lut_ev[k].synchronize()     # the slot's previous upload has run
-                n = len(o.lut)
-                self._lut_host[k, :n].numpy()[:] = o.lut
-                lut = self._lut_dev[k, :n]
-                lut.copy_(self._lut_host[k, :n], non_blocking=True)
-                ev = self.torch.cuda.Event()
-                ev.record()
-                self._lut_ev[k] = ev
             b = None if o.op == self.uvl.REMAP else m.layers[o.b]
-            self.uvl.layer_op(o.op, m.layers[o.dst], m.layers[o.a], b, o.sel_a, o.sel_b, o.out_label, lut)
+            self.uvl.layer_op(o.op, m.layers[o.dst], m.layers[o.a], b, o.sel_a, o.sel_b, o.out_label, o.lut)
         elif r.kind == "area":
             bins = self.uvl.area_query(m.geom, [m.layers[r.layer]], sync=False)
             host = self.torch.empty(bins.shape, dtype=bins.dtype, pin_memory=True)

@@ -76,6 +76,7 @@ SIGNATURES = {
     "uvl_status_str": ([_I32], ctypes.c_char_p),
     "uvl_device_check": ([], _I32),
     "uvl_build_workspace_bytes": ([_I64], _SZ),
+    "uvl_geom_bytes": ([_I32, _I32, _U32], _SZ),
     "uvl_build_geometry_image": ([_P, _P, _P, _SZ, _P], _I32),
     "uvl_create_layer": ([_P, _P], _I32),
     "uvl_depth_workspace_bytes": ([_I64], _SZ),
@@ -621,15 +622,25 @@ def numeric_pad_lasso(geom: GeometryImage, layer: NumericLayer, outline: Outline
 
 
 def layer_op(op: int, dst: Layer, a: Layer, b: Optional[Layer] = None, sel_a: int = 0, sel_b: int = 0,
-             out_label: int = 0, lut: Optional[torch.Tensor] = None, stream=None):
-    """lut: device uint16 tensor of 256 / 65536 entries (REMAP only)."""
+             out_label: int = 0, lut=None, stream=None):
+    """lut: host table of 256 / 65536 uint16 entries (REMAP only; the
+    library checks lut[0] == 0 and that every entry fits dst)."""
+    host = None
     if op == REMAP:
         need = 256 if a.dtype == U8 else 65536
-        if lut is None or lut.dtype != torch.uint16 or not lut.is_cuda or lut.numel() < need:
-            raise ValueError(f"REMAP needs a device uint16 lut of {need} entries")
+        if lut is None:
+            raise ValueError(f"REMAP needs a host uint16 lut of {need} entries")
+        if isinstance(lut, torch.Tensor):
+            if lut.is_cuda:
+                raise ValueError("REMAP tables are host arrays")
+            lut = lut.numpy()
+        host = np.ascontiguousarray(lut, dtype=np.uint16).reshape(-1)
+        if host.size != need:
+            raise ValueError(f"REMAP needs a host uint16 lut of {need} entries")
     _check(_lib().uvl_layer_op(int(op), ctypes.byref(dst.c), ctypes.byref(a.c),
                                None if b is None else ctypes.byref(b.c), int(sel_a), int(sel_b),
-                               int(out_label), _ptr(lut), _stream(stream)), "uvl_layer_op")
+                               int(out_label), None if host is None else host.ctypes.data_as(ctypes.c_void_p),
+                               _stream(stream)), "uvl_layer_op")
 
 
 def nbins(layers: Sequence[Layer]) -> int:

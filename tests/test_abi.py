@@ -127,6 +127,56 @@ def test_layer_op_and_area_validation(uvl):
     assert L.uvl_area_query(ctypes.byref(g), arr, 1, None, None, s) == -1
 
 
+def test_remap_tables_are_checked_on_the_host(uvl):
+    """REMAP tables: the null key must map to itself (UVL_E_INVAL) and every
+    entry must fit the destination's dtype (UVL_E_DTYPE); both are refused
+    before anything is enqueued (fake device addresses, no GPU)."""
+    L = uvl.lib()
+    a8, a16, d8, d16 = _layer(uvl), _layer(uvl, dt=2), _layer(uvl), _layer(uvl, dt=2)
+    s = None
+
+    def remap(dst, a, lut):
+        return L.uvl_layer_op(3, ctypes.byref(dst), ctypes.byref(a), None, 0, 0, 0,
+                              lut.ctypes.data_as(ctypes.c_void_p), s)
+
+    for a, n in ((a8, 256), (a16, 65536)):
+        for dst in (d8, d16):
+            lut = np.arange(n, dtype=np.uint16) % 200
+            lut[0] = 7
+            assert remap(dst, a, lut) == -1
+        lut = np.zeros(n, np.uint16)
+        lut[n - 1] = 256                    # does not fit a u8 destination
+        assert remap(d8, a, lut) == -3
+        lut[n - 1] = 65535
+        assert remap(d8, a, lut) == -3
+    lut = np.zeros(256, np.uint16)
+    lut[255] = 256
+    assert remap(d8, a8, lut) == -3
+
+
+def test_geom_bytes(uvl):
+    """uvl_geom_bytes: each 4-byte plane rounded to 256 bytes, optional
+    planes by flag, the tile bounds of ceil(W/32) x ceil(H/32) tiles."""
+    L = uvl.lib()
+
+    def plane(w, h):
+        return -(-w * h * 4 // 256) * 256
+
+    for w, h in ((1, 1), (37, 53), (512, 512), (8192, 8192), (32768, 3)):
+        tiles = -(-w // 32) * -(-h // 32)
+        box = -(-tiles * 24 // 256) * 256
+        assert L.uvl_geom_bytes(w, h, 0) == 5 * plane(w, h)
+        assert L.uvl_geom_bytes(w, h, 1) == 8 * plane(w, h)
+        assert L.uvl_geom_bytes(w, h, 2) == 7 * plane(w, h)
+        assert L.uvl_geom_bytes(w, h, 7) == 10 * plane(w, h) + box
+    assert L.uvl_geom_bytes(0, 5, 0) == 0
+    assert L.uvl_geom_bytes(5, 32769, 0) == 0
+    assert L.uvl_geom_bytes(5, 5, 64) == 0
+    # the binding's geometry image allocates what the library states (CPU tensors)
+    g = uvl.GeometryImage(300, 173, device="cpu")
+    assert g.nbytes() <= L.uvl_geom_bytes(300, 173, 7) < g.nbytes() + 256
+
+
 def test_build_and_depth_validation(uvl):
     L = uvl.lib()
     m = uvl.CMesh(FAKE, None, FAKE, FAKE, 10, 4)

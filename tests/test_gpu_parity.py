@@ -414,11 +414,52 @@ def test_layer_ops_mixed_dtypes_ragged_alias(gpu, orc):
                 lut[0] = 0
                 A = _dev_layer(gpu, vals[da], W, H, da)
                 D = gpu.Layer(W, H, dd)
-                gpu.layer_op(gpu.REMAP, D, A, None, lut=torch.from_numpy(lut).cuda())
+                gpu.layer_op(gpu.REMAP, D, A, None, lut=lut)
                 ref = np.zeros(n, np.uint8 if dd == gpu.U8 else np.uint16)
                 orc.layer_op(orc.REMAP, ref, vals[da], None, lut=lut)
                 assert np.array_equal(D.numpy(), ref), (W, H, da, dd)
 
+
+
+def test_remap_table_ring_reuse(gpu, orc):
+    """More 65536-entry REMAP tables in flight than the library's staging
+    ring has slots (16): each call's table is the one applied, whether its
+    slot is fresh or reused after waiting, with no synchronisation between
+    the calls; u8 tables (passed by value) interleaved."""
+    W, H = 300, 7
+    n = W * H
+    rng = np.random.default_rng(77)
+    src16 = rng.integers(0, 65536, n).astype(np.uint16)
+    src8 = rng.integers(0, 256, n).astype(np.uint8)
+    A16 = _dev_layer(gpu, src16, W, H, gpu.U16)
+    A8 = _dev_layer(gpu, src8, W, H, gpu.U8)
+    outs = []
+    for k in range(40):
+        if k % 5 == 4:
+            lut = rng.integers(0, 256, 256).astype(np.uint16)
+            lut[0] = 0
+            D, src = gpu.Layer(W, H, gpu.U8), src8
+            gpu.layer_op(gpu.REMAP, D, A8, None, lut=lut)
+        else:
+            lut = rng.integers(0, 65536 if k % 2 else 256, 65536).astype(np.uint16)
+            lut[0] = 0
+            D, src = gpu.Layer(W, H, gpu.U16 if k % 2 else gpu.U8), src16
+            gpu.layer_op(gpu.REMAP, D, A16, None, lut=lut)
+        lut[:] = 0                # the caller may reuse its table at once
+        outs.append((D, src))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(77)
+    rng.integers(0, 65536, n)
+    rng.integers(0, 256, n)
+    for k, (D, src) in enumerate(outs):
+        if k % 5 == 4:
+            lut = rng.integers(0, 256, 256).astype(np.uint16)
+        else:
+            lut = rng.integers(0, 65536 if k % 2 else 256, 65536).astype(np.uint16)
+        lut[0] = 0
+        ref = np.zeros(n, np.uint16 if D.dtype == gpu.U16 else np.uint8)
+        orc.layer_op(orc.REMAP, ref, src, None, lut=lut)
+        assert np.array_equal(D.numpy(), ref), k
 
 # ---------------------------------------------------------------------------
 # area
