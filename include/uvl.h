@@ -44,7 +44,9 @@ typedef enum {
     UVL_E_DTYPE = -3,        /* unknown layer dtype or label does not fit     */
     UVL_E_NOMEM = -4,        /* workspace too small                           */
     UVL_E_DEVICE = -5,       /* a HIP call or kernel launch failed            */
-    UVL_E_UNSUPPORTED = -6   /* the current device is not gfx950              */
+    UVL_E_UNSUPPORTED = -6,  /* the current device is not gfx950              */
+    UVL_E_RANGE = -7         /* texel areas span too wide a range for one
+                                uint32 word per texel: give area_w_hi         */
 } uvl_status;
 
 /* Layer data types (§4.2: the data texture holds 8/16/32-bit integers or
@@ -85,11 +87,22 @@ typedef struct {
  *   nrm_x/y/z     unit normal, 0 where uncovered (all three NULL: skipped)
  *   bary1/2       barycentrics of vertices 1 and 2 (both NULL: skipped)
  *   area_w        surface area of the texel in units of area_scale, 0 where
- *                 uncovered (uint32 fixed point)
+ *                 uncovered (uint32 fixed point; the low word when
+ *                 area_w_hi is given)
+ *   area_w_hi     optional (NULL: one word per texel): the high words, the
+ *                 texel's area then being (area_w_hi * 2^32 + area_w) *
+ *                 area_scale
  * area_scale and area_abs_err are written by uvl_build_geometry_image: a
- * texel's area is area_w * area_scale, off from the exact fp64 weight by at
- * most area_abs_err = area_scale / 2, so a label's area over k texels is
- * within k * area_abs_err.
+ * texel's area is area_w * area_scale (or the two-word form), off from the
+ * exact fp64 weight by at most area_abs_err = area_scale / 2, so a label's
+ * area over k texels is within k * area_abs_err.  The scale is a power of
+ * two chosen from the largest texel area w_max (area_abs_err <= 2^-31 w_max
+ * with one word, 2^-63 w_max with two), so a texel of area at least 2^-11
+ * w_max (one word) or 2^-43 w_max (two words) is within 2^-20 (< 1e-6)
+ * relative.  The one-word build fails with UVL_E_RANGE when some texel's
+ * area lies in [2^-43, 2^-11) w_max (two words would hold it to 2^-20);
+ * texels lighter than 2^-43 w_max (triangles of numerically zero 3D area)
+ * keep the absolute bound only.
  *   tile_box      optional (NULL: skipped): for each tile of UVL_TILE_SIDE x
  *                 UVL_TILE_SIDE texels (tile (tx, ty) holds texels i in
  *                 [32 tx, 32 tx + 32), j in [32 ty, 32 ty + 32); tiles are
@@ -109,6 +122,7 @@ typedef struct {
     double area_scale;      /* out: texel area = area_w * area_scale            */
     double area_abs_err;    /* out: bound on the rounding of one texel's area   */
     float *tile_box;        /* optional per-tile position bounds (see above)    */
+    uint32_t *area_w_hi;    /* optional high words of the texel areas           */
 } uvl_geom;
 
 /* A layer's data texture: width*height values of `dtype`, device memory,
@@ -124,6 +138,7 @@ typedef struct {
 #define UVL_GEOM_NRM      1u   /* nrm_x, nrm_y, nrm_z */
 #define UVL_GEOM_BARY     2u   /* bary1, bary2 */
 #define UVL_GEOM_TILE_BOX 4u   /* tile_box */
+#define UVL_GEOM_AREA_HI  8u   /* area_w_hi */
 
 /* Device bytes of the planes of a width x height geometry image: each plane
  * of N = width*height elements rounded up to a multiple of 256 bytes (so
@@ -151,14 +166,18 @@ size_t uvl_build_workspace_bytes(int64_t nt);
  * zero-area triangles cover nothing), its barycentrics b_k = e_k/|E| from the
  * exact integer edge functions, position b0 P0 + b1 P1 + b2 P2 summed left to
  * right in fp64 and rounded to fp32, unit normal, and area weight
- * 131072 * A3 / |E| (A3 the triangle's 3D area) quantised to uint32 with a
- * power-of-two scale.
+ * 131072 * A3 / |E| (A3 the triangle's 3D area) quantised to one uint32
+ * word (area_w_hi NULL) or two (low and high words) with a power-of-two
+ * scale.
  * ws: device workspace of uvl_build_workspace_bytes(nt) bytes.
  * SYNCHRONOUS: waits for `stream` to read back area_scale.
  * mesh->tri may be NULL when nt == 0 (every texel is then uncovered).
  * Errors: UVL_E_INVAL for null planes, width/height outside [1, 32768],
  * a texture coordinate outside [-4, 4] or a vertex index outside [0, nv)
- * (the planes are then undefined); UVL_E_NOMEM if ws_bytes is too small. */
+ * (the planes are then undefined); UVL_E_NOMEM if ws_bytes is too small;
+ * UVL_E_RANGE (one word only) if some texel's area lies in [2^-43, 2^-11)
+ * of the largest: every plane is written, but such texels may be off by
+ * more than 2^-20 relative (build again with area_w_hi). */
 int32_t uvl_build_geometry_image(const uvl_mesh *mesh, uvl_geom *geom, void *ws, size_t ws_bytes,
                                  void *stream);
 
@@ -228,13 +247,24 @@ int32_t uvl_layer_op(int32_t op, const uvl_layer *dst, const uvl_layer *a, const
  * represents; summed over the texels holding a label it gives the labelled
  * area).  For each of nlayers layers (1..32, same size as geom): bins[l] =
  * sum of area_w over covered texels with value l, exact uint64; layer k's
- * 256 (u8) or 65536 (u16) bins follow layer k-1's in bins_dev (device).
- * If areas_host is non-NULL the call is SYNCHRONOUS and writes
- * areas_host[b] = bins[b] * area_scale (fp64, same layout); otherwise it is
- * asynchronous and the bins stay on the device.
+ * 256 (u8) or 65536 (u16) bins follow layer k-1's in bins_dev (device,
+ * 8-byte aligned).  With two-word weights (geom->area_w_hi non-NULL) the
+ * sums of the low words come first, then as many sums of the high words in
+ * the same layout, and a bin's area is (high * 2^32 + low) * area_scale;
+ * uvl_area_bin_count gives the number of uint64 either way.  One pass reads
+ * each weight once for all the layers (two-word weights: once per 16 u8
+ * layers).  If areas_host is non-NULL the call is SYNCHRONOUS and writes
+ * the fp64 area of each bin there (one double per bin, the layers' bins in
+ * order); otherwise it is asynchronous and the bins stay on the device.
  * Errors: UVL_E_INVAL, UVL_E_SHAPE, UVL_E_DTYPE. */
 int32_t uvl_area_query(const uvl_geom *geom, const uvl_layer *layers, int32_t nlayers,
                        uint64_t *bins_dev, double *areas_host, void *stream);
+
+/* Number of uint64 bins_dev must hold for uvl_area_query on these layers:
+ * the layers' bins (256 per u8 layer, 65536 per u16 layer), twice that with
+ * two-word weights.  0 for null pointers, nlayers outside 1..32 or a dtype
+ * that is not u8/u16. */
+int64_t uvl_area_bin_count(const uvl_geom *geom, const uvl_layer *layers, int32_t nlayers);
 
 /* The paper's screen-space editing tool (§4.3.1): projective texture
  * mapping of the tool's shape texture through the camera, narrowed to the
@@ -342,12 +372,36 @@ int32_t uvl_numeric_tool(const uvl_geom *geom, const uvl_numeric *layer, const f
 int32_t uvl_numeric_select(const uvl_numeric *src, double lo, double hi, const uvl_layer *dst, uint32_t label,
                            void *stream);
 
+/* Operations between numeric layers (§4.2: numeric layers are for
+ * annotating and operating with quantitative information).  Per texel, a
+ * result validity r from the operands' mask bits va, vb:
+ *   UVL_NUM_AND: va && vb    UVL_NUM_OR: va || vb    UVL_NUM_XOR: va != vb
+ *   UVL_NUM_MIN, UVL_NUM_MAX, UVL_NUM_ADD: va && vb;
+ * where r holds dst's data become (AND / OR / XOR) a's value if va, else
+ * b's; (MIN) a if a <= b, else b; (MAX) a if a >= b, else b; (ADD) a + b
+ * rounded once to the dtype (integers exactly, binary32 by its own
+ * addition, binary16 from the exact sum), results beyond the dtype's range
+ * taking its extreme finite value; where r does not hold dst's data stay
+ * and its bit is cleared.  dst's mask bit = r.  All three layers have one
+ * dtype and one size; dst may be a or b (the same data and mask planes) or
+ * share no plane with them.  A NaN operand (edits never store one) leaves
+ * that texel's data unspecified.
+ * Errors: UVL_E_INVAL (op, pointers, partial aliasing), UVL_E_DTYPE
+ * (dtypes differ), UVL_E_SHAPE (sizes differ). */
+typedef enum { UVL_NUM_AND = 0, UVL_NUM_OR = 1, UVL_NUM_XOR = 2, UVL_NUM_MIN = 3, UVL_NUM_MAX = 4,
+               UVL_NUM_ADD = 5 } uvl_numeric_opcode;
+int32_t uvl_numeric_op(int32_t op, const uvl_numeric *dst, const uvl_numeric *a, const uvl_numeric *b,
+                       void *stream);
+
 /* One group of zonal statistics. */
 typedef struct {
     uint64_t count;     /* texels counted                                     */
     uint64_t area_w;    /* sum of their area_w (exact); area = area_w * area_scale */
     double wsum;        /* sum of area_w * value in fp64, in an unspecified order */
     double vmin, vmax;  /* extremes of the value (+inf / -inf when count is 0) */
+    uint64_t area_w_hi; /* two-word weights: sum of the high words (exact), the
+                           area being (area_w_hi * 2^32 + area_w) * area_scale
+                           and wsum summing (high * 2^32 + low) * value; else 0 */
 } uvl_numstat;
 
 /* Texture padding of a numeric layer after a numeric brush or lasso edit

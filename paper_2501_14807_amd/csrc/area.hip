@@ -2,221 +2,343 @@
 //
 // Table 1 of the paper reports the surface area one texel stands for; the
 // labelled area of a layer is the sum of those texel areas over the texels
-// holding the label.  The geometry image stores each texel's area as a
-// uint32 multiple of a power-of-two scale, so the sums are exact uint64
-// integers: independent of summation order, deterministic run to run, and
-// exactly additive (area(A or B) = area(A) + area(B) - area(A and B)).
+// holding the label.  The geometry image stores each texel's area as an
+// integer multiple of a power-of-two scale -- one uint32 word, or two
+// (low and high) when the texel areas span too wide a range for one -- so
+// the sums are exact uint64 integers: independent of summation order,
+// deterministic run to run, and exactly additive (area(A or B) = area(A) +
+// area(B) - area(A and B)).  With two words, the low and the high words are
+// summed into separate bins (each sum stays below 2^62), and the area is
+// (high sum * 2^32 + low sum) * area_scale.
 //
-// One pass reads each area weight once for up to kGroup layers.  The atlas is
-// cut into bands of 4096 columns; a workgroup owns one band over a range of
-// rows and walks it row by row; lane l takes columns [16 l, 16 l + 16) of the
-// band in every row (4 x 16-byte weight loads, one 16-byte u8 or two u16
-// label loads per layer when the width is a multiple of 16).  Every lane
-// keeps, per layer, its current label and the uint64 weight sum of its run of
-// that label, carried down the rows: labelled regions are spatially coherent,
-// so a run usually spans many rows and is added to a bin only when the lane's
-// label changes.  u8 layers add into 256 LDS bins (native LDS atomics);
-// u16 layers (65536 bins) add into an LDS hash table keyed by (layer,
-// label), open addressing with linear probing, falling back to the global
-// bin only if 16 probes find no slot.  Both are flushed to the global bins
-// once per workgroup, so global atomics stay few and spread out.
+// One pass reads every area weight from memory once for all the layers of
+// a query (up to 32).  A work unit is 4 rows x 1024 columns; a wave takes
+// units in turn, each lane holding 16 consecutive columns: it reads the
+// unit's weights once and keeps their per-row sums, then walks the layers,
+// loading each layer's 16 labels per row and adding runs of equal labels to
+// the workgroup's bins.  A row whose 16 labels are equal (the common case:
+// labelled regions are spatially coherent) is checked on the packed words
+// and adds its row sum; any other row reads its 16 weights again, from the
+// cache.  u8 layers add into 256
+// LDS bins each (native 64-bit LDS atomics); u16 layers (65536 bins) add
+// into an LDS hash table keyed by (layer, label), open addressing with
+// linear probing, falling back to the global bin only if 16 probes find no
+// slot.  The LDS bins go to the global bins once per workgroup.  A
+// workgroup is 16 waves with up to 88 KiB of LDS (gfx950 has 160 KiB per
+// CU), one workgroup per CU stride over the units.
 #include "uvl_internal.h"
 
 namespace uvl {
 namespace {
 
-constexpr int kPer = 16;
-constexpr int kGroup = 8;                 // layers per launch
-constexpr int kTexPerIter = kBlock * kPer;
+constexpr int kAreaBlock = 1024;          // 16 waves
+constexpr int kAreaWaves = kAreaBlock / 64;
+constexpr int kCols = 16;                 // columns per lane
+constexpr int kChunk = 64 * kCols;        // columns per wave unit
+constexpr int kMaxLayers = 32;
 constexpr int kHashBits = 11;
 constexpr int kHash = 1 << kHashBits;     // LDS hash slots for u16 labels
 constexpr uint32_t kEmptyKey = 0xffffffffu;
-
-struct U16Table {
-    uint32_t *key;                 // LDS [kHash]
-    unsigned long long *val;       // LDS [kHash]
-    unsigned long long *const *bins;   // global bins per layer (fallback)
-};
-
-// Add `sum` to label `label` of group layer `l` in the LDS hash table.
-__device__ __forceinline__ void table_add(const U16Table &T, int l, uint32_t label, unsigned long long sum) {
-    const uint32_t key = ((uint32_t)l << 16) | label;
-    uint32_t h = (key * 2654435761u) >> (32 - kHashBits);
-    for (int probe = 0; probe < 16; ++probe) {
-        const uint32_t prev = atomicCAS(T.key + h, kEmptyKey, key);
-        if (prev == kEmptyKey || prev == key) {
-            atomicAdd(T.val + h, sum);
-            return;
-        }
-        h = (h + 1) & (kHash - 1);
-    }
-    atomicAdd(T.bins[l] + label, sum);
-}
-
-// Bin sinks: direct LDS bins for u8 layers, the hash table for u16 layers.
-struct SinkU8 {
-    unsigned long long *bins;
-    __device__ __forceinline__ void add(uint32_t label, unsigned long long s) const { atomicAdd(bins + label, s); }
-};
-struct SinkU16 {
-    const U16Table *T;
-    int l;
-    __device__ __forceinline__ void add(uint32_t label, unsigned long long s) const { table_add(*T, l, label, s); }
-};
+constexpr uint32_t kNoLabel = 0xffffffffu;
 
 struct AreaArgs {
-    const void *data[kGroup];
-    unsigned long long *bins[kGroup];
-    int32_t dtype[kGroup];
-    int32_t row[kGroup];      // u8 layers: their LDS bin row (rank among the group's u8 layers)
+    const void *data[kMaxLayers];
+    unsigned long long *bins[kMaxLayers];       // global low-word (or only) bins per layer
+    unsigned long long *bins_hi[kMaxLayers];    // global high-word bins (two-word weights)
+    int32_t dtype[kMaxLayers];
+    int32_t row[kMaxLayers];                    // u8 layers: their LDS bin row
     int32_t nl;
 };
 
-__device__ __forceinline__ void label16_u8(const uint8_t *p, uint32_t v[kPer]) {
-    const uint4 q = *reinterpret_cast<const uint4 *>(p);
-    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) v[k] = (w[k >> 2] >> (8 * (k & 3))) & 0xffu;
-}
+// A weight: one word, or a low and a high word.
+template <bool kWide>
+struct Sum {
+    unsigned long long lo = 0, hi = 0;
+    __device__ __forceinline__ bool nonzero() const { return kWide ? (lo | hi) != 0 : lo != 0; }
+    __device__ __forceinline__ void add(const Sum &o) {
+        lo += o.lo;
+        if constexpr (kWide) hi += o.hi;
+    }
+};
 
-__device__ __forceinline__ void label16_u16(const uint16_t *p, uint32_t v[kPer]) {
-    const uint4 q0 = reinterpret_cast<const uint4 *>(p)[0];
-    const uint4 q1 = reinterpret_cast<const uint4 *>(p)[1];
-    const uint32_t w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) v[k] = (w[k >> 1] >> (16 * (k & 1))) & 0xffffu;
-}
+template <bool kWide>
+struct Bins {
+    unsigned long long *u8;                // LDS [rows][256] (two-word: low rows, then high rows)
+    int nu8;
+    uint32_t *key;                         // LDS [kHash]
+    unsigned long long *val;               // LDS [kHash] (two-word: [2][kHash])
+    const AreaArgs *A;
 
-// Feed 16 (label, weight) pairs into a lane's run; a finished run goes to
-// the sink.
-template <typename Sink>
-__device__ __forceinline__ void feed(const uint32_t lab[kPer], const uint32_t w[kPer], unsigned long long tot,
-                                     uint32_t &cur, unsigned long long &run, const Sink &bins) {
-    bool uni = true;
-#pragma unroll
-    for (int k = 1; k < kPer; ++k) uni = uni && lab[k] == lab[0];
-    if (uni) {
-        if (lab[0] != cur) {
-            if (run) bins.add(cur, run);
-            cur = lab[0];
-            run = 0;
+    __device__ __forceinline__ void add_u8(int row, uint32_t label, const Sum<kWide> &s) const {
+        atomicAdd(u8 + row * 256 + label, s.lo);
+        if constexpr (kWide) atomicAdd(u8 + (nu8 + row) * 256 + label, s.hi);
+    }
+    __device__ __forceinline__ void add_u16(int l, uint32_t label, const Sum<kWide> &s) const {
+        const uint32_t k = ((uint32_t)l << 16) | label;
+        uint32_t h = (k * 2654435761u) >> (32 - kHashBits);
+        for (int probe = 0; probe < 16; ++probe) {
+            const uint32_t prev = atomicCAS(key + h, kEmptyKey, k);
+            if (prev == kEmptyKey || prev == k) {
+                atomicAdd(val + h, s.lo);
+                if constexpr (kWide) atomicAdd(val + kHash + h, s.hi);
+                return;
+            }
+            h = (h + 1) & (kHash - 1);
         }
-        run += tot;
+        atomicAdd(A->bins[l] + label, s.lo);
+        if constexpr (kWide) atomicAdd(A->bins_hi[l] + label, s.hi);
+    }
+};
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint4 ld16(const void *p) {
+    const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+// Labels of one row of a lane: the packed words (u8: 4, u16: 8).
+template <typename T>
+struct RowLabels {
+    static constexpr int kWords = kCols * sizeof(T) / 4;
+    uint32_t w[kWords];
+
+    __device__ __forceinline__ void load_vec(const T *p) {
+#pragma unroll
+        for (int q = 0; q < kWords / 4; ++q) {
+            const uint4 v = ld16(p + q * (16 / sizeof(T)));
+            w[4 * q] = v.x; w[4 * q + 1] = v.y; w[4 * q + 2] = v.z; w[4 * q + 3] = v.w;
+        }
+    }
+    // ragged columns: labels past the row's end repeat the first one
+    __device__ __forceinline__ void load_tail(const T *p, int ncol) {
+        const uint32_t first = ncol > 0 ? (uint32_t)p[0] : 0u;
+        constexpr int kPerWord = 4 / sizeof(T);
+#pragma unroll
+        for (int i = 0; i < kWords; ++i) {
+            uint32_t x = 0;
+#pragma unroll
+            for (int b = 0; b < kPerWord; ++b) {
+                const int k = i * kPerWord + b;
+                x |= (k < ncol ? (uint32_t)p[k] : first) << (8 * sizeof(T) * b);
+            }
+            w[i] = x;
+        }
+    }
+    __device__ __forceinline__ uint32_t at(int k) const {
+        constexpr int kPerWord = 4 / sizeof(T);
+        return (w[k / kPerWord] >> (8 * sizeof(T) * (k % kPerWord))) & (sizeof(T) == 1 ? 0xffu : 0xffffu);
+    }
+    // all 16 labels equal: every word equal and made of one repeated label
+    __device__ __forceinline__ bool uniform() const {
+        bool eq = true;
+#pragma unroll
+        for (int i = 1; i < kWords; ++i) eq = eq && w[i] == w[0];
+        const uint32_t rep = sizeof(T) == 1 ? (w[0] & 0xffu) * 0x01010101u : (w[0] & 0xffffu) * 0x00010001u;
+        return eq && w[0] == rep;
+    }
+};
+
+// A unit's per-row weight sums.  The individual weights are not kept: a
+// row whose labels are not all equal reads its 16 weights again (cache
+// hits: the unit's weights were read just before).
+template <bool kWide, int kRows>
+struct UnitSums {
+    Sum<kWide> tot[kRows];
+};
+
+template <bool kWide>
+__device__ __forceinline__ void row_weights(const uint32_t *__restrict__ aw, const uint32_t *__restrict__ aw_hi,
+                                            int64_t t, int ncol, bool vec, uint32_t lo[kCols], uint32_t hi[kCols]) {
+    if (vec) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(aw + t + 4 * q);
+            lo[4 * q] = v.x; lo[4 * q + 1] = v.y; lo[4 * q + 2] = v.z; lo[4 * q + 3] = v.w;
+            if constexpr (kWide) {
+                const uint4 h = *reinterpret_cast<const uint4 *>(aw_hi + t + 4 * q);
+                hi[4 * q] = h.x; hi[4 * q + 1] = h.y; hi[4 * q + 2] = h.z; hi[4 * q + 3] = h.w;
+            }
+        }
     } else {
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            if (lab[k] != cur) {
-                if (run) bins.add(cur, run);
-                cur = lab[k];
-                run = 0;
-            }
-            run += w[k];
+        for (int k = 0; k < kCols; ++k) {
+            lo[k] = k < ncol ? aw[t + k] : 0u;
+            if constexpr (kWide) hi[k] = k < ncol ? aw_hi[t + k] : 0u;
         }
     }
 }
 
-// kU8 / kU16: the launch's group has u8 / u16 layers; LDS holds only the
-// tables the group needs (u8 bins 2 KiB per layer, the u16 hash 24 KiB), so a
-// one-layer query keeps many workgroups per CU.
-template <int kNU8, bool kU16>
-__global__ __launch_bounds__(kBlock) void k_area(const uint32_t *__restrict__ area_w, int W, int H, int rows_per,
-                                                  AreaArgs A) {
-    __shared__ unsigned long long s_bins[kNU8 > 0 ? kNU8 : 1][256];
-    __shared__ uint32_t s_key[kU16 ? kHash : 1];
-    __shared__ unsigned long long s_val[kU16 ? kHash : 1];
-    if (kNU8 > 0)
-        for (int k = threadIdx.x; k < kNU8 * 256; k += kBlock) (&s_bins[0][0])[k] = 0ull;
-    if (kU16)
-        for (int k = threadIdx.x; k < kHash; k += kBlock) {
-            s_key[k] = kEmptyKey;
-            s_val[k] = 0ull;
-        }
-    __syncthreads();
-    const U16Table table{s_key, s_val, A.bins};
-    uint32_t cur[kGroup];
-    unsigned long long run[kGroup];
+template <bool kWide, int kRows>
+__device__ __forceinline__ void load_sums(const uint32_t *__restrict__ aw, const uint32_t *__restrict__ aw_hi,
+                                          int64_t t0, int W, int nrows, int ncol, bool vec, UnitSums<kWide, kRows> &U) {
 #pragma unroll
-    for (int l = 0; l < kGroup; ++l) {
-        cur[l] = 0;
-        run[l] = 0;
-    }
-    const int col = (int)blockIdx.x * kTexPerIter + (int)threadIdx.x * kPer;   // first column of the lane
-    const int ncol = W - col < kPer ? (W - col > 0 ? W - col : 0) : kPer;       // columns it owns
-    const bool vec = (W % kPer) == 0 && ncol == kPer;                          // aligned 16-wide loads
-    const int r0 = (int)blockIdx.y * rows_per;
-    const int r1 = r0 + rows_per < H ? r0 + rows_per : H;
-    for (int r = r0; r < r1; ++r) {
-        const int64_t t0 = (int64_t)r * W + col;
-        uint32_t w[kPer];
-        if (vec) {
+    for (int r = 0; r < kRows; ++r) {
+        Sum<kWide> s;
+        if (r < nrows) {
+            uint32_t lo[kCols], hi[kCols];
+            row_weights<kWide>(aw, aw_hi, t0 + (int64_t)r * W, ncol, vec, lo, hi);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint4 v = reinterpret_cast<const uint4 *>(area_w + t0)[q];
-                w[4 * q] = v.x; w[4 * q + 1] = v.y; w[4 * q + 2] = v.z; w[4 * q + 3] = v.w;
+            for (int k = 0; k < kCols; ++k) {
+                s.lo += lo[k];
+                if constexpr (kWide) s.hi += hi[k];
             }
+        }
+        U.tot[r] = s;
+    }
+}
+
+// One layer over a unit: runs of equal labels go to the bins.
+template <typename T, bool kWide, int kRows, typename Add>
+__device__ __forceinline__ void layer_unit(const T *__restrict__ L, const uint32_t *__restrict__ aw,
+                                           const uint32_t *__restrict__ aw_hi, int64_t t0, int W, int nrows, int ncol,
+                                           bool vec, const UnitSums<kWide, kRows> &U, Add &&add) {
+    RowLabels<T> lab[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        if (r >= nrows) break;
+        const T *p = L + t0 + (int64_t)r * W;
+        if (vec) lab[r].load_vec(p);
+        else lab[r].load_tail(p, ncol);
+    }
+    uint32_t cur = kNoLabel;
+    Sum<kWide> run;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        if (r >= nrows) break;
+        if (lab[r].uniform()) {
+            const uint32_t l0 = lab[r].at(0);
+            if (l0 != cur) {
+                if (run.nonzero()) add(cur, run);
+                cur = l0;
+                run = Sum<kWide>();
+            }
+            run.add(U.tot[r]);
         } else {
+            uint32_t lo[kCols], hi[kCols];
+            row_weights<kWide>(aw, aw_hi, t0 + (int64_t)r * W, ncol, vec, lo, hi);
 #pragma unroll
-            for (int k = 0; k < kPer; ++k) w[k] = k < ncol ? area_w[t0 + k] : 0u;
-        }
-        unsigned long long tot = 0;
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) tot += w[k];
-#pragma unroll
-        for (int l = 0; l < kGroup; ++l) {
-            if (l >= A.nl) break;
-            uint32_t lab[kPer];
-            if (kNU8 > 0 && (!kU16 || A.dtype[l] == UVL_U8)) {
-                const uint8_t *L = static_cast<const uint8_t *>(A.data[l]);
-                if (vec) {
-                    label16_u8(L + t0, lab);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < kPer; ++k) lab[k] = k < ncol ? L[t0 + k] : cur[l];
+            for (int k = 0; k < kCols; ++k) {
+                const uint32_t lk = lab[r].at(k);
+                if (lk != cur) {
+                    if (run.nonzero()) add(cur, run);
+                    cur = lk;
+                    run = Sum<kWide>();
                 }
-                feed(lab, w, tot, cur[l], run[l], SinkU8{&s_bins[A.row[l]][0]});
-            } else if (kU16) {
-                const uint16_t *L = static_cast<const uint16_t *>(A.data[l]);
-                if (vec) {
-                    label16_u16(L + t0, lab);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < kPer; ++k) lab[k] = k < ncol ? L[t0 + k] : cur[l];
-                }
-                feed(lab, w, tot, cur[l], run[l], SinkU16{&table, l});
+                run.lo += lo[k];
+                if constexpr (kWide) run.hi += hi[k];
             }
         }
     }
-#pragma unroll
-    for (int l = 0; l < kGroup; ++l) {
-        if (l >= A.nl) break;
-        if (run[l]) {
-            if (kNU8 > 0 && (!kU16 || A.dtype[l] == UVL_U8)) atomicAdd(&s_bins[A.row[l]][cur[l]], run[l]);
-            else if (kU16) table_add(table, l, cur[l], run[l]);
+    if (run.nonzero()) add(cur, run);
+}
+
+// kNU8: LDS bin rows for u8 layers (>= the query's u8 layer count);
+// kU16: the query has u16 layers; kWide: two-word weights.
+template <int kNU8, bool kU16, bool kWide, int kRows>
+__global__ __launch_bounds__(kAreaBlock) void k_area(const uint32_t *__restrict__ aw,
+                                                      const uint32_t *__restrict__ aw_hi, int W, int H, AreaArgs A) {
+    constexpr int kBinRows = kNU8 > 0 ? (kWide ? 2 * kNU8 : kNU8) : 1;
+    __shared__ unsigned long long s_bins[kBinRows * 256];
+    __shared__ uint32_t s_key[kU16 ? kHash : 1];
+    __shared__ unsigned long long s_val[kU16 ? (kWide ? 2 * kHash : kHash) : 1];
+    if (kNU8 > 0)
+        for (int k = threadIdx.x; k < kBinRows * 256; k += kAreaBlock) s_bins[k] = 0ull;
+    if (kU16) {
+        for (int k = threadIdx.x; k < kHash; k += kAreaBlock) s_key[k] = kEmptyKey;
+        for (int k = threadIdx.x; k < (kWide ? 2 * kHash : kHash); k += kAreaBlock) s_val[k] = 0ull;
+    }
+    __syncthreads();
+    const Bins<kWide> bins{s_bins, kNU8, s_key, s_val, &A};
+    const int lane = threadIdx.x & 63;
+    const int chunks = (int)ceil_div(W, kChunk), rblocks = (int)ceil_div(H, kRows);
+    const int64_t units = (int64_t)chunks * rblocks;
+    for (int64_t u = (int64_t)blockIdx.x * kAreaWaves + (threadIdx.x >> 6); u < units;
+         u += (int64_t)gridDim.x * kAreaWaves) {
+        const int c = (int)(u % chunks), rb = (int)(u / chunks);
+        const int col = c * kChunk + lane * kCols;
+        const int ncol = W - col < kCols ? (W - col > 0 ? W - col : 0) : kCols;
+        const int row0 = rb * kRows;
+        const int nrows = H - row0 < kRows ? H - row0 : kRows;
+        const bool vec = (W % kCols) == 0 && ncol == kCols;
+        const int64_t t0 = (int64_t)row0 * W + col;
+        if (ncol == 0) continue;
+        UnitSums<kWide, kRows> U;
+        load_sums<kWide, kRows>(aw, aw_hi, t0, W, nrows, ncol, vec, U);
+        for (int l = 0; l < A.nl; ++l) {
+            if (A.dtype[l] == UVL_U8 && kNU8 > 0) {
+                const int row = A.row[l];
+                layer_unit<uint8_t, kWide, kRows>(static_cast<const uint8_t *>(A.data[l]), aw, aw_hi, t0, W, nrows,
+                                                  ncol, vec, U,
+                                                  [&](uint32_t lab, const Sum<kWide> &s) { bins.add_u8(row, lab, s); });
+            } else if (kU16) {
+                layer_unit<uint16_t, kWide, kRows>(static_cast<const uint16_t *>(A.data[l]), aw, aw_hi, t0, W, nrows,
+                                                   ncol, vec, U,
+                                                   [&](uint32_t lab, const Sum<kWide> &s) { bins.add_u16(l, lab, s); });
+            }
         }
     }
     __syncthreads();
     if (kNU8 > 0)
         for (int l = 0; l < A.nl; ++l) {
             if (A.dtype[l] != UVL_U8) continue;
-            const unsigned long long v = s_bins[A.row[l]][threadIdx.x];
-            if (v) atomicAdd(A.bins[l] + threadIdx.x, v);
+            const int row = A.row[l];
+            for (int k = threadIdx.x; k < 256; k += kAreaBlock) {
+                const unsigned long long v = s_bins[row * 256 + k];
+                if (v) atomicAdd(A.bins[l] + k, v);
+                if constexpr (kWide) {
+                    const unsigned long long h = s_bins[(kNU8 + row) * 256 + k];
+                    if (h) atomicAdd(A.bins_hi[l] + k, h);
+                }
+            }
         }
     if (kU16)
-        for (int k = threadIdx.x; k < kHash; k += kBlock) {
+        for (int k = threadIdx.x; k < kHash; k += kAreaBlock) {
             const uint32_t key = s_key[k];
-            if (key != kEmptyKey && s_val[k]) atomicAdd(A.bins[key >> 16] + (key & 0xffffu), s_val[k]);
+            if (key == kEmptyKey) continue;
+            const int l = (int)(key >> 16);
+            const uint32_t lab = key & 0xffffu;
+            if (s_val[k]) atomicAdd(A.bins[l] + lab, s_val[k]);
+            if (kWide && s_val[kHash + k]) atomicAdd(A.bins_hi[l] + lab, s_val[kHash + k]);
         }
 }
 
-// Launch one group with the kernel instance sized to its u8 layer count and
-// whether it has u16 layers.
-template <int kNU8>
-void launch_area(dim3 grid, hipStream_t s, const uint32_t *area_w, int W, int H, int rows_per, const AreaArgs &A,
-                 bool u16) {
-    if (u16)
-        hipLaunchKernelGGL((k_area<kNU8, true>), grid, dim3(kBlock), 0, s, area_w, W, H, rows_per, A);
-    else
-        hipLaunchKernelGGL((k_area<kNU8, false>), grid, dim3(kBlock), 0, s, area_w, W, H, rows_per, A);
+// Workgroups: one per CU at most, fewer when there are few units.
+template <int kNU8, bool kU16, bool kWide>
+void launch_area(hipStream_t s, const uint32_t *aw, const uint32_t *aw_hi, int W, int H, const AreaArgs &A) {
+    constexpr int kRows = 4;
+    const int64_t units = ceil_div(W, kChunk) * ceil_div(H, kRows);
+    int64_t g = ceil_div(units, kAreaWaves * 2);
+    if (g > 256) g = 256;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL((k_area<kNU8, kU16, kWide, kRows>), dim3((unsigned)g), dim3(kAreaBlock), 0, s, aw, aw_hi, W, H,
+                       A);
+}
+
+template <bool kWide>
+void launch_by_layers(hipStream_t s, const uint32_t *aw, const uint32_t *aw_hi, int W, int H, const AreaArgs &A,
+                      int nu8, bool u16) {
+    // bin rows rounded up to a power of two: fewer kernel instances
+    if (u16) {
+        if (nu8 == 0) launch_area<0, true, kWide>(s, aw, aw_hi, W, H, A);
+        else if (nu8 <= 1) launch_area<1, true, kWide>(s, aw, aw_hi, W, H, A);
+        else if (nu8 <= 4) launch_area<4, true, kWide>(s, aw, aw_hi, W, H, A);
+        else if (nu8 <= 8) launch_area<8, true, kWide>(s, aw, aw_hi, W, H, A);
+        else if (nu8 <= 16) launch_area<16, true, kWide>(s, aw, aw_hi, W, H, A);
+        else launch_area<(kWide ? 16 : 32), true, kWide>(s, aw, aw_hi, W, H, A);
+    } else {
+        if (nu8 <= 1) launch_area<1, false, kWide>(s, aw, aw_hi, W, H, A);
+        else if (nu8 <= 4) launch_area<4, false, kWide>(s, aw, aw_hi, W, H, A);
+        else if (nu8 <= 8) launch_area<8, false, kWide>(s, aw, aw_hi, W, H, A);
+        else if (nu8 <= 16) launch_area<16, false, kWide>(s, aw, aw_hi, W, H, A);
+        else launch_area<(kWide ? 16 : 32), false, kWide>(s, aw, aw_hi, W, H, A);
+    }
+}
+
+int64_t bins_of(const uvl_layer *layers, int32_t nlayers) {
+    int64_t n = 0;
+    for (int l = 0; l < nlayers; ++l) n += layers[l].dtype == UVL_U8 ? 256 : 65536;
+    return n;
 }
 
 }  // namespace
@@ -224,62 +346,73 @@ void launch_area(dim3 grid, hipStream_t s, const uint32_t *area_w, int W, int H,
 
 using namespace uvl;
 
+extern "C" int64_t uvl_area_bin_count(const uvl_geom *geom, const uvl_layer *layers, int32_t nlayers) {
+    if (!geom || !layers || nlayers < 1 || nlayers > kMaxLayers) return 0;
+    for (int l = 0; l < nlayers; ++l)
+        if (!dtype_ok(layers[l].dtype)) return 0;
+    return bins_of(layers, nlayers) * (geom->area_w_hi ? 2 : 1);
+}
+
 extern "C" int32_t uvl_area_query(const uvl_geom *geom, const uvl_layer *layers, int32_t nlayers,
                                   uint64_t *bins_dev, double *areas_host, void *stream) {
-    if (!geom || !layers || !bins_dev || nlayers < 1 || nlayers > 32) return UVL_E_INVAL;
+    if (!geom || !layers || !bins_dev || nlayers < 1 || nlayers > kMaxLayers) return UVL_E_INVAL;
     if (!geom->area_w || !aligned16(geom->area_w) || geom->width < 1 || geom->height < 1) return UVL_E_INVAL;
-    int64_t nbins = 0;
+    if (geom->area_w_hi && !aligned16(geom->area_w_hi)) return UVL_E_INVAL;
+    if (reinterpret_cast<uintptr_t>(bins_dev) & 7) return UVL_E_INVAL;
     for (int l = 0; l < nlayers; ++l) {
         if (!layer_ok(&layers[l])) return UVL_E_INVAL;
         if (!dtype_ok(layers[l].dtype)) return UVL_E_DTYPE;
         if (layers[l].width != geom->width || layers[l].height != geom->height) return UVL_E_SHAPE;
-        nbins += layers[l].dtype == UVL_U8 ? 256 : 65536;
     }
     if (int32_t s = device_ok()) return s;
+    const bool wide = geom->area_w_hi != nullptr;
+    const int64_t nbins = bins_of(layers, nlayers);
     hipStream_t s = as_stream(stream);
-    fill_bytes(bins_dev, nbins * 8, s);
-    // grid: column bands x row groups, about 1024 workgroups in all
-    const int bands = (int)ceil_div(geom->width, kTexPerIter);
-    int groups = (int)ceil_div(1024, bands);
-    if (groups > geom->height) groups = geom->height;
-    const int rows_per = (int)ceil_div(geom->height, groups);
-    groups = (int)ceil_div(geom->height, rows_per);
+    unsigned long long *lo = reinterpret_cast<unsigned long long *>(bins_dev);
+    unsigned long long *hi = wide ? lo + nbins : nullptr;
+    fill_bytes(bins_dev, nbins * 8 * (wide ? 2 : 1), s);
+    const int W = geom->width, H = geom->height;
+    // one launch for all layers (two-word weights: up to 16 u8 layers per
+    // launch, to keep the bins within the workgroup's LDS)
     int64_t off = 0;
-    for (int l0 = 0; l0 < nlayers; l0 += kGroup) {
+    for (int l0 = 0; l0 < nlayers;) {
         AreaArgs A{};
-        A.nl = nlayers - l0 < kGroup ? nlayers - l0 : kGroup;
         int nu8 = 0;
         bool u16 = false;
-        for (int k = 0; k < A.nl; ++k) {
+        int k = 0;
+        for (; l0 + k < nlayers && k < kMaxLayers; ++k) {
             const uvl_layer &L = layers[l0 + k];
+            if (L.dtype == UVL_U8) {
+                if (wide && nu8 == 16) break;
+                A.row[k] = nu8++;
+            } else {
+                u16 = true;
+            }
             A.data[k] = L.data;
             A.dtype[k] = L.dtype;
-            A.bins[k] = reinterpret_cast<unsigned long long *>(bins_dev) + off;
+            A.bins[k] = lo + off;
+            A.bins_hi[k] = wide ? hi + off : nullptr;
             off += L.dtype == UVL_U8 ? 256 : 65536;
-            if (L.dtype == UVL_U8) A.row[k] = nu8++;
-            else u16 = true;
         }
-        const dim3 grid((unsigned)bands, (unsigned)groups);
-        const uint32_t *aw = geom->area_w;
-        const int W = geom->width, H = geom->height;
-        switch (nu8) {
-            case 0: launch_area<0>(grid, s, aw, W, H, rows_per, A, u16); break;
-            case 1: launch_area<1>(grid, s, aw, W, H, rows_per, A, u16); break;
-            case 2: launch_area<2>(grid, s, aw, W, H, rows_per, A, u16); break;
-            case 3:
-            case 4: launch_area<4>(grid, s, aw, W, H, rows_per, A, u16); break;
-            default: launch_area<kGroup>(grid, s, aw, W, H, rows_per, A, u16); break;
-        }
+        A.nl = k;
+        if (wide) launch_by_layers<true>(s, geom->area_w, geom->area_w_hi, W, H, A, nu8, u16);
+        else launch_by_layers<false>(s, geom->area_w, nullptr, W, H, A, nu8, u16);
+        l0 += k;
     }
     if (launch_status() != UVL_OK) return UVL_E_DEVICE;
     if (!areas_host) return UVL_OK;
     // bins -> fp64 on the host (synchronous form)
-    uint64_t *tmp = static_cast<uint64_t *>(malloc((size_t)nbins * 8));
+    const int64_t nwords = nbins * (wide ? 2 : 1);
+    uint64_t *tmp = static_cast<uint64_t *>(malloc((size_t)nwords * 8));
     if (!tmp) return UVL_E_NOMEM;
-    hipError_t e = hipMemcpyAsync(tmp, bins_dev, (size_t)nbins * 8, hipMemcpyDeviceToHost, s);
+    hipError_t e = hipMemcpyAsync(tmp, bins_dev, (size_t)nwords * 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess)
-        for (int64_t b = 0; b < nbins; ++b) areas_host[b] = (double)tmp[b] * geom->area_scale;
+        for (int64_t b = 0; b < nbins; ++b) {
+            // high sum * 2^32 + low sum, each below 2^62: exact in 128 bits
+            const unsigned __int128 v = wide ? ((unsigned __int128)tmp[nbins + b] << 32) + tmp[b] : tmp[b];
+            areas_host[b] = (double)v * geom->area_scale;
+        }
     free(tmp);
     return e == hipSuccess ? UVL_OK : UVL_E_DEVICE;
 }

@@ -78,6 +78,7 @@ extern "C" const char *uvl_status_str(int32_t status) {
         case UVL_E_NOMEM: return "workspace too small";
         case UVL_E_DEVICE: return "HIP error";
         case UVL_E_UNSUPPORTED: return "device is not gfx950";
+        case UVL_E_RANGE: return "texel areas span too wide a range: build with area_w_hi";
         default: return "unknown status";
     }
 }

@@ -37,7 +37,7 @@
 namespace uvl {
 
 // ---------------------------------------------------------------------------
-// Host-side value conversion.
+// Value conversion.
 
 namespace {
 
@@ -45,9 +45,9 @@ namespace {
 // formats' bit layouts (binary64: 11-bit exponent, bias 1023, 52 fraction
 // bits; binary16: 5-bit exponent, bias 15, 10 fraction bits, subnormals of
 // spacing 2^-24 below 2^-14).  Returns false if the result is infinite.
-bool f16_from_double(double v, uint16_t &out) {
-    uint64_t b;
-    memcpy(&b, &v, sizeof b);
+// Used on the host (value encoding) and on the device (binary16 sums).
+__host__ __device__ __forceinline__ bool f16_from_double(double v, uint16_t &out) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
     const uint16_t sign = (uint16_t)((b >> 48) & 0x8000u);
     const int ef = (int)((b >> 52) & 0x7ff);
     if (ef == 0x7ff) return false;
@@ -269,16 +269,18 @@ __global__ __launch_bounds__(kBlock) void k_select(const Store<DT> *__restrict__
     }
 }
 
-// One wave step's planes for a lane (statistics).
+// One wave step's planes for a lane (statistics).  wh: the high words of
+// two-word area weights.
+template <bool kWide>
 struct StepData {
-    uint32_t tr[kPer], w[kPer], v[kPer], lab[kPer], m;
+    uint32_t tr[kPer], w[kPer], wh[kWide ? kPer : 1], v[kPer], lab[kPer], m;
 };
 
-template <int32_t DT, typename R>
+template <int32_t DT, typename R, bool kWide>
 __device__ __forceinline__ void fetch_step(const int32_t *__restrict__ tri, const uint32_t *__restrict__ aw,
-                                           const Store<DT> *__restrict__ data, const uint32_t *__restrict__ mask,
-                                           const R *__restrict__ region, int64_t n, int64_t s, int lane,
-                                           StepData &d) {
+                                           const uint32_t *__restrict__ aw_hi, const Store<DT> *__restrict__ data,
+                                           const uint32_t *__restrict__ mask, const R *__restrict__ region, int64_t n,
+                                           int64_t s, int lane, StepData<kWide> &d) {
     constexpr bool kNoRegion = std::is_same<R, void>::value;
     d.m = 0;
     if (s + kWaveStep <= n) {
@@ -287,6 +289,7 @@ __device__ __forceinline__ void fetch_step(const int32_t *__restrict__ tri, cons
             const int64_t t = slot_base(s, lane, q);
             load4(reinterpret_cast<const uint32_t *>(tri), t, d.tr + 4 * q);
             load4(aw, t, d.w + 4 * q);
+            if constexpr (kWide) load4(aw_hi, t, d.wh + 4 * q);
             load4(data, t, d.v + 4 * q);
             if constexpr (!kNoRegion) load4(region, t, d.lab + 4 * q);
             d.m |= mask4(mask, t) << (4 * q);
@@ -297,6 +300,7 @@ __device__ __forceinline__ void fetch_step(const int32_t *__restrict__ tri, cons
             const int64_t t = slot_base(s, lane, q);
             load4_tail(reinterpret_cast<const uint32_t *>(tri), t, n, d.tr + 4 * q);
             load4_tail(aw, t, n, d.w + 4 * q);
+            if constexpr (kWide) load4_tail(aw_hi, t, n, d.wh + 4 * q);
             load4_tail(data, t, n, d.v + 4 * q);
             if constexpr (!kNoRegion) load4_tail(region, t, n, d.lab + 4 * q);
             if (t < n) d.m |= mask4(mask, t) << (4 * q);
@@ -311,7 +315,7 @@ __device__ __forceinline__ void fetch_step(const int32_t *__restrict__ tri, cons
 struct Bin {
     unsigned long long count, aw;
     double wsum;
-    unsigned long long kmin, kmax;
+    unsigned long long kmin, kmax, aw_hi;
 };
 static_assert(sizeof(Bin) == sizeof(uvl_numstat), "bins are finalised in place");
 
@@ -327,12 +331,12 @@ __device__ __forceinline__ double from_key(unsigned long long k) {
 
 struct Run {
     uint32_t label;
-    unsigned long long count, aw;
+    unsigned long long count, aw, aw_hi;
     double wsum, vmin, vmax;
 
     __device__ __forceinline__ void reset(uint32_t l) {
         label = l;
-        count = aw = 0;
+        count = aw = aw_hi = 0;
         wsum = 0.0;
         vmin = INFINITY;
         vmax = -INFINITY;
@@ -340,11 +344,13 @@ struct Run {
 };
 
 // Add totals to a bin: LDS (native LDS atomics) or global memory.
-template <bool kGlobal>
-__device__ __forceinline__ void add_to(Bin *b, unsigned long long count, unsigned long long aw, double wsum,
-                                       unsigned long long kmin, unsigned long long kmax) {
+template <bool kGlobal, bool kWide>
+__device__ __forceinline__ void add_to(Bin *b, unsigned long long count, unsigned long long aw,
+                                       unsigned long long aw_hi, double wsum, unsigned long long kmin,
+                                       unsigned long long kmax) {
     atomicAdd(&b->count, count);
     atomicAdd(&b->aw, aw);
+    if constexpr (kWide) atomicAdd(&b->aw_hi, aw_hi);
     if constexpr (kGlobal) unsafeAtomicAdd(&b->wsum, wsum);
     else atomicAdd(&b->wsum, wsum);
     atomicMin(&b->kmin, kmin);
@@ -369,7 +375,7 @@ __device__ __forceinline__ int hash_slot(uint32_t *tags, uint32_t label) {
 }
 
 __device__ __forceinline__ void bin_clear(Bin &b) {
-    b.count = b.aw = 0;
+    b.count = b.aw = b.aw_hi = 0;
     b.wsum = 0.0;
     b.kmin = ~0ull;
     b.kmax = 0;
@@ -390,6 +396,7 @@ __global__ void k_stats_final(Bin *bins, int nbins) {
     s.wsum = b.wsum;
     s.vmin = b.count ? from_key(b.kmin) : INFINITY;
     s.vmax = b.count ? from_key(b.kmax) : -INFINITY;
+    s.area_w_hi = b.aw_hi;
     reinterpret_cast<uvl_numstat *>(bins)[i] = s;
 }
 
@@ -397,8 +404,9 @@ __global__ void k_stats_final(Bin *bins, int nbins) {
 // Every workgroup accumulates its lanes' runs in LDS -- one bin, 256 bins
 // indexed by a u8 label, or kHashSlots tagged slots for u16 labels -- and
 // adds its non-empty bins to the global bins once at the end.
-template <int32_t DT, typename R>
+template <int32_t DT, typename R, bool kWide>
 __global__ __launch_bounds__(kBlock) void k_stats(const int32_t *__restrict__ tri, const uint32_t *__restrict__ aw,
+                                                  const uint32_t *__restrict__ aw_hi,
                                                   const Store<DT> *__restrict__ data,
                                                   const uint32_t *__restrict__ mask, const R *__restrict__ region,
                                                   int64_t n, Bin *__restrict__ bins) {
@@ -417,9 +425,10 @@ __global__ __launch_bounds__(kBlock) void k_stats(const int32_t *__restrict__ tr
         int slot = kNoRegion ? 0 : (int)r.label;
         if constexpr (kHash) slot = hash_slot(tags, r.label);
         if (slot >= 0)
-            add_to<false>(lds + slot, r.count, r.aw, r.wsum, order_key(r.vmin), order_key(r.vmax));
+            add_to<false, kWide>(lds + slot, r.count, r.aw, r.aw_hi, r.wsum, order_key(r.vmin), order_key(r.vmax));
         else
-            add_to<true>(bins + r.label, r.count, r.aw, r.wsum, order_key(r.vmin), order_key(r.vmax));
+            add_to<true, kWide>(bins + r.label, r.count, r.aw, r.aw_hi, r.wsum, order_key(r.vmin),
+                                order_key(r.vmax));
     };
     Run run;
     run.reset(0);
@@ -427,11 +436,11 @@ __global__ __launch_bounds__(kBlock) void k_stats(const int32_t *__restrict__ tr
     const int64_t stride = (int64_t)gridDim.x * kWaves * kWaveStep;
     int64_t s = ((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * kWaveStep;
     // the next step's loads are issued before this step is processed
-    StepData cur, nxt;
-    if (s < n) fetch_step<DT>(tri, aw, data, mask, region, n, s, lane, cur);
+    StepData<kWide> cur, nxt;
+    if (s < n) fetch_step<DT, R, kWide>(tri, aw, aw_hi, data, mask, region, n, s, lane, cur);
     for (; s < n; s += stride) {
         const bool more = s + stride < n;
-        if (more) fetch_step<DT>(tri, aw, data, mask, region, n, s + stride, lane, nxt);
+        if (more) fetch_step<DT, R, kWide>(tri, aw, aw_hi, data, mask, region, n, s + stride, lane, nxt);
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             if ((int32_t)cur.tr[k] < 0 || !((cur.m >> k) & 1u)) continue;
@@ -443,7 +452,12 @@ __global__ __launch_bounds__(kBlock) void k_stats(const int32_t *__restrict__ tr
             const double x = decode<DT>(cur.v[k]);
             run.count += 1;
             run.aw += cur.w[k];
-            run.wsum += (double)cur.w[k] * x;
+            double wk = (double)cur.w[k];
+            if constexpr (kWide) {
+                run.aw_hi += cur.wh[k];
+                wk += (double)cur.wh[k] * 4294967296.0;   // high * 2^32 + low, rounded once
+            }
+            run.wsum += wk * x;
             run.vmin = fmin(run.vmin, x);
             run.vmax = fmax(run.vmax, x);
         }
@@ -455,7 +469,159 @@ __global__ __launch_bounds__(kBlock) void k_stats(const int32_t *__restrict__ tr
         const Bin &b = lds[i];
         if (b.count == 0) continue;
         const uint32_t label = kHash ? tags[i] : (uint32_t)i;
-        add_to<true>(bins + label, b.count, b.aw, b.wsum, b.kmin, b.kmax);
+        add_to<true, kWide>(bins + label, b.count, b.aw, b.aw_hi, b.wsum, b.kmin, b.kmax);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Operations between numeric layers: per texel a result validity from the
+// operands' mask bits and, where it holds, a value (the operand that is
+// valid for the mask operations, the smaller / larger for MIN / MAX, the
+// saturating sum for ADD); elsewhere the data stay and the bit is cleared.
+// A wave step covers 1024 texels; lane l takes texels 256 q + 4 l .. +3
+// (q < 4) so that each plane load is one contiguous block per wave, and the
+// 8 lanes that share a 32-texel mask word merge their bits with three
+// shuffles before one of them writes the word.
+
+constexpr int kNumAnd = 0, kNumOr = 1, kNumXor = 2, kNumMin = 3, kNumMax = 4, kNumAdd = 5;
+
+template <int32_t DT>
+__device__ __forceinline__ uint32_t add_sat(uint32_t xa, uint32_t xb) {
+    if constexpr (DT == UVL_U8 || DT == UVL_U16) {
+        const uint32_t sum = xa + xb, top = DT == UVL_U8 ? 0xffu : 0xffffu;
+        return sum > top ? top : sum;
+    } else if constexpr (DT == UVL_I32) {
+        const long long sum = (long long)(int32_t)xa + (long long)(int32_t)xb;
+        return (uint32_t)(int32_t)(sum > 2147483647LL ? 2147483647LL : sum < -2147483648LL ? -2147483648LL : sum);
+    } else if constexpr (DT == UVL_F32) {
+        const float sum = __uint_as_float(xa) + __uint_as_float(xb);       // one IEEE rounding
+        return __float_as_uint(isinf(sum) ? copysignf(3.40282346638528859812e+38f, sum) : sum);
+    } else {
+        // binary16: the sum of two binary16 values is exact in fp64, then one
+        // rounding to binary16; beyond the finite range the largest value
+        const double sum = decode<UVL_F16>(xa) + decode<UVL_F16>(xb);
+        uint16_t h;
+        if (f16_from_double(sum, h)) return h;
+        return sum < 0.0 ? 0xfbffu : 0x7bffu;
+    }
+}
+
+template <int32_t DT, int OP>
+__device__ __forceinline__ bool num_valid(bool va, bool vb) {
+    return OP == kNumOr ? (va || vb) : OP == kNumXor ? (va != vb) : (va && vb);
+}
+
+template <int32_t DT, int OP>
+__device__ __forceinline__ uint32_t num_value(uint32_t xa, uint32_t xb, bool va) {
+    if constexpr (OP == kNumMin) return decode<DT>(xa) <= decode<DT>(xb) ? xa : xb;
+    else if constexpr (OP == kNumMax) return decode<DT>(xa) >= decode<DT>(xb) ? xa : xb;
+    else if constexpr (OP == kNumAdd) return add_sat<DT>(xa, xb);
+    else return va ? xa : xb;
+}
+
+template <typename T>
+__device__ __forceinline__ void store4(T *__restrict__ p, int64_t t, const uint32_t *in) {
+    if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<uint4 *>(p + t) = make_uint4(in[0], in[1], in[2], in[3]);
+    } else if constexpr (sizeof(T) == 2) {
+        *reinterpret_cast<uint2 *>(p + t) = make_uint2(in[0] | (in[1] << 16), in[2] | (in[3] << 16));
+    } else {
+        *reinterpret_cast<uint32_t *>(p + t) = in[0] | (in[1] << 8) | (in[2] << 16) | (in[3] << 24);
+    }
+}
+
+// ALIAS: 0 dst is its own layer, 1 dst is a, 2 dst is b (then a texel whose
+// result is not valid keeps that operand's data, already in registers).
+template <int32_t DT, int OP, int ALIAS>
+__global__ __launch_bounds__(kBlock) void k_numop(Store<DT> *dst, uint32_t *dmask, const Store<DT> *a,
+                                                  const uint32_t *amask, const Store<DT> *b,
+                                                  const uint32_t *bmask, int64_t n) {
+    const int lane = threadIdx.x & 63;
+    const int64_t s = ((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * kWaveStep;
+    if (s >= n) return;                                     // whole waves leave together
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t t = slot_base(s, lane, q);
+        uint32_t r4 = 0;
+        if (t + 4 <= n) {
+            uint32_t xa[4], xb[4], out[4];
+            load4(a, t, xa);
+            load4(b, t, xb);
+            const uint32_t ma = mask4(amask, t), mb = mask4(bmask, t);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool va = (ma >> j) & 1u, vb = (mb >> j) & 1u;
+                const bool r = num_valid<DT, OP>(va, vb);
+                r4 |= (uint32_t)r << j;
+                out[j] = num_value<DT, OP>(xa[j], xb[j], va);
+            }
+            if (r4 != 0xfu) {
+                uint32_t old[4];
+                if constexpr (ALIAS == 1) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) old[j] = xa[j];
+                } else if constexpr (ALIAS == 2) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) old[j] = xb[j];
+                } else {
+                    load4(dst, t, old);
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (!((r4 >> j) & 1u)) out[j] = old[j];
+            }
+            store4(dst, t, out);
+        } else if (t < n) {
+            const uint32_t ma = mask4(amask, t), mb = mask4(bmask, t);
+            for (int j = 0; j < 4 && t + j < n; ++j) {
+                const bool va = (ma >> j) & 1u, vb = (mb >> j) & 1u;
+                if (num_valid<DT, OP>(va, vb)) {
+                    r4 |= 1u << j;
+                    dst[t + j] = (Store<DT>)num_value<DT, OP>(a[t + j], b[t + j], va);
+                }
+            }
+        }
+        // the 8 lanes of a mask word merge their 4-bit pieces
+        uint32_t word = r4 << (t & 31);
+        word |= __shfl_xor(word, 1);
+        word |= __shfl_xor(word, 2);
+        word |= __shfl_xor(word, 4);
+        const int64_t wi = t >> 5;
+        if ((lane & 7) == 0 && wi * 32 < n) {
+            const int64_t left = n - wi * 32;               // texels in this word
+            if (left < 32) {
+                const uint32_t low = (1u << left) - 1u;     // bits past the last texel stay
+                word = (word & low) | (dmask[wi] & ~low);
+            }
+            dmask[wi] = word;
+        }
+    }
+}
+
+template <int32_t DT, int OP>
+void launch_numop_alias(const uvl_numeric *d, const uvl_numeric *a, const uvl_numeric *b, int alias, hipStream_t s) {
+    const int64_t n = (int64_t)d->width * d->height;
+    const dim3 grid((unsigned)ceil_div(n, (int64_t)kWaves * kWaveStep));
+    Store<DT> *D = static_cast<Store<DT> *>(d->data);
+    const Store<DT> *A = static_cast<const Store<DT> *>(a->data), *B = static_cast<const Store<DT> *>(b->data);
+    if (alias == 1)
+        hipLaunchKernelGGL((k_numop<DT, OP, 1>), grid, dim3(kBlock), 0, s, D, d->mask, A, a->mask, B, b->mask, n);
+    else if (alias == 2)
+        hipLaunchKernelGGL((k_numop<DT, OP, 2>), grid, dim3(kBlock), 0, s, D, d->mask, A, a->mask, B, b->mask, n);
+    else
+        hipLaunchKernelGGL((k_numop<DT, OP, 0>), grid, dim3(kBlock), 0, s, D, d->mask, A, a->mask, B, b->mask, n);
+}
+
+template <int32_t DT>
+void launch_numop(int op, const uvl_numeric *d, const uvl_numeric *a, const uvl_numeric *b, int alias,
+                  hipStream_t s) {
+    switch (op) {
+    case kNumAnd: launch_numop_alias<DT, kNumAnd>(d, a, b, alias, s); break;
+    case kNumOr: launch_numop_alias<DT, kNumOr>(d, a, b, alias, s); break;
+    case kNumXor: launch_numop_alias<DT, kNumXor>(d, a, b, alias, s); break;
+    case kNumMin: launch_numop_alias<DT, kNumMin>(d, a, b, alias, s); break;
+    case kNumMax: launch_numop_alias<DT, kNumMax>(d, a, b, alias, s); break;
+    default: launch_numop_alias<DT, kNumAdd>(d, a, b, alias, s); break;
     }
 }
 
@@ -473,20 +639,27 @@ void launch_select(const uvl_numeric *src, double lo, double hi, const uvl_layer
                            static_cast<uint16_t *>(dst->data), label);
 }
 
-template <int32_t DT>
-void launch_stats(const uvl_geom *g, const uvl_numeric *l, const uvl_layer *region, Bin *bins, hipStream_t s) {
+template <int32_t DT, bool kWide>
+void launch_stats_w(const uvl_geom *g, const uvl_numeric *l, const uvl_layer *region, Bin *bins, hipStream_t s) {
     const int64_t n = (int64_t)l->width * l->height;
     const dim3 grid((unsigned)std::min<int64_t>(ceil_div(n, (int64_t)kWaves * kWaveStep), kMaxStatBlocks));
     const Store<DT> *data = static_cast<const Store<DT> *>(l->data);
+    const uint32_t *hi = g->area_w_hi;
     if (!region)
-        hipLaunchKernelGGL((k_stats<DT, void>), grid, dim3(kBlock), 0, s, g->tri_id, g->area_w, data, l->mask,
-                           (const void *)nullptr, n, bins);
+        hipLaunchKernelGGL((k_stats<DT, void, kWide>), grid, dim3(kBlock), 0, s, g->tri_id, g->area_w, hi, data,
+                           l->mask, (const void *)nullptr, n, bins);
     else if (region->dtype == UVL_U8)
-        hipLaunchKernelGGL((k_stats<DT, uint8_t>), grid, dim3(kBlock), 0, s, g->tri_id, g->area_w, data, l->mask,
-                           static_cast<const uint8_t *>(region->data), n, bins);
+        hipLaunchKernelGGL((k_stats<DT, uint8_t, kWide>), grid, dim3(kBlock), 0, s, g->tri_id, g->area_w, hi, data,
+                           l->mask, static_cast<const uint8_t *>(region->data), n, bins);
     else
-        hipLaunchKernelGGL((k_stats<DT, uint16_t>), grid, dim3(kBlock), 0, s, g->tri_id, g->area_w, data, l->mask,
-                           static_cast<const uint16_t *>(region->data), n, bins);
+        hipLaunchKernelGGL((k_stats<DT, uint16_t, kWide>), grid, dim3(kBlock), 0, s, g->tri_id, g->area_w, hi, data,
+                           l->mask, static_cast<const uint16_t *>(region->data), n, bins);
+}
+
+template <int32_t DT>
+void launch_stats(const uvl_geom *g, const uvl_numeric *l, const uvl_layer *region, Bin *bins, hipStream_t s) {
+    if (g->area_w_hi) launch_stats_w<DT, true>(g, l, region, bins, s);
+    else launch_stats_w<DT, false>(g, l, region, bins, s);
 }
 
 template <typename F>
@@ -528,6 +701,7 @@ extern "C" int32_t uvl_numeric_stats(const uvl_geom *geom, const uvl_numeric *la
                                      uvl_numstat *bins_dev, uvl_numstat *bins_host, void *stream) {
     if (!geom || !geom->tri_id || !geom->area_w || !aligned16(geom->tri_id) || !aligned16(geom->area_w))
         return UVL_E_INVAL;
+    if (geom->area_w_hi && !aligned16(geom->area_w_hi)) return UVL_E_INVAL;
     if (!numeric_ok(layer) || !bins_dev || (reinterpret_cast<uintptr_t>(bins_dev) & 7)) return UVL_E_INVAL;
     if (region && !layer_ok(region)) return UVL_E_INVAL;
     if (region && !dtype_ok(region->dtype)) return UVL_E_DTYPE;
@@ -547,4 +721,20 @@ extern "C" int32_t uvl_numeric_stats(const uvl_geom *geom, const uvl_numeric *la
             return UVL_E_DEVICE;
     }
     return UVL_OK;
+}
+
+extern "C" int32_t uvl_numeric_op(int32_t op, const uvl_numeric *dst, const uvl_numeric *a, const uvl_numeric *b,
+                                  void *stream) {
+    if (op < UVL_NUM_AND || op > UVL_NUM_ADD) return UVL_E_INVAL;
+    if (!numeric_ok(dst) || !numeric_ok(a) || !numeric_ok(b)) return UVL_E_INVAL;
+    if (a->dtype != dst->dtype || b->dtype != dst->dtype) return UVL_E_DTYPE;
+    if (a->width != dst->width || a->height != dst->height || b->width != dst->width || b->height != dst->height)
+        return UVL_E_SHAPE;
+    // dst is a or b entirely, or shares no plane with them
+    for (const uvl_numeric *x : {a, b})
+        if ((x->data == dst->data) != (x->mask == dst->mask)) return UVL_E_INVAL;
+    if (int32_t s = device_ok()) return s;
+    const int alias = dst->data == a->data ? 1 : dst->data == b->data ? 2 : 0;
+    by_dtype(dst->dtype, [&](auto dt) { launch_numop<decltype(dt)::value>(op, dst, a, b, alias, as_stream(stream)); });
+    return launch_status();
 }

@@ -37,9 +37,15 @@ struct Counters {
     unsigned int pad0;
     unsigned int pad1;
     unsigned long long max_w_bits;   // fp64 bits of the largest texel weight (positive)
+    unsigned long long min_w_bits;   // fp64 bits of the smallest weight two words hold to 2^-20
 };
 
 constexpr unsigned kFlagIndex = 1u, kFlagUV = 2u;
+
+// Largest ratio of texel weights for which one rounding onto the scale's
+// grid stays within 2^-20 relative: one word (largest weight in [2^30,
+// 2^31)) and two words (in [2^62, 2^63)).
+constexpr int kNarrowRatioLog2 = 11, kWideRatioLog2 = 43;
 
 struct Tri2 {
     long long X[3], Y[3];
@@ -200,6 +206,12 @@ __device__ __forceinline__ double wave_max(double x) {
     return x;
 }
 
+__device__ __forceinline__ double wave_min(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o));
+    return x;
+}
+
 struct GeomPlanes {
     int32_t *owner;
     float *px, *py, *pz, *nx, *ny, *nz, *b1, *b2;
@@ -278,18 +290,44 @@ __global__ __launch_bounds__(kBlock) void k_geom_attr(const float *__restrict__ 
     }
 }
 
+// One word per texel (hi == NULL): the largest weight maps into [2^30,
+// 2^31); two words: into [2^62, 2^63), low and high words.  Also the
+// smallest weight among the texels two words represent to 2^-20 (those of
+// at least 2^-kWideRatioLog2 of the largest; lighter ones come from
+// triangles of numerically zero 3D area and keep an absolute bound only):
+// the host compares it with the largest to tell whether one word suffices.
 __global__ __launch_bounds__(kBlock) void k_geom_quant(const int32_t *__restrict__ owner,
                                                        const double *__restrict__ w_tri,
-                                                       uint32_t *__restrict__ area_w, int64_t N,
-                                                       const Counters *__restrict__ ctr) {
+                                                       uint32_t *__restrict__ area_w, uint32_t *__restrict__ hi,
+                                                       int64_t N, Counters *__restrict__ ctr) {
     const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const double mx = __longlong_as_double((long long)ctr->max_w_bits);
     int ex;
     frexp(mx, &ex);
-    const int k = 31 - ex;     // largest weight maps into [2^30, 2^31]
+    double wmin = INFINITY;
     if (idx < N) {
         const int32_t t = owner[idx];
-        area_w[idx] = t >= 0 ? (unsigned)rint(ldexp(w_tri[t], k)) : 0u;
+        const double w = t >= 0 ? w_tri[t] : 0.0;
+        if (t >= 0 && w >= ldexp(mx, -kWideRatioLog2)) wmin = w;
+        if (!hi) {
+            area_w[idx] = (unsigned)rint(ldexp(w, 31 - ex));
+        } else {
+            const unsigned long long v = (unsigned long long)rint(ldexp(w, 63 - ex));
+            area_w[idx] = (uint32_t)v;
+            hi[idx] = (uint32_t)(v >> 32);
+        }
+    }
+    __shared__ double s_w[kBlock / 64];
+    wmin = wave_min(wmin);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = wmin;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 1; k < kBlock / 64; ++k) wmin = fmin(wmin, s_w[k]);
+        // positive doubles order as their bit patterns; the counter only falls
+        const unsigned long long b = (unsigned long long)__double_as_longlong(wmin);
+        if (wmin < INFINITY && b < __atomic_load_n(&ctr->min_w_bits, __ATOMIC_RELAXED))
+            atomicMin(&ctr->min_w_bits, b);
     }
 }
 
@@ -445,6 +483,7 @@ __global__ void k_counters_reset(Counters *ctr) {
         ctr->pad0 = 0;
         ctr->pad1 = 0;
         ctr->max_w_bits = 0;
+        ctr->min_w_bits = ~0ull;
     }
 }
 
@@ -457,12 +496,13 @@ using namespace uvl;
 
 extern "C" size_t uvl_geom_bytes(int32_t width, int32_t height, uint32_t flags) {
     if (width < 1 || height < 1 || width > kMaxSide || height > kMaxSide) return 0;
-    if (flags & ~(uint32_t)(UVL_GEOM_NRM | UVL_GEOM_BARY | UVL_GEOM_TILE_BOX)) return 0;
+    if (flags & ~(uint32_t)(UVL_GEOM_NRM | UVL_GEOM_BARY | UVL_GEOM_TILE_BOX | UVL_GEOM_AREA_HI)) return 0;
     const size_t n = (size_t)width * height;
     const size_t plane = align256(n * 4);        // every plane holds 4-byte elements
     size_t planes = 5;                            // tri_id, pos x/y/z, area_w
     if (flags & UVL_GEOM_NRM) planes += 3;
     if (flags & UVL_GEOM_BARY) planes += 2;
+    if (flags & UVL_GEOM_AREA_HI) planes += 1;
     size_t bytes = planes * plane;
     if (flags & UVL_GEOM_TILE_BOX)
         bytes += align256((size_t)ceil_div(width, UVL_TILE_SIDE) * ceil_div(height, UVL_TILE_SIDE) * 6 * sizeof(float));
@@ -508,7 +548,8 @@ extern "C" int32_t uvl_build_geometry_image(const uvl_mesh *mesh, uvl_geom *g, v
     const unsigned grid = (unsigned)ceil_div(N, kBlock);
     hipLaunchKernelGGL(k_geom_attr, dim3(grid), dim3(kBlock), 0, s, mesh->uv, mesh->pos, mesh->nrm, mesh->tri, W,
                        H, gp, w_tri, ctr);
-    hipLaunchKernelGGL(k_geom_quant, dim3(grid), dim3(kBlock), 0, s, g->tri_id, w_tri, g->area_w, N, ctr);
+    hipLaunchKernelGGL(k_geom_quant, dim3(grid), dim3(kBlock), 0, s, g->tri_id, w_tri, g->area_w, g->area_w_hi, N,
+                       ctr);
     if (g->tile_box)
         hipLaunchKernelGGL(k_tile_box, dim3((unsigned)ceil_div(W, UVL_TILE_SIDE), (unsigned)ceil_div(H, UVL_TILE_SIDE)),
                            dim3(kBlock), 0, s, g->pos_x, g->pos_y, g->pos_z, W, H, g->tile_box);
@@ -516,11 +557,17 @@ extern "C" int32_t uvl_build_geometry_image(const uvl_mesh *mesh, uvl_geom *g, v
     Counters host{};
     if (hipMemcpyAsync(&host, ctr, sizeof(Counters), hipMemcpyDeviceToHost, s) != hipSuccess) return UVL_E_DEVICE;
     if (hipStreamSynchronize(s) != hipSuccess) return UVL_E_DEVICE;
-    if (host.flags) return UVL_E_INVAL;
+    if (host.flags & (kFlagIndex | kFlagUV)) return UVL_E_INVAL;
+    const double mx = host.max_w_bits ? __builtin_bit_cast(double, host.max_w_bits) : 0.0;
     int ex = 0;
-    frexp(host.max_w_bits ? __builtin_bit_cast(double, host.max_w_bits) : 0.0, &ex);
-    g->area_scale = ldexp(1.0, ex - 31);
+    frexp(mx, &ex);
+    g->area_scale = ldexp(1.0, ex - (g->area_w_hi ? 63 : 31));
     g->area_abs_err = 0.5 * g->area_scale;
+    // one word holds every texel to 2^-20 if none lies below 2^-11 of the
+    // largest (among those two words would hold to 2^-20)
+    if (!g->area_w_hi && host.min_w_bits != ~0ull &&
+        __builtin_bit_cast(double, host.min_w_bits) < ldexp(mx, -kNarrowRatioLog2))
+        return UVL_E_RANGE;
     return UVL_OK;
 }
 
@@ -529,15 +576,21 @@ extern "C" size_t uvl_depth_workspace_bytes(int64_t nt) {
     return 256 + align256((size_t)nt * sizeof(unsigned));
 }
 
-extern "C" int32_t uvl_render_depth(const uvl_mesh *mesh, const float view_proj[16], float *depth, int32_t dw,
-                                    int32_t dh, void *ws, size_t ws_bytes, void *stream) {
-    if (!mesh || !view_proj || !depth || !ws) return UVL_E_INVAL;
+namespace uvl {
+namespace {
+
+int32_t depth_args_ok(const uvl_mesh *mesh, const float *view_proj, const float *depth, int32_t dw, int32_t dh) {
+    if (!mesh || !view_proj || !depth) return UVL_E_INVAL;
     if (mesh->nv < 0 || mesh->nt < 0 || mesh->nt > (1LL << 31) - 1) return UVL_E_INVAL;
     if (mesh->nt > 0 && (!mesh->pos || !mesh->tri)) return UVL_E_INVAL;
     if (dw < 1 || dh < 1 || dw > kMaxDepthSide || dh > kMaxDepthSide) return UVL_E_INVAL;
-    if (ws_bytes < uvl_depth_workspace_bytes(mesh->nt)) return UVL_E_NOMEM;
-    if (int32_t s = device_ok()) return s;
-    hipStream_t s = as_stream(stream);
+    return UVL_OK;
+}
+
+// The depth raster on a workspace of uvl_depth_workspace_bytes(nt) bytes:
+// counters in the first 256 bytes, then the queue of large triangles.
+int32_t launch_depth(const uvl_mesh *mesh, const float *view_proj, float *depth, int32_t dw, int32_t dh, void *ws,
+                     hipStream_t s) {
     Mat4 M;
     for (int k = 0; k < 16; ++k) M.m[k] = view_proj[k];
     Counters *ctr = static_cast<Counters *>(ws);
@@ -551,4 +604,16 @@ extern "C" int32_t uvl_render_depth(const uvl_mesh *mesh, const float view_proj[
                            reinterpret_cast<unsigned *>(depth), queue, ctr);
     }
     return launch_status();
+}
+
+}  // namespace
+}  // namespace uvl
+
+extern "C" int32_t uvl_render_depth(const uvl_mesh *mesh, const float view_proj[16], float *depth, int32_t dw,
+                                    int32_t dh, void *ws, size_t ws_bytes, void *stream) {
+    if (int32_t st = depth_args_ok(mesh, view_proj, depth, dw, dh)) return st;
+    if (!ws) return UVL_E_INVAL;
+    if (ws_bytes < uvl_depth_workspace_bytes(mesh->nt)) return UVL_E_NOMEM;
+    if (int32_t s = device_ok()) return s;
+    return launch_depth(mesh, view_proj, depth, dw, dh, ws, as_stream(stream));
 }

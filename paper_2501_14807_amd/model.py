@@ -113,7 +113,12 @@ class Model:
     # -- queries -------------------------------------------------------------
     def areas(self, sync: bool = True, layers: Optional[Sequence[int]] = None):
         ls = self.layers if layers is None else [self.layers[k] for k in layers]
-        bins = self.bins if layers is None else None
+        bins = None
+        if layers is None:
+            need = uvl.nbins(self.layers) * (2 if self.geom.wide else 1)
+            if self.bins.numel() < need:
+                self.bins = torch.empty(need, dtype=torch.int64, device=self.device)
+            bins = self.bins
         return uvl.area_query(self.geom, ls, bins=bins, sync=sync)
 
     def run(self, wl):

@@ -46,7 +46,7 @@ class CGeom(ctypes.Structure):
                 ("bary1", ctypes.c_void_p), ("bary2", ctypes.c_void_p),
                 ("area_w", ctypes.c_void_p),
                 ("area_scale", ctypes.c_double), ("area_abs_err", ctypes.c_double),
-                ("tile_box", ctypes.c_void_p)]
+                ("tile_box", ctypes.c_void_p), ("area_w_hi", ctypes.c_void_p)]
 
 TILE_SIDE = 32
 
@@ -63,7 +63,8 @@ class CNumeric(ctypes.Structure):
 
 # uvl_numstat
 NUMSTAT = np.dtype([("count", np.uint64), ("area_w", np.uint64), ("wsum", np.float64), ("vmin", np.float64),
-                    ("vmax", np.float64)])
+                    ("vmax", np.float64), ("area_w_hi", np.uint64)])
+E_RANGE = -7
 
 _L = None
 
@@ -84,6 +85,7 @@ SIGNATURES = {
     "uvl_edit_brush": ([_P, _P, _P, _F32, _U32, _P], _I32),
     "uvl_edit_lasso": ([_P, _P, _P, _P, _I32, _P, _I32, _I32, _F32, _U32, _P], _I32),
     "uvl_layer_op": ([_I32, _P, _P, _P, _U32, _U32, _U32, _P, _P], _I32),
+    "uvl_area_bin_count": ([_P, _P, _I32], _I64),
     "uvl_area_query": ([_P, _P, _I32, _P, _P, _P], _I32),
     "uvl_wave_workspace_bytes": ([_I32, _I32, _I64], _SZ),
     "uvl_wave_create": ([_I32, _I32, _I64, _P, _SZ, _P], _I32),
@@ -102,6 +104,7 @@ SIGNATURES = {
     "uvl_numeric_brush": ([_P, _P, _P, _F32, _I32, _F64, _P], _I32),
     "uvl_numeric_lasso": ([_P, _P, _P, _P, _I32, _P, _I32, _I32, _F32, _I32, _F64, _P], _I32),
     "uvl_numeric_tool": ([_P, _P, _P, _P, _P, _I32, _I32, _P, _I32, _I32, _F32, _I32, _F64, _P], _I32),
+    "uvl_numeric_op": ([_I32, _P, _P, _P, _P], _I32),
     "uvl_numeric_select": ([_P, _F64, _F64, _P, _U32, _P], _I32),
     "uvl_numeric_pad_brush": ([_P, _P, _P, _I64, _I32, _P, _F32, _I32, _F64, _P], _I32),
     "uvl_numeric_pad_lasso": ([_P, _P, _P, _I64, _I32, _P, _P, _I32, _P, _I32, _I32, _F32, _I32, _F64, _P], _I32),
@@ -221,7 +224,7 @@ class GeometryImage:
     """
 
     def __init__(self, width: int, height: int, normals: bool = True, bary: bool = True,
-                 device="cuda", tile_box: bool = True):
+                 device="cuda", tile_box: bool = True, wide: bool = False):
         self.width, self.height = int(width), int(height)
         n = self.width * self.height
         self.n = n
@@ -231,6 +234,8 @@ class GeometryImage:
         self.nrm = torch.empty((3, p), dtype=torch.float32, device=device) if normals else None
         self.bary = torch.empty((2, p), dtype=torch.float32, device=device) if bary else None
         self.area_w = torch.empty(p, dtype=torch.int32, device=device)   # uint32 bits
+        self.area_w_hi = None
+        self._device = device
         self.tiles_x = (self.width + TILE_SIDE - 1) // TILE_SIDE
         self.tiles_y = (self.height + TILE_SIDE - 1) // TILE_SIDE
         self.ntiles = self.tiles_x * self.tiles_y
@@ -245,9 +250,22 @@ class GeometryImage:
             self.c.bary1, self.c.bary2 = self.bary[0].data_ptr(), self.bary[1].data_ptr()
         self.c.area_w = self.area_w.data_ptr()
         self.c.tile_box = None if self.tile_box is None else self.tile_box.data_ptr()
+        if wide:
+            self.make_wide()
         self.c.area_scale = 0.0
         self.c.area_abs_err = 0.0
         self.addr = ctypes.addressof(self.c)     # the uvl_geom the library reads
+
+    def make_wide(self):
+        """Give the image a plane of high words: two-word texel areas (for
+        meshes whose texel areas span more than 2^11)."""
+        if self.area_w_hi is None:
+            self.area_w_hi = torch.empty(self.area_w.numel(), dtype=torch.int32, device=self._device)
+            self.c.area_w_hi = self.area_w_hi.data_ptr()
+
+    @property
+    def wide(self) -> bool:
+        return self.area_w_hi is not None
 
     @property
     def area_scale(self) -> float:
@@ -258,7 +276,7 @@ class GeometryImage:
         return float(self.c.area_abs_err)
 
     def nbytes(self) -> int:
-        ts = [self.tri_id, self.pos, self.nrm, self.bary, self.area_w, self.tile_box]
+        ts = [self.tri_id, self.pos, self.nrm, self.bary, self.area_w, self.tile_box, self.area_w_hi]
         return sum(t.numel() * t.element_size() for t in ts if t is not None)
 
     # host copies of the first n elements of each plane
@@ -266,6 +284,8 @@ class GeometryImage:
         n = self.n
         out = {"tri_id": self.tri_id[:n].cpu().numpy(), "pos": self.pos[:, :n].cpu().numpy(),
                "area_w": self.area_w[:n].cpu().numpy().view(np.uint32)}
+        if self.area_w_hi is not None:
+            out["area_w_hi"] = self.area_w_hi[:n].cpu().numpy().view(np.uint32)
         if self.nrm is not None:
             out["nrm"] = self.nrm[:, :n].cpu().numpy()
         if self.bary is not None:
@@ -349,8 +369,14 @@ def build_geometry_image(mesh: DeviceMesh, geom: GeometryImage, workspace: Optio
     need = L.uvl_build_workspace_bytes(mesh.nt)
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=mesh.pos.device)
-    _check(L.uvl_build_geometry_image(ctypes.byref(mesh.c), ctypes.byref(geom.c), _ptr(workspace),
-                                      workspace.numel(), _stream(stream)), "uvl_build_geometry_image")
+    st = L.uvl_build_geometry_image(ctypes.byref(mesh.c), ctypes.byref(geom.c), _ptr(workspace),
+                                    workspace.numel(), _stream(stream))
+    if st == E_RANGE and not geom.wide:
+        # texel areas too spread out for one word per texel: two words
+        geom.make_wide()
+        st = L.uvl_build_geometry_image(ctypes.byref(mesh.c), ctypes.byref(geom.c), _ptr(workspace),
+                                        workspace.numel(), _stream(stream))
+    _check(st, "uvl_build_geometry_image")
     return geom
 
 
@@ -491,6 +517,16 @@ def numeric_create(layer: NumericLayer, stream=None) -> NumericLayer:
     return layer
 
 
+NUM_AND, NUM_OR, NUM_XOR, NUM_MIN, NUM_MAX, NUM_ADD = 0, 1, 2, 3, 4, 5
+
+
+def numeric_op(op: int, dst: NumericLayer, a: NumericLayer, b: NumericLayer, stream=None) -> NumericLayer:
+    """dst = a op b texel by texel (uvl_numeric_op); dst may be a or b."""
+    _check(_lib().uvl_numeric_op(int(op), ctypes.byref(dst.c), ctypes.byref(a.c), ctypes.byref(b.c),
+                                 _stream(stream)), "uvl_numeric_op")
+    return dst
+
+
 def numeric_brush(geom: GeometryImage, layer: NumericLayer, center, radius: float, mode: int, value: float = 0.0,
                   stream=None):
     c = _f32(center, 3)
@@ -533,9 +569,10 @@ def numeric_stats(geom: GeometryImage, layer: NumericLayer, region: Optional[Lay
                   bins: Optional[torch.Tensor] = None, host: bool = True, stream=None):
     """Zonal statistics: a NUMSTAT record per value of `region` (one when
     None).  host=True returns them as a numpy array (synchronous); host=False
-    leaves them in `bins` (a device tensor of >= 40 bytes per group) and
+    leaves them in `bins` (a device tensor of >= 48 bytes per group) and
     returns that tensor."""
     groups = 1 if region is None else (256 if region.dtype == U8 else 65536)
+    assert NUMSTAT.itemsize == 48
     if bins is None:
         bins = torch.empty(groups * NUMSTAT.itemsize, dtype=torch.uint8, device=layer.data.device)
     if bins.numel() * bins.element_size() < groups * NUMSTAT.itemsize:
@@ -647,17 +684,31 @@ def nbins(layers: Sequence[Layer]) -> int:
     return sum(256 if l.dtype == U8 else 65536 for l in layers)
 
 
+def bins_to_areas(bins: np.ndarray, nb: int, scale: float, wide: bool) -> np.ndarray:
+    """fp64 areas of nb bins read back from the device (uint64 words; with
+    two-word weights the low sums, then the high sums)."""
+    b = np.asarray(bins).view(np.uint64)
+    if not wide:
+        return b[:nb].astype(np.float64) * scale
+    lo, hi = b[:nb], b[nb:2 * nb]
+    return np.array([float((int(h) << 32) + int(l)) * scale for l, h in zip(lo, hi)], np.float64)
+
+
 def area_query(geom: GeometryImage, layers: Sequence[Layer], bins: Optional[torch.Tensor] = None,
                sync: bool = True, stream=None):
     """Per-label areas of each layer.
 
     sync=True: returns a list of fp64 numpy arrays (256 or 65536 bins each).
-    sync=False: returns the device uint64 bins tensor (asynchronous).
+    sync=False: returns the device uint64 bins tensor (asynchronous; with
+    two-word weights the low-word sums, then the high-word sums).
     """
     arr = (CLayer * len(layers))(*[l.c for l in layers])
     nb = nbins(layers)
+    words = nb * (2 if geom.wide else 1)
     if bins is None:
-        bins = torch.empty(nb, dtype=torch.int64, device=layers[0].data.device)
+        bins = torch.empty(words, dtype=torch.int64, device=layers[0].data.device)
+    if bins.numel() < words:
+        raise ValueError(f"bins needs {words} entries")
     host = np.empty(nb, np.float64) if sync else None
     _check(_lib().uvl_area_query(ctypes.byref(geom.c), arr, len(layers), _ptr(bins),
                                  None if host is None else host.ctypes.data_as(ctypes.c_void_p), _stream(stream)),

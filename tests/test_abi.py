@@ -46,7 +46,7 @@ def test_library_exports_every_declared_symbol(uvl):
 
 def test_status_strings(uvl):
     L = uvl.lib()
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert L.uvl_status_str(code)
     assert L.uvl_status_str(-99) == b"unknown status"
 
@@ -367,3 +367,32 @@ def test_pool_validation(uvl):
     assert L.uvl_pool_stats(None, ctypes.byref(r), ctypes.byref(c), ctypes.byref(k)) == -1
     assert L.uvl_pool_array(None, 64, 64, 1, ctypes.byref(p), ctypes.byref(ctypes.c_size_t()), ctypes.byref(s)) == -1
     assert L.uvl_pool_destroy(None) == -1
+
+
+def test_ctypes_structs_match_the_header(uvl, tmp_path):
+    """Sizes and field offsets of the binding's structures equal those a C
+    compiler gives the header's (gcc, this machine's ABI)."""
+    import subprocess
+    structs = {"uvl_mesh": uvl.CMesh, "uvl_geom": uvl.CGeom, "uvl_layer": uvl.CLayer,
+               "uvl_numeric": uvl.CNumeric, "uvl_edit": uvl.CEdit, "uvl_wave_outline": uvl.CWaveOutline}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "uvl.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f in cls._fields_:
+            lines.append(f'printf("{cname}.{f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines.append('printf("uvl_numstat %zu\\n", sizeof(uvl_numstat));')
+    for f in uvl.NUMSTAT.names:
+        lines.append(f'printf("uvl_numstat.{f} %zu\\n", offsetof(uvl_numstat, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(l.rsplit(" ", 1) for l in subprocess.check_output([str(exe)]).decode().split("\n") if l)
+    for cname, cls in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for f in cls._fields_:
+            assert int(got[f"{cname}.{f[0]}"]) == getattr(cls, f[0]).offset, (cname, f[0])
+    assert int(got["uvl_numstat"]) == uvl.NUMSTAT.itemsize
+    for f in uvl.NUMSTAT.names:
+        assert int(got[f"uvl_numstat.{f}"]) == uvl.NUMSTAT.fields[f][1], f

@@ -262,3 +262,92 @@ def test_scan_full_size_numeric(gpu, orc):
     want = N.stats(np.concatenate(tri), np.concatenate(w), R)
     assert want["count"][0] > 0
     _check_stats(got[1:2], want, m.geom.area_scale, m.geom.area_abs_err, "full-size rows")
+
+
+# ---------------------------------------------------------------------------
+# operations between numeric layers
+
+
+def _random_values(rng, dtype, n):
+    """Values over the dtype's whole range, with its extremes and (floats)
+    random bit patterns, so that sums saturate, round to ties and land on
+    subnormals."""
+    if dtype == N.U8:
+        v = rng.integers(0, 256, n).astype(np.uint8)
+        edge = [0, 1, 254, 255, 128]
+    elif dtype == N.U16:
+        v = rng.integers(0, 65536, n).astype(np.uint16)
+        edge = [0, 1, 65534, 65535, 32768]
+    elif dtype == N.I32:
+        v = rng.integers(-2 ** 31, 2 ** 31, n, dtype=np.int64).astype(np.int32)
+        edge = [-2 ** 31, 2 ** 31 - 1, -1, 0, 1]
+    elif dtype == N.F16:
+        b = rng.integers(0, 65536, n).astype(np.uint16)
+        b[(b & 0x7c00) == 0x7c00] &= 0xbfff            # no inf / NaN
+        v = b.view(np.float16)
+        edge = [65504.0, -65504.0, 2.0 ** -24, -2.0 ** -24, 1.0, 2.0 ** -11, 0.0, -0.0, 65472.0]
+    else:
+        b = rng.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+        b[(b & 0x7f800000) == 0x7f800000] &= 0xbfffffff
+        v = b.view(np.float32)
+        m = float(np.finfo(np.float32).max)
+        edge = [m, -m, m / 2, 1.0, 2.0 ** -24, 2.0 ** -149, 0.0, -0.0]
+    k = min(n, 4 * len(edge))
+    v[:k] = np.resize(np.array(edge, dtype=v.dtype), k)
+    return v
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_numeric_ops_bit_exact(gpu, dtype):
+    """AND / OR / XOR / MIN / MAX / ADD between numeric layers, into a third
+    layer and in place (dst = a, dst = b), on sizes with and without whole
+    mask words and 4-texel groups, against the oracle's numeric layers: data
+    bits and mask words identical; the mask bits past the last texel stay."""
+    rng = np.random.default_rng(4100 + dtype)
+    for (W, H) in ((1024, 37), (37, 53), (300, 200), (1, 1), (4099, 3)):
+        n = W * H
+        print(f"case: dtype {dtype} size {W}x{H}", flush=True)
+        for op in (N.NUM_AND, N.NUM_OR, N.NUM_XOR, N.NUM_MIN, N.NUM_MAX, N.NUM_ADD):
+            for alias in (0, 1, 2):
+                va, vb, vd = (rng.random(n) < p for p in (0.6, 0.5, 0.3))
+                xa, xb, xd = (_random_values(rng, dtype, n) for _ in range(3))
+                # the same pairs again with shuffled partners
+                xb[n // 2:] = rng.permutation(xa[n // 2:])
+                ra, rb, rd = N.NumericLayer(n, dtype), N.NumericLayer(n, dtype), N.NumericLayer(n, dtype)
+                for r, x, v in ((ra, xa, va), (rb, xb, vb), (rd, xd, vd)):
+                    r.data[:] = x
+                    r.valid[:] = v
+                A, B, D = (gpu.NumericLayer(W, H, dtype) for _ in range(3))
+                A.copy_from(xa, va)
+                B.copy_from(xb, vb)
+                D.copy_from(xd, vd)
+                nw = (n + 31) // 32
+                if n % 32:
+                    # bits past the last texel of dst's last word must stay
+                    import torch
+                    tail = np.array([np.uint32(0xffffffff) << np.uint32(n % 32)], np.uint32)
+                    last = D.mask[nw - 1:nw].cpu().numpy().view(np.uint32) | tail
+                    D.mask[nw - 1:nw].copy_(torch.from_numpy(last.view(np.int32)))
+                gd, od = {0: (D, rd), 1: (A, ra), 2: (B, rb)}[alias]
+                gpu.numeric_op(op, gd, A, B)
+                N.combine(op, od, ra, rb)
+                got_words = gd.mask_words()
+                want_words = od.words
+                if n % 32 and alias == 0:
+                    want_words = want_words.copy()
+                    want_words[-1] |= tail[0]
+                tag = (W, H, op, alias)
+                assert np.array_equal(_bits(gd.numpy()), _bits(od.data)), tag
+                assert np.array_equal(got_words, want_words), tag
+
+
+def test_numeric_ops_refuse_mismatches(gpu):
+    A = gpu.NumericLayer(64, 8, N.F32)
+    B = gpu.NumericLayer(64, 8, N.F16)
+    C = gpu.NumericLayer(64, 9, N.F32)
+    with pytest.raises(Exception):
+        gpu.numeric_op(N.NUM_ADD, A, A, B)
+    with pytest.raises(Exception):
+        gpu.numeric_op(N.NUM_ADD, A, A, C)
+    with pytest.raises(Exception):
+        gpu.numeric_op(9, A, A, A)

@@ -426,6 +426,7 @@ def test_remap_table_ring_reuse(gpu, orc):
     ring has slots (16): each call's table is the one applied, whether its
     slot is fresh or reused after waiting, with no synchronisation between
     the calls; u8 tables (passed by value) interleaved."""
+    import torch
     W, H = 300, 7
     n = W * H
     rng = np.random.default_rng(77)
