@@ -200,6 +200,20 @@ size_t uvl_depth_workspace_bytes(int64_t nt);
 int32_t uvl_render_depth(const uvl_mesh *mesh, const float view_proj[16], float *depth, int32_t dw,
                          int32_t dh, void *ws, size_t ws_bytes, void *stream);
 
+/* Allocation-free variant of uvl_render_depth, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, result and
+ * errors without ws/ws_bytes: the workspace is a static device array of
+ * 256 + 4 * UVL_DEPTH_NOALLOC_MAX_TRIS bytes (16 MiB) per device, held
+ * until the process ends, so meshes of more than UVL_DEPTH_NOALLOC_MAX_TRIS
+ * triangles are refused with UVL_E_NOMEM.  Every call on one device shares
+ * that array: calls that overlap on one device (different streams, or
+ * different host threads) race and must be ordered by the caller.  The
+ * call allocates nothing itself. */
+#define UVL_DEPTH_NOALLOC_MAX_TRIS 4194304
+int32_t uvl_render_depth_noalloc(const uvl_mesh *mesh, const float view_proj[16], float *depth, int32_t dw,
+                                 int32_t dh, void *stream);
+
 /* Surface brush (§4.3.1 selects part of the surface and stores the chosen
  * value in the selected texels; here the tool is a 3D ball).  Every texel
  * whose position p satisfies, in fp32,

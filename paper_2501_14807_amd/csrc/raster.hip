@@ -22,6 +22,8 @@
 //   4. (geometry image) one thread per texel quantises the area weight.
 #include <math.h>
 
+#include <mutex>
+
 #include "uvl_internal.h"
 
 namespace uvl {
@@ -606,6 +608,32 @@ int32_t launch_depth(const uvl_mesh *mesh, const float *view_proj, float *depth,
     return launch_status();
 }
 
+// Scratch of the allocation-free depth render: the counters and the queue
+// of a mesh of up to UVL_DEPTH_NOALLOC_MAX_TRIS triangles, one static array
+// per device (held from module load to process end).  Host code never
+// passes the array's name to a kernel: its device address on each device
+// comes from hipGetSymbolAddress.
+constexpr size_t kDepthScratchBytes = 256 + (size_t)UVL_DEPTH_NOALLOC_MAX_TRIS * sizeof(unsigned);
+__device__ __align__(256) unsigned char depth_scratch[kDepthScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64];
+
+// Device address of depth_scratch on the current device (looked up once
+// per device, with that device current).
+int32_t depth_scratch_ptr(void *&out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return UVL_E_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(depth_scratch)) != hipSuccess || !p) return UVL_E_DEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    out = g_scratch_ptr[dev];
+    return UVL_OK;
+}
+
 }  // namespace
 }  // namespace uvl
 
@@ -615,5 +643,15 @@ extern "C" int32_t uvl_render_depth(const uvl_mesh *mesh, const float view_proj[
     if (!ws) return UVL_E_INVAL;
     if (ws_bytes < uvl_depth_workspace_bytes(mesh->nt)) return UVL_E_NOMEM;
     if (int32_t s = device_ok()) return s;
+    return launch_depth(mesh, view_proj, depth, dw, dh, ws, as_stream(stream));
+}
+
+extern "C" int32_t uvl_render_depth_noalloc(const uvl_mesh *mesh, const float view_proj[16], float *depth,
+                                            int32_t dw, int32_t dh, void *stream) {
+    if (int32_t st = depth_args_ok(mesh, view_proj, depth, dw, dh)) return st;
+    if (mesh->nt > UVL_DEPTH_NOALLOC_MAX_TRIS) return UVL_E_NOMEM;
+    if (int32_t s = device_ok()) return s;
+    void *ws = nullptr;
+    if (int32_t st = depth_scratch_ptr(ws)) return st;
     return launch_depth(mesh, view_proj, depth, dw, dh, ws, as_stream(stream));
 }

@@ -82,6 +82,7 @@ SIGNATURES = {
     "uvl_create_layer": ([_P, _P], _I32),
     "uvl_depth_workspace_bytes": ([_I64], _SZ),
     "uvl_render_depth": ([_P, _P, _P, _I32, _I32, _P, _SZ, _P], _I32),
+    "uvl_render_depth_noalloc": ([_P, _P, _P, _I32, _I32, _P], _I32),
     "uvl_edit_brush": ([_P, _P, _P, _F32, _U32, _P], _I32),
     "uvl_edit_lasso": ([_P, _P, _P, _P, _I32, _P, _I32, _I32, _F32, _U32, _P], _I32),
     "uvl_layer_op": ([_I32, _P, _P, _P, _U32, _U32, _U32, _P, _P], _I32),
@@ -398,6 +399,16 @@ def render_depth(mesh: DeviceMesh, view_proj, depth: torch.Tensor, workspace: Op
     _check(_lib().uvl_render_depth(ctypes.byref(mesh.c), M.ctypes.data_as(ctypes.c_void_p), _ptr(depth),
                                    dw, dh, _ptr(workspace), workspace.numel(), _stream(stream)),
            "uvl_render_depth")
+    return depth
+
+
+def render_depth_noalloc(mesh: DeviceMesh, view_proj, depth: torch.Tensor, stream=None) -> torch.Tensor:
+    """uvl_render_depth on the library's static scratch (no workspace, no
+    allocation); calls that overlap on one device race."""
+    M = _f32(view_proj, 16)
+    dh, dw = depth.shape
+    _check(_lib().uvl_render_depth_noalloc(ctypes.byref(mesh.c), M.ctypes.data_as(ctypes.c_void_p), _ptr(depth),
+                                           dw, dh, _stream(stream)), "uvl_render_depth_noalloc")
     return depth
 
 

@@ -193,6 +193,10 @@ def test_build_and_depth_validation(uvl):
     dws = L.uvl_depth_workspace_bytes(4)
     assert L.uvl_render_depth(ctypes.byref(m), M, FAKE, 0, 16, FAKE, dws, None) == -1
     assert L.uvl_render_depth(ctypes.byref(m), M, FAKE, 16, 16, FAKE, dws - 1, None) == -4
+    big = uvl.CMesh(FAKE, None, FAKE, FAKE, 10, 4194305)     # above the scratch's limit
+    assert L.uvl_render_depth_noalloc(ctypes.byref(big), M, FAKE, 16, 16, None) == -4
+    assert L.uvl_render_depth_noalloc(ctypes.byref(m), M, FAKE, 16, 0, None) == -1
+    assert L.uvl_render_depth_noalloc(None, M, FAKE, 16, 16, None) == -1
     assert L.uvl_create_layer(ctypes.byref(_layer(uvl, dt=5)), None) == -3
     assert L.uvl_create_layer(None, None) == -1
 
