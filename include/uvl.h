@@ -516,7 +516,15 @@ towards the wave's lasso capacity.  With numeric
  * non-NULL (and layer NULL) the edit SETs or ERASEs that numeric layer
  * (mode, value as for uvl_numeric_brush / uvl_numeric_lasso; label ignored):
  * the result is that of the numeric single-edit calls in array order.
- * Records without numeric edits leave numeric NULL and the rest 0. */
+ * Records without numeric edits leave numeric NULL and the rest 0.
+ * bins (label edits only; every edit of a layer names the same bins or
+ * none): device uint64, 8-byte aligned, the layer's bins in the layout
+ * uvl_area_query writes for this one layer (uvl_area_bin_count words).  The
+ * wave moves the area of every covered texel whose label it changes from the
+ * old label's bin to the new one's, so bins that held the layer's areas
+ * before the wave hold them after it (exact integers; bins are unsigned and
+ * a decrease wraps, the totals coming out exact).  Texture padding writes
+ * uncovered texels only and changes no bin. */
 typedef struct {
     const uvl_geom *geom;
     const uvl_layer *layer;
@@ -537,6 +545,8 @@ typedef struct {
     const double *tool;     /* tool edits: {Ww, Wh, Tpx, Tpy, Tw, Th} */
     const uint8_t *shape;
     int32_t sw, sh;
+    uint64_t *bins;         /* label edits, optional (NULL: none): the layer's
+                               area bins, see below */
 } uvl_edit;
 
 typedef struct uvl_wave uvl_wave;   /* opaque handle */

@@ -84,7 +84,9 @@ struct WaveStream {
     int32_t cull;       // 1: masks at mask0 (tiles x groups words), 0: no culling
     int32_t numeric;    // 1: a numeric layer (edits SET / ERASE with value bits)
     int32_t padk;       // padding radius
-    int32_t pad3;
+    int32_t nbins;      // label streams with bins: 256 (u8) or 65536 (u16)
+    unsigned long long *bins;       // label layer's area bins kept up to date (null: none)
+    const uint32_t *aw, *aw_hi;     // texel areas (low words; high words or null)
 };
 
 struct WaveEdit {
@@ -341,6 +343,89 @@ __global__ __launch_bounds__(kBlock) void k_wave_plan(char *__restrict__ ws) {
     }
 }
 
+// Area bins kept up to date by a label stream: every texel whose label the
+// wave changes moves its area from the old label's bin to the new one's.
+// The lanes of a wave settle one (old, new) pair at a time -- the pair of the
+// first lane with a pending change -- summing the area of all texels with
+// that pair and adding it with one pair of atomics (the bins are unsigned,
+// a subtraction wraps and the exact totals come out).  A wave's texels
+// usually share one or two pairs.  Control flow is uniform over the wave.
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned lo = __shfl_xor((unsigned)x, o), hi = __shfl_xor((unsigned)(x >> 32), o);
+        x += ((unsigned long long)hi << 32) | lo;
+    }
+    return x;
+}
+
+template <typename T>
+__device__ __forceinline__ void wave_bins(const UVL_CONST WaveStream &S, int64_t t, const uint32_t val[4],
+                                          const bool wr[4], const bool in[4], const bool cov[4], bool full) {
+    const T *L = static_cast<const T *>(S.layer);
+    bool ch[4];
+    uint32_t old[4] = {0, 0, 0, 0};
+    unsigned long long wl[4] = {0, 0, 0, 0}, wh[4] = {0, 0, 0, 0};
+    const bool any = (wr[0] && cov[0]) || (wr[1] && cov[1]) || (wr[2] && cov[2]) || (wr[3] && cov[3]);
+    if (any) {
+        if (full) {
+            if (sizeof(T) == 1) {
+                const uint32_t v = *reinterpret_cast<const uint32_t *>(L + t);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) old[k] = (v >> (8 * k)) & 0xffu;
+            } else {
+                const uint2 v = *reinterpret_cast<const uint2 *>(L + t);
+                old[0] = v.x & 0xffffu; old[1] = v.x >> 16; old[2] = v.y & 0xffffu; old[3] = v.y >> 16;
+            }
+            const uint4 w = *reinterpret_cast<const uint4 *>(S.aw + t);
+            wl[0] = w.x; wl[1] = w.y; wl[2] = w.z; wl[3] = w.w;
+            if (S.aw_hi) {
+                const uint4 h = *reinterpret_cast<const uint4 *>(S.aw_hi + t);
+                wh[0] = h.x; wh[1] = h.y; wh[2] = h.z; wh[3] = h.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (in[k]) {
+                    old[k] = L[t + k];
+                    wl[k] = S.aw[t + k];
+                    if (S.aw_hi) wh[k] = S.aw_hi[t + k];
+                }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ch[k] = wr[k] && in[k] && cov[k] && old[k] != val[k] && (wl[k] | wh[k]) != 0;
+    for (;;) {
+        const bool have = ch[0] || ch[1] || ch[2] || ch[3];
+        const unsigned long long lanes = __builtin_amdgcn_ballot_w64(have);
+        if (lanes == 0) break;
+        uint32_t key = 0;
+#pragma unroll
+        for (int k = 3; k >= 0; --k)
+            if (ch[k]) key = (old[k] << 16) | val[k];
+        const uint32_t lead = __shfl(key, __builtin_ctzll(lanes));
+        unsigned long long sl = 0, sh = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (ch[k] && ((old[k] << 16) | val[k]) == lead) {
+                sl += wl[k];
+                sh += wh[k];
+                ch[k] = false;
+            }
+        sl = wave_sum_u64(sl);
+        sh = wave_sum_u64(sh);
+        if ((threadIdx.x & 63) == 0) {
+            const uint32_t o = lead >> 16, v = lead & 0xffffu;
+            atomicAdd(S.bins + o, ~sl + 1ull);
+            atomicAdd(S.bins + v, sl);
+            if (S.aw_hi) {
+                atomicAdd(S.bins + S.nbins + o, ~sh + 1ull);
+                atomicAdd(S.bins + S.nbins + v, sh);
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_wave(char *__restrict__ ws, const uint64_t *__restrict__ masks_in,
                                                   const uint64_t *__restrict__ imasks_in,
                                                   const uint32_t *__restrict__ live_in) {
@@ -484,6 +569,10 @@ __global__ __launch_bounds__(kBlock) void k_wave(char *__restrict__ ws, const ui
                         wave_store_value<uint32_t>(static_cast<uint32_t *>(S.layer), S.vmask, t, val, wd, wr, mset,
                                                    in, full, group_word);
                 } else {
+                    if (S.bins) {
+                        if (S.dtype == UVL_U8) wave_bins<uint8_t>(S, t, val, wr, in, cov, full);
+                        else wave_bins<uint16_t>(S, t, val, wr, in, cov, full);
+                    }
                     if (S.dtype == UVL_U8) wave_store<uint8_t>(static_cast<uint8_t *>(S.layer), t, val, wr, in, full);
                     else wave_store<uint16_t>(static_cast<uint16_t *>(S.layer), t, val, wr, in, full);
                 }
@@ -717,6 +806,10 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
         const int32_t tdt = num ? e.numeric->dtype : e.layer->dtype;
         const void *target = num ? e.numeric->data : e.layer->data;
         if (tw != e.geom->width || th != e.geom->height) return UVL_E_SHAPE;
+        if (e.bins && (num || !e.geom->area_w || !aligned16(e.geom->area_w) ||
+                       (e.geom->area_w_hi && !aligned16(e.geom->area_w_hi)) ||
+                       (reinterpret_cast<uintptr_t>(e.bins) & 7)))
+            return UVL_E_INVAL;
         if (e.kind == UVL_EDIT_BRUSH) {
             if (!(e.radius >= 0.0f) || !std::isfinite(e.radius)) return UVL_E_INVAL;
             if (!std::isfinite(e.center[0]) || !std::isfinite(e.center[1]) || !std::isfinite(e.center[2]))
@@ -739,7 +832,8 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
             const uvl_edit &f = edits[members[k][0]];
             const bool fnum = f.numeric != nullptr;
             if (f.geom->pos_x != e.geom->pos_x || fnum != num || f.geom->width != tw || f.geom->height != th ||
-                (fnum ? f.numeric->dtype != tdt || f.numeric->mask != e.numeric->mask : f.layer->dtype != tdt))
+                (fnum ? f.numeric->dtype != tdt || f.numeric->mask != e.numeric->mask : f.layer->dtype != tdt) ||
+                f.bins != e.bins)
                 return UVL_E_INVAL;
         }
         members[k].push_back(i);
@@ -790,7 +884,10 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
         s.outline = nullptr;
         s.nout = 0;
         s.padk = 0;
-        s.pad3 = 0;
+        s.bins = f.numeric ? nullptr : reinterpret_cast<unsigned long long *>(f.bins);
+        s.aw = f.geom->area_w;
+        s.aw_hi = f.geom->area_w_hi;
+        s.nbins = f.numeric ? 0 : (f.layer->dtype == UVL_U8 ? 256 : 65536);
         s.out0 = nout_total;
         for (int32_t q = 0; q < noutlines; ++q) {
             const uvl_wave_outline &o = outlines[q];

@@ -24,10 +24,17 @@ from . import uvl
 class Model:
     def __init__(self, mesh, width: int, height: int, layer_dtypes: Sequence[int], depth_w: int = 256,
                  depth_h: int = 256, bias: float = 1e-4, normals: bool = True, bary: bool = True,
-                 device="cuda", depth_cache: int = 2):
+                 device="cuda", depth_cache: int = 2, pool: Optional["uvl.LayerPool"] = None):
+        """pool: commit the layers in a LayerPool (§4.2's texture arrays per
+        (width, height, dtype)) instead of torch tensors; release() returns
+        them."""
         self.mesh = uvl.DeviceMesh.from_mesh(mesh, device=device)
         self.geom = uvl.GeometryImage(width, height, normals=normals, bary=bary, device=device)
-        self.layers: List[uvl.Layer] = [uvl.Layer(width, height, dt, device=device) for dt in layer_dtypes]
+        self.pool = pool
+        if pool is None:
+            self.layers = [uvl.Layer(width, height, dt, device=device) for dt in layer_dtypes]
+        else:
+            self.layers = [pool.alloc(width, height, dt) for dt in layer_dtypes]
         self.depth_w, self.depth_h, self.bias = int(depth_w), int(depth_h), float(bias)
         self.device = device
         self.build_ws = torch.empty(uvl.lib().uvl_build_workspace_bytes(self.mesh.nt), dtype=torch.uint8,
@@ -36,6 +43,13 @@ class Model:
         self._depth: "OrderedDict[int, torch.Tensor]" = OrderedDict()
         self._depth_cap = max(1, depth_cache)
         self.bins = torch.empty(uvl.nbins(self.layers), dtype=torch.int64, device=device)
+
+    def release(self):
+        """Return pool-committed layers to their pool (waits for the device)."""
+        if self.pool is not None:
+            for l in self.layers:
+                self.pool.free(l)
+            self.layers = []
 
     @classmethod
     def from_workload(cls, wl, **kw):

@@ -133,7 +133,8 @@ class CEdit(ctypes.Structure):
                 ("dw", ctypes.c_int32), ("dh", ctypes.c_int32), ("bias", ctypes.c_float),
                 ("depth", ctypes.c_void_p), ("numeric", ctypes.c_void_p), ("mode", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("value", ctypes.c_double), ("tool", ctypes.c_void_p),
-                ("shape", ctypes.c_void_p), ("sw", ctypes.c_int32), ("sh", ctypes.c_int32)]
+                ("shape", ctypes.c_void_p), ("sw", ctypes.c_int32), ("sh", ctypes.c_int32),
+                ("bins", ctypes.c_void_p)]
 
 
 def _lib():
@@ -717,7 +718,7 @@ def area_query(geom: GeometryImage, layers: Sequence[Layer], bins: Optional[torc
     nb = nbins(layers)
     words = nb * (2 if geom.wide else 1)
     if bins is None:
-        bins = torch.empty(words, dtype=torch.int64, device=layers[0].data.device)
+        bins = torch.empty(words, dtype=torch.int64, device=geom.area_w.device)
     if bins.numel() < words:
         raise ValueError(f"bins needs {words} entries")
     host = np.empty(nb, np.float64) if sync else None
@@ -742,7 +743,8 @@ def area_query(geom: GeometryImage, layers: Sequence[Layer], bins: Optional[torc
 # filled one tuple per edit and handed to the library without a copy
 EDIT_DTYPE = np.dtype({"names": [f[0] for f in CEdit._fields_],
                        "formats": ["<u8", "<u8", "<i4", "<u4", ("<f4", (3,)), "<f4", "<u8", "<u8", "<i4", "<i4",
-                                   "<i4", "<f4", "<u8", "<u8", "<i4", "<i4", "<f8", "<u8", "<u8", "<i4", "<i4"],
+                                   "<i4", "<f4", "<u8", "<u8", "<i4", "<i4", "<f8", "<u8", "<u8", "<i4", "<i4",
+                                   "<u8"],
                        "offsets": [getattr(CEdit, f[0]).offset for f in CEdit._fields_],
                        "itemsize": ctypes.sizeof(CEdit)})
 
@@ -768,30 +770,34 @@ class EditBatch:
         self._n += 1
         return self._n - 1
 
-    def brush(self, geom: GeometryImage, layer: Layer, center, radius: float, label: int):
+    def brush(self, geom: GeometryImage, layer: Layer, center, radius: float, label: int,
+              bins: Optional[torch.Tensor] = None):
+        """bins: optional device uint64 area bins of the layer, kept up to
+        date by the wave (uvl_edit.bins)."""
         c = _f32(center, 3)
         i = self._slot()
         self._a[i] = (geom.addr, layer.addr, EDIT_BRUSH, int(label), c, np.float32(radius), 0, 0, 0, 0, 0, 0.0, 0,
-                      0, 0, 0, 0.0, 0, 0, 0, 0)
-        self._keep.append((geom, layer))
+                      0, 0, 0, 0.0, 0, 0, 0, 0, 0 if bins is None else bins.data_ptr())
+        self._keep.append((geom, layer, bins))
 
     def lasso(self, geom: GeometryImage, layer: Layer, view_proj, poly, depth: torch.Tensor, bias: float,
-              label: int):
+              label: int, bins: Optional[torch.Tensor] = None):
         M = _f32(view_proj, 16)
         P = _f32(poly).reshape(-1)
         dh, dw = depth.shape
         i = self._slot()
         self._a[i] = (geom.addr, layer.addr, EDIT_LASSO, int(label), (0.0, 0.0, 0.0), 0.0, _addr(M), _addr(P),
-                      P.size // 2, dw, dh, np.float32(bias), depth.data_ptr(), 0, 0, 0, 0.0, 0, 0, 0, 0)
+                      P.size // 2, dw, dh, np.float32(bias), depth.data_ptr(), 0, 0, 0, 0.0, 0, 0, 0, 0,
+                      0 if bins is None else bins.data_ptr())
         self._nl += 1
-        self._keep.append((geom, layer, M, P, depth))
+        self._keep.append((geom, layer, M, P, depth, bins))
 
     def numeric_brush(self, geom: GeometryImage, layer: "NumericLayer", center, radius: float, mode: int,
                       value: float = 0.0):
         c = _f32(center, 3)
         i = self._slot()
         self._a[i] = (geom.addr, 0, EDIT_BRUSH, 0, c, np.float32(radius), 0, 0, 0, 0, 0, 0.0, 0,
-                      ctypes.addressof(layer.c), int(mode), 0, float(value), 0, 0, 0, 0)
+                      ctypes.addressof(layer.c), int(mode), 0, float(value), 0, 0, 0, 0, 0)
         self._keep.append((geom, layer))
 
     def numeric_lasso(self, geom: GeometryImage, layer: "NumericLayer", view_proj, poly, depth: torch.Tensor,
@@ -802,7 +808,7 @@ class EditBatch:
         i = self._slot()
         self._a[i] = (geom.addr, 0, EDIT_LASSO, 0, (0.0, 0.0, 0.0), 0.0, _addr(M), _addr(P), P.size // 2, dw, dh,
                       np.float32(bias), depth.data_ptr(), ctypes.addressof(layer.c), int(mode), 0, float(value),
-                      0, 0, 0, 0)
+                      0, 0, 0, 0, 0)
         self._nl += 1
         self._keep.append((geom, layer, M, P, depth))
 
@@ -816,7 +822,7 @@ class EditBatch:
         i = self._slot()
         self._a[i] = (geom.addr, layer_addr, EDIT_TOOL, int(label), (0.0, 0.0, 0.0), 0.0, _addr(M), 0, 0, dw, dh,
                       np.float32(bias), depth.data_ptr(), numeric_addr, int(mode), 0, float(value), _addr(tp),
-                      shape.data_ptr(), sw, sh)
+                      shape.data_ptr(), sw, sh, 0)
         self._nl += 1
         self._keep.append((geom, keep, M, tp, shape, depth))
 

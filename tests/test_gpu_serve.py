@@ -1,7 +1,10 @@
 """Serving on the GPU: each request's result is the same alone and in the
 mix (continuous batching vs plain one-launch-per-request vs each model's
 requests applied on their own), bit for bit, with and without texture
-padding."""
+padding; under a budget that holds only some of the models at once (models
+evicted to the host and admitted again); and the same request stream
+replayed in the oracle, model by model in arrival order (edits, layer
+operations, area queries), matches element by element."""
 
 import numpy as np
 import pytest
@@ -21,17 +24,15 @@ def gpu():
     return uvl
 
 
-def _setup(gpu):
-    from paper_2501_14807_amd.model import Model
+def _setup(gpu, n_requests=700):
+    from paper_2501_14807_amd.serve import ModelSpec
     scan = synth.scan_workload(n_brush=0, n_lasso=0, n_ops=0, W=1024, n_charts=4, nx=64, ny=32, depth=512)
     meshes = [synth.vessel(seed=s) for s in range(3)] + [scan.mesh]
     sizes = [(512, 512), (300, 200), (256, 384), (1024, 1024)]
     dtypes = [[gpu.U8, gpu.U16]] * 4
-    models = [Model(m, w, h, dt, depth_w=256, depth_h=256) for m, (w, h), dt in zip(meshes, sizes, dtypes)]
-    for m in models:
-        m.build()
-    cams, stream = synth.serve_stream(meshes, dtypes, 700, 30000.0, seed=11)
-    return models, cams, stream
+    specs = [ModelSpec(m, w, h, dt, depth=256) for m, (w, h), dt in zip(meshes, sizes, dtypes)]
+    cams, stream = synth.serve_stream(meshes, dtypes, n_requests, 30000.0, seed=11)
+    return specs, cams, stream
 
 
 def _requests(stream, only=None):
@@ -45,39 +46,108 @@ def _requests(stream, only=None):
     return out
 
 
-def _run(gpu, models, cams, reqs, mode, pad_k=None):
-    import torch
+def _run(gpu, specs, cams, reqs, mode, pad_k=None, budget=1 << 40):
     from paper_2501_14807_amd.serve import GpuExecutor, Server
-    for m in models:
-        m.clear_layers()
-    ex = GpuExecutor(models, cams, max_wave_edits=1024, pad_k=pad_k)
-    st = Server(ex, len(models), 1 << 40).run(reqs, mode)
-    torch.cuda.synchronize()
-    layers = [[l.numpy().copy() for l in m.layers] for m in models]
+    ex = GpuExecutor(specs, cams, max_wave_edits=1024, pad_k=pad_k, keep_bins=(mode == "batched"))
+    srv = Server(ex, len(specs), budget)
+    st = srv.run(reqs, mode)
+    layers = [ex.layers_of(m) for m in range(len(specs))]
     areas = {r.rid: r.result for r in reqs if r.kind == "area"}
-    ex.wave.close()
+    ex.close()
     return st, layers, areas
 
 
+def _same_layers(a, b):
+    for x, y in zip(a, b):
+        if x is None or y is None:
+            assert x is None and y is None
+            continue
+        for p, q in zip(x, y):
+            assert np.array_equal(p, q)
+
+
 def test_alone_equals_mix(gpu):
-    models, cams, stream = _setup(gpu)
-    st_b, lay_b, area_b = _run(gpu, models, cams, _requests(stream), "batched")
-    st_p, lay_p, area_p = _run(gpu, models, cams, _requests(stream), "plain")
+    specs, cams, stream = _setup(gpu)
+    st_b, lay_b, area_b = _run(gpu, specs, cams, _requests(stream), "batched")
+    st_p, lay_p, area_p = _run(gpu, specs, cams, _requests(stream), "plain")
     assert st_b.failed == st_p.failed == 0
     assert st_b.rounds < st_b.n                  # requests were batched
-    for a, b in zip(lay_b, lay_p):
-        for x, y in zip(a, b):
-            assert np.array_equal(x, y)
+    _same_layers(lay_b, lay_p)
     assert area_b.keys() == area_p.keys() and len(area_b) > 10
+    # batched answers come from the bins the waves keep, plain ones from a scan
     for k in area_b:
         assert np.array_equal(area_b[k], area_p[k]), k
     # each model's requests on their own
-    for mi in range(len(models)):
-        st, lay, areas = _run(gpu, models, cams, _requests(stream, only=mi), "plain")
+    for mi in range(len(specs)):
+        st, lay, areas = _run(gpu, specs, cams, _requests(stream, only=mi), "plain")
         for x, y in zip(lay[mi], lay_b[mi]):
             assert np.array_equal(x, y)
         for k, v in areas.items():
             assert np.array_equal(v, area_b[k])
+
+
+def test_eviction_under_a_tight_budget(gpu):
+    """A budget for about two of the four models: models are evicted to the
+    host and admitted again as requests for them arrive, and every result
+    equals that of the unconstrained run."""
+    from paper_2501_14807_amd.serve import GpuExecutor
+    specs, cams, stream = _setup(gpu)
+    ex = GpuExecutor(specs, cams)
+    fp = [ex.footprint(m) for m in range(len(specs))]
+    ex.close()
+    budget = fp[3] + max(fp[:3]) + 1             # the scan model and one vessel
+    st_u, lay_u, area_u = _run(gpu, specs, cams, _requests(stream), "batched")
+    for mode in ("batched", "plain"):
+        st, lay, areas = _run(gpu, specs, cams, _requests(stream), mode, budget=budget)
+        assert st.failed == 0 and st.refused == 0
+        assert st.evictions > 0 and st.admissions > len(specs)
+        _same_layers(lay, lay_u)
+        for k in area_u:
+            assert np.array_equal(areas[k], area_u[k]), (mode, k)
+
+
+def test_serving_matches_the_oracle(gpu, orc):
+    """The served stream replayed in the oracle, per model in arrival order:
+    final layers identical, and every area answer (the bins the waves keep)
+    within 1e-6 of the oracle's areas at that point of the stream."""
+    import torch
+    specs, cams, stream = _setup(gpu, n_requests=400)
+    reqs = _requests(stream)
+    from paper_2501_14807_amd.serve import GpuExecutor, Server
+    ex = GpuExecutor(specs, cams, max_wave_edits=1024)
+    srv = Server(ex, len(specs), 1 << 40)
+    st = srv.run(reqs, "batched")
+    assert st.failed == 0
+    scales = {m: ex.models[m].geom.area_scale for m in ex.models}
+    lay_gpu = [ex.layers_of(m) for m in range(len(specs))]
+    ex.close()
+    checked = 0
+    for mi, sp in enumerate(specs):
+        og = orc.geometry_image(sp.mesh, sp.width, sp.height)
+        layers = [np.zeros(sp.width * sp.height, np.uint8 if dt == gpu.U8 else np.uint16) for dt in sp.layer_dtypes]
+        depth = {}
+        for r in sorted((r for r in reqs if r.model == mi), key=lambda r: (r.t_arrival, r.rid)):
+            if r.kind == "brush":
+                e = r.edit
+                orc.brush(og.pos32, layers[e.layer], e.centre, e.radius, e.label)
+            elif r.kind == "lasso":
+                e = r.edit
+                if e.camera not in depth:
+                    depth[e.camera] = orc.depth_map(sp.mesh, cams[mi][e.camera], sp.depth, sp.depth)
+                orc.lasso(og.pos32, layers[e.layer], cams[mi][e.camera], e.poly, depth[e.camera], sp.bias, e.label)
+            elif r.kind == "algebra":
+                o = r.op
+                orc.layer_op(o.op, layers[o.dst], layers[o.a], layers[o.b], o.sel_a, o.sel_b, o.out_label, o.lut)
+            else:
+                ref = orc.area(og, layers[r.layer])
+                got = r.result.astype(np.float64) * scales[mi]
+                nz = ref > 0
+                assert np.allclose(got[nz], ref[nz], rtol=1e-6, atol=0), (mi, r.rid)
+                assert (got[~nz] == 0).all(), (mi, r.rid)
+                checked += 1
+        for x, y in zip(layers, lay_gpu[mi]):
+            assert np.array_equal(x, y), mi
+    assert checked > 20
 
 
 def test_padded_serving_batched_equals_plain(gpu):
@@ -85,10 +155,10 @@ def test_padded_serving_batched_equals_plain(gpu):
     inside the waves) gives the layers of plain serving (an edit launch and
     its padding launch per request), and the areas of unpadded serving
     (padding writes uncovered texels only)."""
-    models, cams, stream = _setup(gpu)
-    st_b, lay_b, area_b = _run(gpu, models, cams, _requests(stream), "batched", pad_k=1)
-    st_p, lay_p, area_p = _run(gpu, models, cams, _requests(stream), "plain", pad_k=1)
-    _, lay_u, area_u = _run(gpu, models, cams, _requests(stream), "plain")
+    specs, cams, stream = _setup(gpu)
+    st_b, lay_b, area_b = _run(gpu, specs, cams, _requests(stream), "batched", pad_k=1)
+    st_p, lay_p, area_p = _run(gpu, specs, cams, _requests(stream), "plain", pad_k=1)
+    _, lay_u, area_u = _run(gpu, specs, cams, _requests(stream), "plain")
     assert st_b.failed == st_p.failed == 0 and st_b.rounds < st_b.n
     padded_somewhere = False
     for a, b, u in zip(lay_b, lay_p, lay_u):

@@ -41,7 +41,7 @@ def test_fifo_per_model(mode):
             assert r.result == want[r.rid]
     # per model, launches happen in arrival order
     for m in range(7):
-        launched = [rid for _, mm, rid in ex.log if mm == m]
+        launched = [rid for _, mm, rid in ex.log if mm == m and rid >= 0]
         arrived = [r.rid for r in sorted(reqs, key=lambda r: (r.t_arrival, r.rid)) if r.model == m]
         assert launched == arrived
 
@@ -56,18 +56,55 @@ def test_continuous_batching_beats_plain_under_load():
     assert st_b.wall_s <= st_p.wall_s + 0.05
 
 
-def test_admission_by_footprint_and_refusals():
-    reqs = _stream(500, 4, 20000.0, seed=2)
+def test_admission_by_footprint_and_eviction():
+    """Four models of footprint 40 under a budget of 100: at most two are
+    resident at once; models are admitted as their requests arrive and the
+    least recently used idle ones evicted; every request completes, in
+    per-model arrival order, seeing its model's earlier requests."""
+    reqs = _stream(1500, 4, 20000.0, seed=2)
     ex = SimExecutor([40, 40, 40, 40])
-    srv = Server(ex, 4, 100)                     # only two models fit
-    assert srv.resident == {0, 1} and srv.used_bytes == 80
+    srv = Server(ex, 4, 100)
     st = srv.run(reqs, "batched")
+    assert st.failed == 0 and st.refused == 0
+    assert st.evictions > 0 and st.admissions > 4
+    want = _expected_seen(reqs)
     for r in reqs:
-        if r.model in (2, 3):
-            assert not r.ok and r.result == "model not resident"
+        assert r.ok
+        if r.kind == "area":
+            assert r.result == want[r.rid]
+    # replay the log: the resident set never exceeds the budget, and no work
+    # is launched for a model that is not resident
+    resident = set()
+    for kind, m, _ in ex.log:
+        if kind == "admit":
+            resident.add(m)
+            assert 40 * len(resident) <= 100
+        elif kind == "evict":
+            resident.discard(m)
         else:
-            assert r.ok
-    assert st.refused == sum(1 for r in reqs if r.model in (2, 3))
+            assert m in resident
+    for m in range(4):
+        launched = [rid for kind, mm, rid in ex.log if mm == m and rid >= 0]
+        arrived = [r.rid for r in sorted(reqs, key=lambda r: (r.t_arrival, r.rid)) if r.model == m]
+        assert launched == arrived
+
+
+def test_model_larger_than_the_budget_is_refused():
+    reqs = _stream(400, 3, 20000.0, seed=6)
+    ex = SimExecutor([40, 200, 40])
+    st = Server(ex, 3, 100).run(reqs, "plain")
+    for r in reqs:
+        assert r.ok == (r.model != 1)
+        if r.model == 1:
+            assert r.result == "model larger than the budget"
+    assert st.refused == sum(1 for r in reqs if r.model == 1)
+
+
+def test_preload():
+    ex = SimExecutor([40, 40, 40])
+    srv = Server(ex, 3, 100)
+    srv.preload()
+    assert srv.resident == {0, 1} and srv.used_bytes == 80
 
 
 def test_failure_is_isolated():
