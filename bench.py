@@ -162,7 +162,11 @@ def bench_batched(n_models, reps, torch, uvl):
     t = time.perf_counter()
     wls = synth.batch_workload(n_models=n_models)
     log(f"batch workload generated in {time.perf_counter() - t:.1f} s")
-    models = [Model.from_workload(w, normals=False, bary=False).build() for w in wls]
+    models = []
+    for k, w in enumerate(wls):
+        models.append(Model.from_workload(w, normals=False, bary=False).build())
+        if (k + 1) % 32 == 0:
+            log(f"batch models built: {k + 1}/{len(wls)}")
     n_edits = sum(len(w.edits) for w in wls)
     n_lassos = sum(1 for w in wls for e in w.edits if e.kind == "lasso")
     texels = sum(w.W * w.H for w in wls)

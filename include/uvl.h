@@ -154,8 +154,8 @@ const char *uvl_status_str(int32_t status);
 int32_t uvl_device_check(void);
 
 /* Workspace bytes uvl_build_geometry_image needs for a mesh of nt
- * triangles. */
-size_t uvl_build_workspace_bytes(int64_t nt);
+ * triangles and a width x height atlas (0 for sizes out of range). */
+size_t uvl_build_workspace_bytes(int64_t nt, int32_t width, int32_t height);
 
 /* Render the mesh into texture space (§4.3.1, the texture-space render with
  * texture coordinates as positions; §4.1, texture coordinates index the
@@ -169,7 +169,7 @@ size_t uvl_build_workspace_bytes(int64_t nt);
  * 131072 * A3 / |E| (A3 the triangle's 3D area) quantised to one uint32
  * word (area_w_hi NULL) or two (low and high words) with a power-of-two
  * scale.
- * ws: device workspace of uvl_build_workspace_bytes(nt) bytes.
+ * ws: device workspace of uvl_build_workspace_bytes(nt, width, height) bytes.
  * SYNCHRONOUS: waits for `stream` to read back area_scale.
  * mesh->tri may be NULL when nt == 0 (every texel is then uncovered).
  * Errors: UVL_E_INVAL for null planes, width/height outside [1, 32768],

@@ -24,7 +24,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libuvl.so")
 
-SOURCES = ["common.hip", "raster.hip", "edit.hip", "algebra.hip", "area.hip", "wave.hip", "pad.hip", "tool.hip", "numeric.hip", "pool.hip"]
+SOURCES = ["common.hip", "raster.hip", "geom.hip", "edit.hip", "algebra.hip", "area.hip", "wave.hip", "pad.hip", "tool.hip", "numeric.hip", "pool.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 ARCH = "gfx950"

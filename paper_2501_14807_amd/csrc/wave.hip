@@ -102,7 +102,7 @@ struct WaveEdit {
 // Byte offsets, within the workspace, of the regions of one packed wave.
 struct WaveHeader {
     int32_t nstreams;
-    int32_t pad;
+    int32_t any_bins;        // 1: some label stream keeps area bins
     int64_t total_cull_waves;
     int64_t total_items;     // written by k_wave_plan
     int64_t total_out;       // outline entries to pad, over all streams
@@ -359,17 +359,46 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
     return x;
 }
 
-template <typename T>
-__device__ __forceinline__ void wave_bins(const UVL_CONST WaveStream &S, int64_t t, const uint32_t val[4],
-                                          const bool wr[4], const bool in[4], const bool cov[4], bool full) {
-    const T *L = static_cast<const T *>(S.layer);
+// The workgroup's area changes, keyed by (stream, label), in LDS: added to
+// the streams' bins once, when the persistent workgroup ends, so that the
+// many tiles of an edit do not all hit the same two global bins.
+constexpr int kBinSlots = 512;
+constexpr uint32_t kNoBinKey = 0xffffffffu;
+
+struct BinTable {
+    uint32_t *key;
+    unsigned long long *lo, *hi;
+
+    __device__ __forceinline__ void add(const UVL_CONST WaveStream &S, int si, uint32_t label, unsigned long long dl,
+                                        unsigned long long dh) const {
+        const uint32_t k = ((uint32_t)si << 16) | label;
+        uint32_t h = (k * 2654435761u) >> 23;         // 9 bits: kBinSlots
+        for (int probe = 0; probe < 8 && si < 65535; ++probe) {
+            const uint32_t prev = atomicCAS(key + h, kNoBinKey, k);
+            if (prev == kNoBinKey || prev == k) {
+                atomicAdd(lo + h, dl);
+                if (S.aw_hi) atomicAdd(hi + h, dh);
+                return;
+            }
+            h = (h + 1) & (kBinSlots - 1);
+        }
+        atomicAdd(S.bins + label, dl);
+        if (S.aw_hi) atomicAdd(S.bins + S.nbins + label, dh);
+    }
+};
+
+template <typename Lab>
+__device__ __forceinline__ void wave_bins(const UVL_CONST WaveStream &S, int si, const BinTable &tab, int64_t t,
+                                          const uint32_t val[4], const bool wr[4], const bool in[4],
+                                          const bool cov[4], bool full) {
+    const Lab *L = static_cast<const Lab *>(S.layer);
     bool ch[4];
     uint32_t old[4] = {0, 0, 0, 0};
     unsigned long long wl[4] = {0, 0, 0, 0}, wh[4] = {0, 0, 0, 0};
     const bool any = (wr[0] && cov[0]) || (wr[1] && cov[1]) || (wr[2] && cov[2]) || (wr[3] && cov[3]);
     if (any) {
         if (full) {
-            if (sizeof(T) == 1) {
+            if (sizeof(Lab) == 1) {
                 const uint32_t v = *reinterpret_cast<const uint32_t *>(L + t);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) old[k] = (v >> (8 * k)) & 0xffu;
@@ -416,12 +445,8 @@ __device__ __forceinline__ void wave_bins(const UVL_CONST WaveStream &S, int64_t
         sh = wave_sum_u64(sh);
         if ((threadIdx.x & 63) == 0) {
             const uint32_t o = lead >> 16, v = lead & 0xffffu;
-            atomicAdd(S.bins + o, ~sl + 1ull);
-            atomicAdd(S.bins + v, sl);
-            if (S.aw_hi) {
-                atomicAdd(S.bins + S.nbins + o, ~sh + 1ull);
-                atomicAdd(S.bins + S.nbins + v, sh);
-            }
+            tab.add(S, si, o, ~sl + 1ull, ~sh + 1ull);
+            tab.add(S, si, v, sl, sh);
         }
     }
 }
@@ -443,6 +468,15 @@ __global__ __launch_bounds__(kBlock) void k_wave(char *__restrict__ ws, const ui
     const UVL_CONST uint64_t *imasks = (const UVL_CONST uint64_t *)imasks_in;
     const UVL_CONST uint32_t *live = (const UVL_CONST uint32_t *)live_in;
     __shared__ long long s_item;
+    __shared__ uint32_t s_bkey[kBinSlots];
+    __shared__ unsigned long long s_blo[kBinSlots], s_bhi[kBinSlots];
+    const bool any_bins = chdr->any_bins != 0;
+    if (any_bins)
+        for (int k = threadIdx.x; k < kBinSlots; k += kBlock) {
+            s_bkey[k] = kNoBinKey;
+            s_blo[k] = s_bhi[k] = 0ull;
+        }
+    const BinTable tab{s_bkey, s_blo, s_bhi};
     const int32_t nstreams = chdr->nstreams;
     const int64_t total = chdr->total_items;
     const int trow = threadIdx.x >> 3, tcol = (threadIdx.x & 7) * 4;
@@ -570,8 +604,8 @@ __global__ __launch_bounds__(kBlock) void k_wave(char *__restrict__ ws, const ui
                                                    in, full, group_word);
                 } else {
                     if (S.bins) {
-                        if (S.dtype == UVL_U8) wave_bins<uint8_t>(S, t, val, wr, in, cov, full);
-                        else wave_bins<uint16_t>(S, t, val, wr, in, cov, full);
+                        if (S.dtype == UVL_U8) wave_bins<uint8_t>(S, si, tab, t, val, wr, in, cov, full);
+                        else wave_bins<uint16_t>(S, si, tab, t, val, wr, in, cov, full);
                     }
                     if (S.dtype == UVL_U8) wave_store<uint8_t>(static_cast<uint8_t *>(S.layer), t, val, wr, in, full);
                     else wave_store<uint16_t>(static_cast<uint16_t *>(S.layer), t, val, wr, in, full);
@@ -579,6 +613,18 @@ __global__ __launch_bounds__(kBlock) void k_wave(char *__restrict__ ws, const ui
             };
             if (S.numeric) tile(std::true_type{});
             else tile(std::false_type{});
+        }
+    }
+    // the workgroup's area changes to the streams' bins
+    if (any_bins) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < kBinSlots; k += kBlock) {
+            const uint32_t key = s_bkey[k];
+            if (key == kNoBinKey) continue;
+            const UVL_CONST WaveStream &S = streams[key >> 16];
+            const uint32_t label = key & 0xffffu;
+            if (s_blo[k]) atomicAdd(S.bins + label, s_blo[k]);
+            if (S.aw_hi && s_bhi[k]) atomicAdd(S.bins + S.nbins + label, s_bhi[k]);
         }
     }
 }
@@ -935,7 +981,9 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
         }
     }
     hdr->nstreams = (int32_t)keys.size();
-    hdr->pad = 0;
+    hdr->any_bins = 0;
+    for (size_t k = 0; k < keys.size(); ++k)
+        if (S[k].bins) hdr->any_bins = 1;
     hdr->total_cull_waves = cwaves;
     hdr->total_items = 0;
     hdr->total_out = nout_total;

@@ -37,7 +37,7 @@ class Model:
             self.layers = [pool.alloc(width, height, dt) for dt in layer_dtypes]
         self.depth_w, self.depth_h, self.bias = int(depth_w), int(depth_h), float(bias)
         self.device = device
-        self.build_ws = torch.empty(uvl.lib().uvl_build_workspace_bytes(self.mesh.nt), dtype=torch.uint8,
+        self.build_ws = torch.empty(uvl.lib().uvl_build_workspace_bytes(self.mesh.nt, width, height), dtype=torch.uint8,
                                     device=device)
         self.depth_ws = uvl.depth_workspace(self.mesh)
         self._depth: "OrderedDict[int, torch.Tensor]" = OrderedDict()

@@ -76,7 +76,7 @@ _F64 = ctypes.c_double
 SIGNATURES = {
     "uvl_status_str": ([_I32], ctypes.c_char_p),
     "uvl_device_check": ([], _I32),
-    "uvl_build_workspace_bytes": ([_I64], _SZ),
+    "uvl_build_workspace_bytes": ([_I64, _I32, _I32], _SZ),
     "uvl_geom_bytes": ([_I32, _I32, _U32], _SZ),
     "uvl_build_geometry_image": ([_P, _P, _P, _SZ, _P], _I32),
     "uvl_create_layer": ([_P, _P], _I32),
@@ -368,7 +368,7 @@ class NumericLayer:
 def build_geometry_image(mesh: DeviceMesh, geom: GeometryImage, workspace: Optional[torch.Tensor] = None,
                          stream=None) -> GeometryImage:
     L = _lib()
-    need = L.uvl_build_workspace_bytes(mesh.nt)
+    need = L.uvl_build_workspace_bytes(mesh.nt, geom.width, geom.height)
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=mesh.pos.device)
     st = L.uvl_build_geometry_image(ctypes.byref(mesh.c), ctypes.byref(geom.c), _ptr(workspace),

@@ -181,7 +181,8 @@ def test_build_and_depth_validation(uvl):
     L = uvl.lib()
     m = uvl.CMesh(FAKE, None, FAKE, FAKE, 10, 4)
     g = _geom(uvl)
-    ws_need = L.uvl_build_workspace_bytes(4)
+    ws_need = L.uvl_build_workspace_bytes(4, 64, 32)
+    assert L.uvl_build_workspace_bytes(4, 0, 32) == 0 and L.uvl_build_workspace_bytes(-1, 64, 32) == 0
     assert ws_need >= 4 * 12
     assert L.uvl_build_geometry_image(ctypes.byref(m), ctypes.byref(g), FAKE, ws_need - 1, None) == -4
     g.width = 40000

@@ -99,7 +99,7 @@ def test_two_word_texel_areas(gpu, orc):
     assert og.w[cov].max() / og.w[cov].min() > 1e5
     # one word: refused (the planes are still written)
     g1 = gpu.GeometryImage(W, H)
-    ws = torch.empty(gpu.lib().uvl_build_workspace_bytes(dm.nt), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(gpu.lib().uvl_build_workspace_bytes(dm.nt, W, H), dtype=torch.uint8, device="cuda")
     st = gpu.lib().uvl_build_geometry_image(ctypes.byref(dm.c), ctypes.byref(g1.c), ws.data_ptr(), ws.numel(), None)
     assert st == gpu.E_RANGE
     # the binding rebuilds with two words
