@@ -48,6 +48,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz (one
+# non-packed operation per lane per clock) = 39.3e12 lane-operations/s, i.e.
+# 614e9 wave64 instructions/s
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+HOST_CORE_CAP = 16          # the GPU machine's host share for one GPU
 
 
 def log(msg):
@@ -64,7 +69,8 @@ def parse():
                         "also applied as waves of 256; tiny: the vessel")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-rows", type=int, default=64, help="atlas rows in the oracle's timed sample")
-    p.add_argument("--cpu-edits", type=int, default=200, help="edits in the oracle's timed sample")
+    p.add_argument("--cpu-edits", type=int, default=None,
+                   help="edits in the oracle's timed sample (default 200; 100 for --workload max)")
     p.add_argument("--batch-models", type=int, default=256,
                    help="models in the batched-wave comparison (0: skip it)")
     p.add_argument("--serve-models", type=int, default=32,
@@ -534,7 +540,8 @@ def cpu_baseline(wl, wl_name, rows, n_edits):
     t3 = time.perf_counter()
     texels = rows * wl.W * len(edits)
     single = texels / (t3 - t2)
-    procs = max(1, min(16, os.cpu_count() or 1, wl.H // rows))
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    procs = max(1, min(HOST_CORE_CAP, avail, wl.H // rows))
     ctx = mp.get_context("spawn")           # fresh interpreters: nothing inherited from the GPU process
     with ctx.Manager() as mgr:
         barrier = mgr.Barrier(procs + 1)
@@ -544,20 +551,34 @@ def cpu_baseline(wl, wl_name, rows, n_edits):
             ta = time.perf_counter()
             res.get()
             wall = time.perf_counter() - ta
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
+    value = procs * texels / wall
     return {
-        "value": procs * texels / wall, "unit": "edited texels/s", "cores": procs, "kind": "oracle",
+        "value": value, "unit": "edited texels/s", "cores": procs, "kind": "oracle",
         "single_thread_value": single,
-        "sample": (f"{procs} processes, each atlas rows of its own {rows}-row band ({rows * wl.W} texels) x the "
+        "host": {"nproc": os.cpu_count(), "affinity_cpus": avail, "cpu_model": model,
+                 "process_cap": HOST_CORE_CAP},
+        # the step's edits over the whole atlas at the sampled rate
+        "extrapolated_step_edits_s": len(wl.edits) * wl.W * wl.H / value,
+        "sample": (f"{procs} processes (one per host core, at most {HOST_CORE_CAP}: the box's share for one GPU), "
+                   f"each atlas rows of its own {rows}-row band ({rows * wl.W} texels) x the "
                    f"first {len(edits)} edits, wall time from a common start; single thread on rows 0-{rows - 1}: "
                    f"geometry band {t1 - t0:.2f} s, {len(cache)} depth maps {t2 - t1:.2f} s, "
                    f"edits {t3 - t2:.2f} s"),
     }
 
 
-def traffic_from_profiles(kernel_key, src_files):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources (else null)."""
-    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+def counters_from_profiles(kernel_key, src_files):
+    """Per-launch counter figures of a kernel from the committed rocprofv3
+    summary (HBM bytes from FETCH_SIZE / WRITE_SIZE, VALU wave instructions
+    from SQ_INSTS_VALU), if it was taken on the current kernel sources (else
+    null)."""
+    path = os.path.join(ROOT, "profiles", "pmc_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -569,7 +590,23 @@ def traffic_from_profiles(kernel_key, src_files):
     ent = rec.get(kernel_key)
     if not ent or ent.get("source_sha256") != h.hexdigest():
         return None
-    return ent.get("bytes_per_launch")
+    return ent
+
+
+def headline_roofline(kernel, rl):
+    """The contract's roofline object for the dominant kernel: against HBM,
+    or against the VALU issue peak when the measured instruction count
+    bounds it more tightly (both fractions kept)."""
+    out = {"kernel": kernel, "bytes_per_launch": rl["bytes_per_launch"], "avg_us": rl["avg_us"],
+           "traffic": rl["traffic"], "hbm_frac": rl["frac"], "valu_frac": rl["valu_frac"]}
+    if rl["bound"] == "alu":
+        achieved = rl["valu_frac"] * VALU_PEAK_LANE_OPS / 1e12
+        out.update({"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_LANE_OPS / 1e12,
+                    "unit": "T VALU lane-ops/s", "frac": rl["valu_frac"]})
+    else:
+        out.update({"bound": "hbm", "achieved": rl["achieved"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                    "frac": rl["frac"]})
+    return out
 
 
 def main():
@@ -610,28 +647,55 @@ def main():
     ms_step = 1e3 * dt / args.steps
     value = n_edits * N * args.steps / dt
 
-    # roofline of the dominant edit kernel (algorithmic bytes: 12 B of
-    # positions per texel; lassos also read their depth map once)
+    # algorithmic bytes per launch (what the method must move):
+    #   brush: 12 B of positions per texel; lasso: the same plus its depth
+    #   map once; layer operation: the operands and the destination per
+    #   texel (REMAP: one operand); area: the texel weight and every layer's
+    #   label per texel; geometry image: 40 B of planes per texel (tri_id,
+    #   position, normal, barycentrics, area), the tile bounds, and the mesh
+    #   (positions, normals, uv per vertex, indices per triangle); depth map:
+    #   4 B per pixel written and the mesh's positions and indices read
     dw, dh = wl.depth_w, wl.depth_h
-    per_launch = {"edit_brush": 12.0 * N, "edit_lasso": 12.0 * N + 4.0 * dw * dh}
-    kern = max(("edit_brush", "edit_lasso"), key=lambda k: stats.get(k, {"total_ms": 0})["total_ms"])
-    avg_s = stats[kern]["avg_us"] * 1e-6
-    achieved = per_launch[kern] / avg_s / 1e9
-    srcs = ["paper_2501_14807_amd/csrc/edit.hip", "paper_2501_14807_amd/csrc/edit_texel.h",
-            "paper_2501_14807_amd/csrc/sink.h"]
-    # the committed counter summary was taken on the scan-scale workload
-    traffic = traffic_from_profiles(kern, srcs) if args.workload == "scan" else None
-    kernels = {}
-    for k, s in stats.items():
-        ent = dict(s)
+    lb = [1 if dt_ == uvl.U8 else 2 for dt_ in wl.layer_dtypes]
+    nv, nt = wl.mesh.pos.shape[0], wl.mesh.tri.shape[0]
+    tiles = -(-wl.W // 32) * -(-wl.H // 32)
+    op_bytes = [N * (lb[o.a] + lb[o.dst] + (0 if o.op == uvl.REMAP else lb[o.b])) for o in wl.ops]
+    per_launch = {
+        "edit_brush": 12.0 * N,
+        "edit_lasso": 12.0 * N + 4.0 * dw * dh,
+        "layer_op": float(sum(op_bytes)) / max(1, len(op_bytes)),
+        "area_query": float(N * (4 + sum(lb))),
+        "build_geometry_image": 40.0 * N + 24.0 * tiles + 32.0 * nv + 12.0 * nt,
+        "render_depth": 4.0 * dw * dh + 12.0 * nv + 12.0 * nt,
+    }
+    edit_src = ["paper_2501_14807_amd/csrc/edit.hip", "paper_2501_14807_amd/csrc/edit_texel.h",
+                "paper_2501_14807_amd/csrc/sink.h"]
+    # the committed counter summaries were taken on the scan-scale workload
+    counters = {k: counters_from_profiles(k, edit_src) if args.workload == "scan" else None
+                for k in ("edit_brush", "edit_lasso")}
+    rooflines, kernels = {}, {}
+    for k, st in stats.items():
+        ent = dict(st)
         if k in per_launch:
-            ent["gbps"] = per_launch[k] / (s["avg_us"] * 1e-6) / 1e9
-            ent["texels_per_s"] = N / (s["avg_us"] * 1e-6)
+            avg_s = st["avg_us"] * 1e-6
+            gbps = per_launch[k] / avg_s / 1e9
+            ent["gbps"] = gbps
+            if k.startswith("edit_"):
+                ent["texels_per_s"] = N / avg_s
+            rl = {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                  "frac": gbps / HBM_PEAK_GBPS, "bytes_per_launch": per_launch[k], "avg_us": st["avg_us"],
+                  "traffic": None, "valu_frac": None}
+            c = counters.get(k)
+            if c:
+                rl["traffic"] = c.get("bytes_per_launch")
+                if c.get("valu_insts_per_launch"):
+                    # measured VALU wave instructions per launch against the issue peak
+                    rl["valu_frac"] = c["valu_insts_per_launch"] * 64 / avg_s / VALU_PEAK_LANE_OPS
+                    if rl["valu_frac"] > rl["frac"]:
+                        rl["bound"] = "alu"
+            rooflines[k] = rl
         kernels[k] = ent
-    layer_bytes = [1 if dt_ == uvl.U8 else 2 for dt_ in wl.layer_dtypes]
-    if "area_query" in stats:
-        ab = N * (4 + sum(layer_bytes))
-        kernels["area_query"]["gbps"] = ab / (stats["area_query"]["avg_us"] * 1e-6) / 1e9
+    kern = max(("edit_brush", "edit_lasso"), key=lambda k: stats.get(k, {"total_ms": 0})["total_ms"])
     tool = padding = numeric = radius = max_waves = None
     if args.workload == "max":
         max_waves = bench_max_waves(m, wl, uvl, torch)
@@ -682,9 +746,8 @@ def main():
                    "edits_per_step": n_edits, "layer_ops_per_step": len(wl.ops),
                    "depth_map": [dw, dh], "parallelism": "single GPU"},
         "edits_per_s": n_edits * args.steps / dt,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic, "kernel": kern,
-                     "bytes_per_launch": per_launch[kern], "avg_us": stats[kern]["avg_us"]},
+        "roofline": headline_roofline(kern, rooflines[kern]),
+        "rooflines": rooflines,
         "kernels": kernels,
         "copy_gbps": copy_gbps,
         "tool": tool,
@@ -697,7 +760,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(wl, args.workload, args.cpu_rows, args.cpu_edits)
+        n_cpu = args.cpu_edits if args.cpu_edits is not None else (100 if args.workload == "max" else 200)
+        out["cpu_baseline"] = cpu_baseline(wl, args.workload, args.cpu_rows, n_cpu)
         log("oracle sample done")
     print(json.dumps(out), flush=True)
 

@@ -19,11 +19,12 @@
 //      to "no owner" in the tri_id plane, then a workgroup per triangle
 //      rasterises it with atomicMin into that plane;
 //   4. k_tile, a 256-thread workgroup per tile: its triangles' records,
-//      vertex positions and normals staged in LDS, ownership resolved with
-//      64-bit LDS atomicMin on (triangle, LDS slot), starting from the plane
-//      for marked tiles; then every texel's attributes from its owner's
-//      record (fp64, in the order the definition gives), the area weight
-//      quantised, and the tile's position bounds, all written once.
+//      vertex positions and normals staged in LDS (a small hash maps a
+//      triangle index to its record), ownership resolved with LDS
+//      atomicMin, starting from the plane for marked tiles; then every
+//      texel's attributes from its owner's record (fp64, in the order the
+//      definition gives), the area weight quantised, and the tile's
+//      position bounds, all written once.
 // The area scale comes from the largest weight among the triangles whose
 // box holds a texel centre (found in step 1), so the tile pass can quantise
 // at once; it also finds the smallest owner weight for the range check.
@@ -45,7 +46,7 @@ constexpr int kMaxSpan = 4;                     // tiles a binned triangle may s
 constexpr int kBigGrid = 2048;
 constexpr int kScanThreads = 1024, kScanPer = 8, kScanSpan = kScanThreads * kScanPer;
 constexpr int32_t kNoOwner = 0x7fffffff;
-constexpr unsigned long long kEmptyKey = ~0ull;
+constexpr int kHashBits = 8, kHashSlots = 1 << kHashBits;   // staged records by triangle index
 
 // Largest ratio of texel weights for which one rounding onto the scale's
 // grid stays within 2^-20 relative: one word (largest weight in [2^30,
@@ -72,12 +73,48 @@ struct alignas(16) TriRec {
 };
 static_assert(sizeof(TriRec) == 64, "one 64-byte record per triangle");
 
-struct TileRec {
-    TriRec r;
-    float P[9];          // vertex positions, original order
-    float N[9];          // vertex normals (when the mesh has them)
-    float pad[2];
+// The staged records of a tile, one array per field: lanes reading
+// consecutive records touch consecutive banks (an array of 160-byte records
+// put every 4th lane on one bank).
+struct TileRecs {
+    long long C[3][kTileRecs];
+    long long E[kTileRecs];
+    double w[kTileRecs];                // texel weight
+    double rE[kTileRecs];               // 1 / |E|, correctly rounded
+    unsigned long long q[kTileRecs];    // the quantised texel weight (one or two words)
+    int A[3][kTileRecs], B[3][kTileRecs];
+    float P[9][kTileRecs];              // vertex positions, original order
+    float N[9][kTileRecs];              // vertex normals (when the mesh has them)
+
+    __device__ __forceinline__ TriRec rec(int k) const {
+        TriRec R;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            R.C[v] = C[v][k];
+            R.A[v] = A[v][k];
+            R.B[v] = B[v][k];
+        }
+        R.E = E[k];
+        R.w = w[k];
+        return R;
+    }
 };
+
+// The quantised texel weight of a triangle: the largest weight of the
+// image maps into [2^30, 2^31) (one word) or [2^62, 2^63) (two words).
+__device__ __forceinline__ unsigned long long quantise(double w, int ex, bool wide) {
+    return wide ? (unsigned long long)rint(ldexp(w, 63 - ex)) : (unsigned long long)rint(ldexp(w, 31 - ex));
+}
+
+// b = e / E correctly rounded from r = RN(1 / E): q0 = RN(e r) is within an
+// ulp of e / E, the remainder e - E q0 is exact (one fma), and q0 + rem r
+// rounded once is the correctly rounded quotient (Markstein's theorem; e
+// and E are integers below 2^53, far from overflow and underflow).
+__device__ __forceinline__ double div_by(double e, double E, double r) {
+    const double q0 = e * r;
+    const double rem = fma(-q0, E, e);
+    return fma(rem, r, q0);
+}
 
 struct GeomArgs {
     const float *uv, *pos, *nrm;
@@ -122,16 +159,43 @@ __device__ __forceinline__ bool geom_tri(const GeomArgs &a, int64_t t, Tri2 &T, 
     return tri_setup(T);
 }
 
+// Slots in the tiles' lists for one entry per lane (tile < 0: none): the
+// lanes asking for one tile get consecutive slots from a single atomic add
+// by the first of them, since neighbouring triangles share tiles and one
+// counter hit by a whole wave would serialise.  All lanes take part.
+__device__ __forceinline__ int wave_slot(unsigned *__restrict__ count, int tile) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    bool pend = tile >= 0;
+    int slot = -1;
+    for (;;) {
+        const unsigned long long m = __builtin_amdgcn_ballot_w64(pend);
+        if (m == 0) break;
+        const int leader = __builtin_ctzll(m);
+        const int lt = __shfl(tile, leader);
+        const bool same = pend && tile == lt;
+        const unsigned long long group = __builtin_amdgcn_ballot_w64(same);
+        unsigned base = 0;
+        if (lane == leader) base = atomicAdd(count + lt, (unsigned)__builtin_popcountll(group));
+        base = __shfl(base, leader);
+        if (same) {
+            slot = (int)(base + (unsigned)__builtin_popcountll(group & below));
+            pend = false;
+        }
+    }
+    return slot;
+}
+
 // 1. set-up, binning counts, queue of large triangles, largest weight
 __global__ __launch_bounds__(kBlock) void k_setup(GeomArgs a) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double wmax = 0.0;
+    int tiles[kMaxSpan] = {-1, -1, -1, -1};
     if (t < a.nt) {
         Tri2 T;
         int v[3];
         TriRec R{};
         int4 box = make_int4(0, -1, 0, -1);
-        int4 sl = make_int4(-1, -1, -1, -1);
         if (geom_tri(a, t, T, v)) {
             // texel area weight 131072 A3 / |E| (surface area per 1/(W H) of UV area)
             double P[3][3];
@@ -168,12 +232,9 @@ __global__ __launch_bounds__(kBlock) void k_setup(GeomArgs a) {
                 const int tx0 = i0 / kTile, ty0 = j0 / kTile;
                 const int wx = i1 / kTile - tx0 + 1, span = wx * (j1 / kTile - ty0 + 1);
                 if (span <= kMaxSpan) {
-                    int s[kMaxSpan];
 #pragma unroll
                     for (int k = 0; k < kMaxSpan; ++k)
-                        s[k] = k < span ? (int)atomicAdd(a.tcount + (int64_t)(ty0 + k / wx) * a.tiles_x + tx0 + k % wx, 1u)
-                                        : -1;
-                    sl = make_int4(s[0], s[1], s[2], s[3]);
+                        if (k < span) tiles[k] = (ty0 + k / wx) * a.tiles_x + tx0 + k % wx;
                 } else {
                     a.big[atomicAdd(&a.ctr->big_len, 1u)] = (unsigned)t;
                 }
@@ -181,8 +242,11 @@ __global__ __launch_bounds__(kBlock) void k_setup(GeomArgs a) {
         }
         a.recs[t] = R;
         a.boxes[t] = box;
-        a.slots[t] = sl;
     }
+    int s[kMaxSpan];
+#pragma unroll
+    for (int k = 0; k < kMaxSpan; ++k) s[k] = wave_slot(a.tcount, tiles[k]);
+    if (t < a.nt) a.slots[t] = make_int4(s[0], s[1], s[2], s[3]);
     // one atomic per workgroup at most: the counter only grows, so a value
     // read is a lower bound of the final one
     __shared__ double s_w[kBlock / 64];
@@ -328,7 +392,7 @@ __global__ __launch_bounds__(kBlock) void k_big_raster(GeomArgs a, int32_t *__re
 // Owner candidates of one triangle over cells [bi0, bi1] x [bj0, bj1] of
 // the tile at (ti0, tj0), by one thread: incremental edge functions.
 __device__ __forceinline__ void raster_cells(const TriRec &R, int bi0, int bi1, int bj0, int bj1, int ti0, int tj0,
-                                             unsigned long long key, unsigned long long *own) {
+                                             int32_t key, int32_t *own) {
     const long long px0 = 256LL * bi0 + 128;
     long long s[3], bs[3];
 #pragma unroll
@@ -341,7 +405,7 @@ __device__ __forceinline__ void raster_cells(const TriRec &R, int bi0, int bi1, 
         long long e[3];
 #pragma unroll
         for (int v = 0; v < 3; ++v) e[v] = (long long)R.A[v] * px0 + (long long)R.B[v] * py + R.C[v] - bs[v];
-        unsigned long long *row = own + (j - tj0) * kTile - ti0;
+        int32_t *row = own + (j - tj0) * kTile - ti0;
         for (int i = bi0; i <= bi1; ++i) {
             if ((e[0] | e[1] | e[2]) >= 0) atomicMin(row + i, key);
 #pragma unroll
@@ -364,8 +428,10 @@ __device__ __forceinline__ float wave_maxf(float x) {
 
 // 4. a workgroup per tile: ownership in LDS, then attributes written once
 __global__ __launch_bounds__(kTileThreads) void k_tile(GeomArgs a, GeomOut g) {
-    __shared__ unsigned long long s_own[kTileTexels];
-    __shared__ TileRec s_rec[kTileRecs];
+    __shared__ int32_t s_own[kTileTexels];
+    __shared__ TileRecs s_rec;
+    __shared__ int32_t s_hkey[kHashSlots];
+    __shared__ int32_t s_hval[kHashSlots];
     __shared__ int s_coop[kMaxCoop];
     __shared__ int s_ncoop;
     __shared__ float s_red[7][kTileThreads / 64];
@@ -377,26 +443,42 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(GeomArgs a, GeomOut g) {
     const bool marked = a.tflag[tile] != 0u;
     for (int c = threadIdx.x; c < kTileTexels; c += kTileThreads) {
         const int i = ti0 + (c % kTile), j = tj0 + (c / kTile);
-        unsigned long long k = kEmptyKey;
-        if (marked && i < W && j < H) {
-            const int32_t o = g.tri_id[(int64_t)j * W + i];
-            if (o != kNoOwner) k = ((unsigned long long)(uint32_t)o << 32) | 0xffffffffull;
-        }
-        s_own[c] = k;
+        s_own[c] = marked && i < W && j < H ? g.tri_id[(int64_t)j * W + i] : kNoOwner;
     }
+    for (int h = threadIdx.x; h < kHashSlots; h += kTileThreads) s_hkey[h] = -1;
     if (threadIdx.x == 0) s_ncoop = 0;
+    __syncthreads();
+    int ex;
+    const double mx = __longlong_as_double((long long)a.ctr->max_w_bits);
+    frexp(mx, &ex);
+    const bool wide = g.aw_hi != nullptr;
     const int nstage = cnt < (unsigned)kTileRecs ? (int)cnt : kTileRecs;
     for (int k = threadIdx.x; k < nstage; k += kTileThreads) {
         const int32_t t = a.list[off + k];
-        TileRec &S = s_rec[k];
-        S.r = a.recs[t];
+        const TriRec R = a.recs[t];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            s_rec.C[v][k] = R.C[v];
+            s_rec.A[v][k] = R.A[v];
+            s_rec.B[v][k] = R.B[v];
+        }
+        s_rec.E[k] = R.E;
+        s_rec.w[k] = R.w;
+        s_rec.rE[k] = 1.0 / (double)R.E;
+        s_rec.q[k] = quantise(R.w, ex, wide);
+        // triangle index -> LDS slot (open addressing; a triangle is listed once)
+        for (uint32_t h = ((uint32_t)t * 2654435761u) >> (32 - kHashBits);; h = (h + 1) & (kHashSlots - 1))
+            if (atomicCAS(&s_hkey[h], -1, t) == -1) {
+                s_hval[h] = k;
+                break;
+            }
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int64_t v = a.tri[3 * (int64_t)t + q];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                S.P[3 * q + c] = a.pos[3 * v + c];
-                S.N[3 * q + c] = a.nrm ? a.nrm[3 * v + c] : 0.0f;
+                s_rec.P[3 * q + c][k] = a.pos[3 * v + c];
+                s_rec.N[3 * q + c][k] = a.nrm ? a.nrm[3 * v + c] : 0.0f;
             }
         }
     }
@@ -405,7 +487,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(GeomArgs a, GeomOut g) {
     // tile are left to the whole workgroup
     for (int k = threadIdx.x; k < (int)cnt; k += kTileThreads) {
         const int32_t t = a.list[off + k];
-        const TriRec R = k < kTileRecs ? s_rec[k].r : a.recs[t];
+        const TriRec R = k < kTileRecs ? s_rec.rec(k) : a.recs[t];
         const int4 b = a.boxes[t];
         const int bi0 = max(b.x, ti0), bi1 = min(b.y, ti0 + kTile - 1);
         const int bj0 = max(b.z, tj0), bj1 = min(b.w, tj0 + kTile - 1);
@@ -417,30 +499,25 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(GeomArgs a, GeomOut g) {
                 continue;
             }
         }
-        const unsigned long long key = ((unsigned long long)(uint32_t)t << 32) | (k < kTileRecs ? (unsigned)k : 0xffffffffu);
-        raster_cells(R, bi0, bi1, bj0, bj1, ti0, tj0, key, s_own);
+        raster_cells(R, bi0, bi1, bj0, bj1, ti0, tj0, t, s_own);
     }
     __syncthreads();
     const int ncoop = s_ncoop < kMaxCoop ? s_ncoop : kMaxCoop;
     for (int q = 0; q < ncoop; ++q) {
         const int k = s_coop[q];
         const int32_t t = a.list[off + k];
-        const TriRec R = k < kTileRecs ? s_rec[k].r : a.recs[t];
+        const TriRec R = k < kTileRecs ? s_rec.rec(k) : a.recs[t];
         const int4 b = a.boxes[t];
         const int bi0 = max(b.x, ti0), bi1 = min(b.y, ti0 + kTile - 1);
         const int bj0 = max(b.z, tj0), bj1 = min(b.w, tj0 + kTile - 1);
         const int bw = bi1 - bi0 + 1, cells = bw * (bj1 - bj0 + 1);
-        const unsigned long long key = ((unsigned long long)(uint32_t)t << 32) | (k < kTileRecs ? (unsigned)k : 0xffffffffu);
         for (int c = threadIdx.x; c < cells; c += kTileThreads) {
             const int i = bi0 + c % bw, j = bj0 + c / bw;
-            if (inside(R, 256LL * i + 128, 256LL * j + 128)) atomicMin(&s_own[(j - tj0) * kTile + (i - ti0)], key);
+            if (inside(R, 256LL * i + 128, 256LL * j + 128)) atomicMin(&s_own[(j - tj0) * kTile + (i - ti0)], t);
         }
     }
     __syncthreads();
     // attributes, every plane written once per texel
-    int ex;
-    const double mx = __longlong_as_double((long long)a.ctr->max_w_bits);
-    frexp(mx, &ex);
     const double wfloor = ldexp(mx, -kWideRatioLog2);
     float mn[3] = {INFINITY, INFINITY, INFINITY}, mxp[3] = {-INFINITY, -INFINITY, -INFINITY};
     double wmin = INFINITY;
@@ -449,8 +526,8 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(GeomArgs a, GeomOut g) {
         const int i = ti0 + (c % kTile), j = tj0 + (c / kTile);
         if (i >= W || j >= H) continue;
         const int64_t idx = (int64_t)j * W + i;
-        const unsigned long long key = s_own[c];
-        if (key == kEmptyKey) {
+        const int32_t t = s_own[c];
+        if (t == kNoOwner) {
             g.tri_id[idx] = -1;
             g.px[idx] = g.py[idx] = g.pz[idx] = nan;
             if (g.nx) g.nx[idx] = g.ny[idx] = g.nz[idx] = 0.0f;
@@ -459,19 +536,32 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(GeomArgs a, GeomOut g) {
             if (g.aw_hi) g.aw_hi[idx] = 0u;
             continue;
         }
-        const int32_t t = (int32_t)(key >> 32);
-        const unsigned slot = (unsigned)key;
+        unsigned slot = 0xffffffffu;          // the owner's LDS record, if staged
+        for (uint32_t h = ((uint32_t)t * 2654435761u) >> (32 - kHashBits);; h = (h + 1) & (kHashSlots - 1)) {
+            const int32_t key = s_hkey[h];
+            if (key == t) {
+                slot = (unsigned)s_hval[h];
+                break;
+            }
+            if (key == -1) break;
+        }
         TriRec R;
         float P[9], N[9];
+        double rE;
+        unsigned long long qw;
         if (slot < (unsigned)kTileRecs) {
-            R = s_rec[slot].r;
+            R = s_rec.rec(slot);
+            rE = s_rec.rE[slot];
+            qw = s_rec.q[slot];
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
-                P[q] = s_rec[slot].P[q];
-                N[q] = s_rec[slot].N[q];
+                P[q] = s_rec.P[q][slot];
+                N[q] = s_rec.N[q][slot];
             }
         } else {
             R = a.recs[t];
+            rE = 1.0 / (double)R.E;
+            qw = quantise(R.w, ex, wide);
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 const int64_t v = a.tri[3 * (int64_t)t + q];
@@ -486,7 +576,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(GeomArgs a, GeomOut g) {
         const double E = (double)R.E;
         double b[3];
 #pragma unroll
-        for (int v = 0; v < 3; ++v) b[v] = (double)((long long)R.A[v] * px + (long long)R.B[v] * py + R.C[v]) / E;
+        for (int v = 0; v < 3; ++v) b[v] = div_by((double)((long long)R.A[v] * px + (long long)R.B[v] * py + R.C[v]), E, rE);
         g.tri_id[idx] = t;
         if (g.b1) {
             g.b1[idx] = (float)b[1];
@@ -522,17 +612,13 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(GeomArgs a, GeomOut g) {
                 m[2] = u1[0] * u2[1] - u1[1] * u2[0];
             }
             const double len = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
-            g.nx[idx] = len > 0.0 ? (float)(m[0] / len) : 0.0f;
-            g.ny[idx] = len > 0.0 ? (float)(m[1] / len) : 0.0f;
-            g.nz[idx] = len > 0.0 ? (float)(m[2] / len) : 0.0f;
+            const double inv = len > 0.0 ? 1.0 / len : 0.0;
+            g.nx[idx] = (float)(m[0] * inv);
+            g.ny[idx] = (float)(m[1] * inv);
+            g.nz[idx] = (float)(m[2] * inv);
         }
-        if (!g.aw_hi) {
-            g.aw[idx] = (unsigned)rint(ldexp(R.w, 31 - ex));
-        } else {
-            const unsigned long long q = (unsigned long long)rint(ldexp(R.w, 63 - ex));
-            g.aw[idx] = (uint32_t)q;
-            g.aw_hi[idx] = (uint32_t)(q >> 32);
-        }
+        g.aw[idx] = (uint32_t)qw;
+        if (wide) g.aw_hi[idx] = (uint32_t)(qw >> 32);
         if (R.w >= wfloor) wmin = fmin(wmin, R.w);
     }
     // the tile's position bounds and the smallest owner weight
