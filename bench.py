@@ -78,6 +78,9 @@ def parse():
     p.add_argument("--serve-requests", type=int, default=100000, help="measured requests per rate")
     p.add_argument("--serve-warmup", type=int, default=5000, help="warm-up requests per rate")
     p.add_argument("--serve-slo-ms", type=float, default=10.0, help="the p99 bound both modes are compared at")
+    p.add_argument("--serve-rates", default=None,
+                   help="comma-separated offered rates (requests/s) instead of the default sweep")
+    p.add_argument("--serve-modes", default="plain,batched", help="serving modes to run (plain, batched)")
     return p.parse_args()
 
 
@@ -240,7 +243,8 @@ SERVE_SATURATED_MS = 200.0
 SERVE_SLOS_MS = (5.0, 10.0, 20.0)
 
 
-def bench_serving(n_each, n_requests, slo_ms, torch, uvl, warmup=5000):
+def bench_serving(n_each, n_requests, slo_ms, torch, uvl, warmup=5000, rates=SERVE_RATES,
+                  modes=("plain", "batched")):
     """Continuous batching against plain one-launch-per-request serving.
 
     n_each vessel-size models (512^2) and n_each scan-scale models (8192^2,
@@ -269,8 +273,8 @@ def bench_serving(n_each, n_requests, slo_ms, torch, uvl, warmup=5000):
     specs = [ModelSpec(m, s_, s_, dt, depth=d) for m, s_, dt, d in zip(meshes, sizes, dtypes, depth)]
     log(f"serving: {len(specs)} model specs after {time.perf_counter() - t:.1f} s")
     sweep = []
-    done = {"plain": False, "batched": False}
-    for qps in SERVE_RATES:
+    done = {m: m not in modes for m in ("plain", "batched")}
+    for qps in rates:
         if all(done.values()):
             break
         cams, stream = synth.serve_stream(meshes, dtypes, warmup + n_requests, qps, seed=int(qps))
@@ -726,8 +730,9 @@ def main():
         torch.cuda.empty_cache()
     serving = None
     if args.serve_models > 0 and args.workload != "max":
+        rates = SERVE_RATES if not args.serve_rates else tuple(float(x) for x in args.serve_rates.split(","))
         serving = bench_serving(args.serve_models, args.serve_requests, args.serve_slo_ms, torch, uvl,
-                                warmup=args.serve_warmup)
+                                warmup=args.serve_warmup, rates=rates, modes=tuple(args.serve_modes.split(",")))
 
     out = {
         "metric": "edited texels/s (% HBM peak); batched edits/s + p50/p99 latency vs plain",

@@ -562,3 +562,53 @@ def test_scan_full_size_sampled_rows(gpu, orc):
         workload.apply_edits(wl, og, L, edits, cache)
         for k, lay in enumerate(m.layers):
             assert np.array_equal(lay.data[sl].cpu().numpy(), L[k]), (r, k)
+
+
+def test_max_model_sampled_rows(gpu, orc):
+    """The 16384^2, 8,258,048-triangle model (256 charts) against the oracle
+    on sampled atlas rows, computed one band at a time: triangle ids and
+    positions bit-exact; the 32 layers after 160 edits bit-exact on those
+    rows; per-label areas of the sampled rows (a layer holding the edited
+    labels on those rows only, 16 wave units per row) within 1e-6, the
+    unlabelled bin aside (it also holds the texels off those rows)."""
+    from oracle import workload
+    from paper_2501_14807_amd.model import Model
+    wl = synth.max_workload(n_edits=160)
+    print(f"case: max model {wl.W}x{wl.H}, {wl.mesh.nt} triangles, 160 edits", flush=True)
+    m = Model.from_workload(wl).build()
+    m.apply_all(wl.edits, wl.cameras)
+    rng = np.random.default_rng(78)
+    rows = sorted(rng.choice(wl.H, size=6, replace=False).tolist())
+    cache = {}
+    W = wl.W
+    sampled = np.zeros(wl.W * wl.H, np.uint8)
+    w_rows, lab_rows = [], []
+    for r in rows:
+        og = orc.geometry_image(wl.mesh, wl.W, wl.H, rows=(r, r + 1))
+        sl = slice(r * W, (r + 1) * W)
+        assert np.array_equal(m.geom.tri_id[sl].cpu().numpy(), og.tri_id), r
+        assert np.array_equal(m.geom.pos[:, sl].cpu().numpy(), og.pos32, equal_nan=True), r
+        L = workload.new_layers(wl, W)
+        workload.apply_edits(wl, og, L, wl.edits, cache)
+        for k, lay in enumerate(m.layers):
+            assert np.array_equal(lay.data[sl].cpu().numpy(), L[k]), (r, k)
+        k_area = max(range(len(L)), key=lambda k: int((L[k] > 0).sum()))
+        sampled[sl] = m.layers[k_area].data[sl].cpu().numpy()
+        w_rows.append(og.w)
+        lab_rows.append(sampled[sl].copy())
+    assert sum(int((x > 0).sum()) for x in lab_rows) > 0
+    lay = gpu.Layer(wl.W, wl.H, gpu.U8)
+    lay.copy_from(sampled)
+    got = gpu.area_query(m.geom, [lay])[0]
+    w = np.concatenate(w_rows)
+    lab = np.concatenate(lab_rows)
+    ref = np.zeros(256)
+    for l in range(256):
+        sel = (lab == l) & (w > 0)
+        ref[l] = math.fsum(w[sel]) if sel.any() else 0.0
+    # bin 0 also holds every covered texel off the sampled rows
+    nz = ref > 0
+    nz[0] = False
+    assert nz.any()
+    assert np.allclose(got[nz], ref[nz], rtol=1e-6, atol=0)
+    assert (got[1:][~nz[1:]] == 0).all()
