@@ -238,7 +238,8 @@ def bench_batched(n_models, reps, torch, uvl):
 
 # offered request rates of the serving sweep (requests/s); a mode's sweep
 # stops once its p99 passes SERVE_SATURATED_MS (higher rates only queue more)
-SERVE_RATES = (8000.0, 12000.0, 16000.0, 24000.0, 32000.0, 40000.0, 48000.0, 56000.0, 64000.0, 72000.0, 80000.0)
+SERVE_RATES = (8000.0, 12000.0, 13000.0, 14000.0, 15000.0, 16000.0, 24000.0, 32000.0, 40000.0, 48000.0, 52000.0,
+               56000.0, 60000.0, 64000.0, 68000.0, 72000.0, 80000.0)
 SERVE_SATURATED_MS = 200.0
 SERVE_SLOS_MS = (5.0, 10.0, 20.0)
 
@@ -311,7 +312,8 @@ def bench_serving(n_each, n_requests, slo_ms, torch, uvl, warmup=5000, rates=SER
                             "ratio": (bb / bp) if bp and bb else None}
     return {"workload": f"{n_each} vessel-size (512^2) + {n_each} scan-scale (8192^2) models, u8+u16 layers, "
                         f"{warmup} warm-up + {n_requests} measured Poisson requests per rate, "
-                        f"60/25/10/5 brush/lasso/area/op; batched area answers from wave-maintained bins",
+                        f"60/25/10/5 brush/lasso/area/op; batched area answers from wave-maintained bins (a layer written by an op "
+                        f"is rescanned at its next area request)",
             "sweep": sweep, "slo_p99_ms": slo_ms, "at_p99_bound_ms": at,
             "plain_edits_per_s_at_slo": at[f"{slo_ms:g}"]["plain_edits_per_s"],
             "batched_edits_per_s_at_slo": at[f"{slo_ms:g}"]["batched_edits_per_s"],

@@ -12,20 +12,22 @@
 // (high sum * 2^32 + low sum) * area_scale.
 //
 // One pass reads every area weight from memory once for all the layers of
-// a query (up to 32).  A work unit is 4 rows x 1024 columns; a wave takes
-// units in turn, each lane holding 16 consecutive columns: it reads the
-// unit's weights once and keeps their per-row sums, then walks the layers,
-// loading each layer's 16 labels per row and adding runs of equal labels to
-// the workgroup's bins.  A row whose 16 labels are equal (the common case:
-// labelled regions are spatially coherent) is checked on the packed words
-// and adds its row sum; any other row reads its 16 weights again, from the
-// cache.  u8 layers add into 256
-// LDS bins each (native 64-bit LDS atomics); u16 layers (65536 bins) add
-// into an LDS hash table keyed by (layer, label), open addressing with
-// linear probing, falling back to the global bin only if 16 probes find no
-// slot.  The LDS bins go to the global bins once per workgroup.  A
-// workgroup is 16 waves with up to 88 KiB of LDS (gfx950 has 160 KiB per
-// CU), one workgroup per CU stride over the units.
+// a query (up to 32).  A work unit is 4 rows x 512 columns (2 rows with
+// two-word weights); a wave takes units in turn, each lane holding 8
+// consecutive columns: it loads the unit's weights into registers, where
+// they stay while the wave walks the layers, u8 layers first, requesting
+// the labels of up to four u8 layers before it sums any (a unit whose rows
+// and columns all exist has every load issued ahead of the first wait; a
+// ragged unit takes a path with per-row checks).  Per layer, runs of equal
+// labels go to the workgroup's bins; a row whose 8 labels are equal (the
+// common case: labelled regions are spatially coherent) is checked on the
+// packed words and adds its row sum.  u8 layers add into 256 LDS bins each
+// (native 64-bit LDS atomics); u16 layers (65536 bins) add into an LDS hash
+// table keyed by (layer, label), open addressing with linear probing,
+// falling back to the global bin only if 16 probes find no slot.  The LDS
+// bins go to the global bins once per workgroup.  A workgroup is 16 waves
+// with up to 88 KiB of LDS (gfx950 has 160 KiB per CU), one workgroup per
+// CU stride over the units.
 #include "uvl_internal.h"
 
 namespace uvl {
@@ -33,9 +35,10 @@ namespace {
 
 constexpr int kAreaBlock = 1024;          // 16 waves
 constexpr int kAreaWaves = kAreaBlock / 64;
-constexpr int kCols = 16;                 // columns per lane
+constexpr int kCols = 8;                  // columns per lane
 constexpr int kChunk = 64 * kCols;        // columns per wave unit
 constexpr int kMaxLayers = 32;
+constexpr int kU8Group = 4;               // u8 layers whose labels are loaded together
 constexpr int kHashBits = 11;
 constexpr int kHash = 1 << kHashBits;     // LDS hash slots for u16 labels
 constexpr uint32_t kEmptyKey = 0xffffffffu;
@@ -45,9 +48,8 @@ struct AreaArgs {
     const void *data[kMaxLayers];
     unsigned long long *bins[kMaxLayers];       // global low-word (or only) bins per layer
     unsigned long long *bins_hi[kMaxLayers];    // global high-word bins (two-word weights)
-    int32_t dtype[kMaxLayers];
-    int32_t row[kMaxLayers];                    // u8 layers: their LDS bin row
-    int32_t nl;
+    int32_t nu8;                                // layers [0, nu8) are u8 (LDS bin row = index),
+    int32_t nl;                                 // [nu8, nl) are u16
 };
 
 // A weight: one word, or a low and a high word.
@@ -91,23 +93,23 @@ struct Bins {
 };
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ uint4 ld16(const void *p) {
-    const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
-    return make_uint4(v.x, v.y, v.z, v.w);
-}
-
-// Labels of one row of a lane: the packed words (u8: 4, u16: 8).
+// Labels of one row of a lane: the packed words (u8: 2, u16: 4).
 template <typename T>
 struct RowLabels {
     static constexpr int kWords = kCols * sizeof(T) / 4;
     uint32_t w[kWords];
 
+    // streamed once: non-temporal loads of 8 (u8) or 16 (u16) bytes
     __device__ __forceinline__ void load_vec(const T *p) {
-#pragma unroll
-        for (int q = 0; q < kWords / 4; ++q) {
-            const uint4 v = ld16(p + q * (16 / sizeof(T)));
-            w[4 * q] = v.x; w[4 * q + 1] = v.y; w[4 * q + 2] = v.z; w[4 * q + 3] = v.w;
+        if constexpr (kWords == 4) {
+            const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+            w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+        } else {
+            static_assert(kWords == 2, "8 columns of u8 or u16 labels");
+            const u32x2 v = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p));
+            w[0] = v.x; w[1] = v.y;
         }
     }
     // ragged columns: labels past the row's end repeat the first one
@@ -129,7 +131,7 @@ struct RowLabels {
         constexpr int kPerWord = 4 / sizeof(T);
         return (w[k / kPerWord] >> (8 * sizeof(T) * (k % kPerWord))) & (sizeof(T) == 1 ? 0xffu : 0xffffu);
     }
-    // all 16 labels equal: every word equal and made of one repeated label
+    // all kCols labels equal: every word equal and made of one repeated label
     __device__ __forceinline__ bool uniform() const {
         bool eq = true;
 #pragma unroll
@@ -139,73 +141,75 @@ struct RowLabels {
     }
 };
 
-// A unit's per-row weight sums.  The individual weights are not kept: a
-// row whose labels are not all equal reads its 16 weights again (cache
-// hits: the unit's weights were read just before).
+// A unit's weights, held in registers for all the layers of the query,
+// and their per-row sums.
 template <bool kWide, int kRows>
-struct UnitSums {
+struct UnitWeights {
+    uint32_t lo[kRows][kCols];
+    uint32_t hi[kWide ? kRows : 1][kWide ? kCols : 1];
     Sum<kWide> tot[kRows];
 };
 
-template <bool kWide>
-__device__ __forceinline__ void row_weights(const uint32_t *__restrict__ aw, const uint32_t *__restrict__ aw_hi,
-                                            int64_t t, int ncol, bool vec, uint32_t lo[kCols], uint32_t hi[kCols]) {
-    if (vec) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(aw + t + 4 * q);
-            lo[4 * q] = v.x; lo[4 * q + 1] = v.y; lo[4 * q + 2] = v.z; lo[4 * q + 3] = v.w;
-            if constexpr (kWide) {
-                const uint4 h = *reinterpret_cast<const uint4 *>(aw_hi + t + 4 * q);
-                hi[4 * q] = h.x; hi[4 * q + 1] = h.y; hi[4 * q + 2] = h.z; hi[4 * q + 3] = h.w;
-            }
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < kCols; ++k) {
-            lo[k] = k < ncol ? aw[t + k] : 0u;
-            if constexpr (kWide) hi[k] = k < ncol ? aw_hi[t + k] : 0u;
-        }
-    }
-}
-
-template <bool kWide, int kRows>
-__device__ __forceinline__ void load_sums(const uint32_t *__restrict__ aw, const uint32_t *__restrict__ aw_hi,
-                                          int64_t t0, int W, int nrows, int ncol, bool vec, UnitSums<kWide, kRows> &U) {
+// kFull: every row of the unit exists and the lane's kCols columns are
+// aligned and in the atlas (vector loads), known at compile time so that
+// all the loads are issued before the first wait.
+template <bool kFull, bool kWide, int kRows>
+__device__ __forceinline__ void load_weights(const uint32_t *__restrict__ aw, const uint32_t *__restrict__ aw_hi,
+                                             int64_t t0, int W, int nrows, int ncol, bool vec,
+                                             UnitWeights<kWide, kRows> &U) {
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
-        Sum<kWide> s;
-        if (r < nrows) {
-            uint32_t lo[kCols], hi[kCols];
-            row_weights<kWide>(aw, aw_hi, t0 + (int64_t)r * W, ncol, vec, lo, hi);
+        const int64_t t = t0 + (int64_t)r * W;
+        if (kFull || (r < nrows && vec)) {
+#pragma unroll
+            for (int q = 0; q < kCols / 4; ++q) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(aw + t + 4 * q);
+                U.lo[r][4 * q] = v.x; U.lo[r][4 * q + 1] = v.y; U.lo[r][4 * q + 2] = v.z; U.lo[r][4 * q + 3] = v.w;
+                if constexpr (kWide) {
+                    const uint4 h = *reinterpret_cast<const uint4 *>(aw_hi + t + 4 * q);
+                    U.hi[r][4 * q] = h.x; U.hi[r][4 * q + 1] = h.y; U.hi[r][4 * q + 2] = h.z; U.hi[r][4 * q + 3] = h.w;
+                }
+            }
+        } else {
 #pragma unroll
             for (int k = 0; k < kCols; ++k) {
-                s.lo += lo[k];
-                if constexpr (kWide) s.hi += hi[k];
+                const bool in = r < nrows && k < ncol;
+                U.lo[r][k] = in ? aw[t + k] : 0u;
+                if constexpr (kWide) U.hi[r][k] = in ? aw_hi[t + k] : 0u;
             }
+        }
+        Sum<kWide> s;
+#pragma unroll
+        for (int k = 0; k < kCols; ++k) {
+            s.lo += U.lo[r][k];
+            if constexpr (kWide) s.hi += U.hi[r][k];
         }
         U.tot[r] = s;
     }
 }
 
-// One layer over a unit: runs of equal labels go to the bins.
-template <typename T, bool kWide, int kRows, typename Add>
-__device__ __forceinline__ void layer_unit(const T *__restrict__ L, const uint32_t *__restrict__ aw,
-                                           const uint32_t *__restrict__ aw_hi, int64_t t0, int W, int nrows, int ncol,
-                                           bool vec, const UnitSums<kWide, kRows> &U, Add &&add) {
-    RowLabels<T> lab[kRows];
+// A layer's labels over a unit (its rows of kCols columns).
+template <bool kFull, typename T, int kRows>
+__device__ __forceinline__ void load_rows(const T *__restrict__ L, int64_t t0, int W, int nrows, int ncol, bool vec,
+                                          RowLabels<T> lab[kRows]) {
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
-        if (r >= nrows) break;
+        if (!kFull && r >= nrows) break;
         const T *p = L + t0 + (int64_t)r * W;
-        if (vec) lab[r].load_vec(p);
+        if (kFull || vec) lab[r].load_vec(p);
         else lab[r].load_tail(p, ncol);
     }
+}
+
+// One layer over a unit: runs of equal labels go to the bins.
+template <bool kFull, typename T, bool kWide, int kRows, typename Add>
+__device__ __forceinline__ void unit_runs(const RowLabels<T> lab[kRows], int nrows,
+                                          const UnitWeights<kWide, kRows> &U, Add &&add) {
     uint32_t cur = kNoLabel;
     Sum<kWide> run;
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
-        if (r >= nrows) break;
+        if (!kFull && r >= nrows) break;
         if (lab[r].uniform()) {
             const uint32_t l0 = lab[r].at(0);
             if (l0 != cur) {
@@ -215,8 +219,6 @@ __device__ __forceinline__ void layer_unit(const T *__restrict__ L, const uint32
             }
             run.add(U.tot[r]);
         } else {
-            uint32_t lo[kCols], hi[kCols];
-            row_weights<kWide>(aw, aw_hi, t0 + (int64_t)r * W, ncol, vec, lo, hi);
 #pragma unroll
             for (int k = 0; k < kCols; ++k) {
                 const uint32_t lk = lab[r].at(k);
@@ -225,12 +227,57 @@ __device__ __forceinline__ void layer_unit(const T *__restrict__ L, const uint32
                     cur = lk;
                     run = Sum<kWide>();
                 }
-                run.lo += lo[k];
-                if constexpr (kWide) run.hi += hi[k];
+                run.lo += U.lo[r][k];
+                if constexpr (kWide) run.hi += U.hi[r][k];
             }
         }
     }
     if (run.nonzero()) add(cur, run);
+}
+
+// kG consecutive u8 layers from layer l over a unit: the labels of all of
+// them are requested before any is used, so that kG * kRows loads are in
+// flight at once rather than kRows.
+template <bool kFull, int kG, bool kWide, int kRows>
+__device__ __forceinline__ void u8_group(const AreaArgs &A, int l, const Bins<kWide> &bins,
+                                         int64_t t0, int W, int nrows, int ncol, bool vec,
+                                         const UnitWeights<kWide, kRows> &U) {
+    RowLabels<uint8_t> lab[kG][kRows];
+#pragma unroll
+    for (int j = 0; j < kG; ++j)
+        load_rows<kFull, uint8_t, kRows>(static_cast<const uint8_t *>(A.data[l + j]), t0, W, nrows, ncol, vec,
+                                         lab[j]);
+#pragma unroll
+    for (int j = 0; j < kG; ++j) {
+        const int row = l + j;
+        unit_runs<kFull, uint8_t, kWide, kRows>(lab[j], nrows, U,
+                                         [&](uint32_t lab_, const Sum<kWide> &s) { bins.add_u8(row, lab_, s); });
+    }
+}
+
+// One unit over every layer of the query: its weights, then the u8 layers
+// (first in A) in groups of up to kU8Group, then the u16 layers.
+template <bool kFull, int kNU8, bool kU16, bool kWide, int kRows>
+__device__ __forceinline__ void area_unit(const AreaArgs &A, const Bins<kWide> &bins, const uint32_t *__restrict__ aw,
+                                          const uint32_t *__restrict__ aw_hi, int64_t t0, int W, int nrows, int ncol,
+                                          bool vec) {
+    UnitWeights<kWide, kRows> U;
+    load_weights<kFull, kWide, kRows>(aw, aw_hi, t0, W, nrows, ncol, vec, U);
+    if constexpr (kNU8 > 0)
+        for (int l = 0; l < A.nu8;) {
+            const int g = A.nu8 - l >= kU8Group ? kU8Group : (A.nu8 - l >= 2 ? 2 : 1);
+            if (g == kU8Group) u8_group<kFull, kU8Group, kWide, kRows>(A, l, bins, t0, W, nrows, ncol, vec, U);
+            else if (g == 2) u8_group<kFull, 2, kWide, kRows>(A, l, bins, t0, W, nrows, ncol, vec, U);
+            else u8_group<kFull, 1, kWide, kRows>(A, l, bins, t0, W, nrows, ncol, vec, U);
+            l += g;
+        }
+    if constexpr (kU16)
+        for (int l = A.nu8; l < A.nl; ++l) {
+            RowLabels<uint16_t> lab[kRows];
+            load_rows<kFull, uint16_t, kRows>(static_cast<const uint16_t *>(A.data[l]), t0, W, nrows, ncol, vec, lab);
+            unit_runs<kFull, uint16_t, kWide, kRows>(lab, nrows, U,
+                                                     [&](uint32_t lab_, const Sum<kWide> &s) { bins.add_u16(l, lab_, s); });
+        }
 }
 
 // kNU8: LDS bin rows for u8 layers (>= the query's u8 layer count);
@@ -263,35 +310,20 @@ __global__ __launch_bounds__(kAreaBlock) void k_area(const uint32_t *__restrict_
         const bool vec = (W % kCols) == 0 && ncol == kCols;
         const int64_t t0 = (int64_t)row0 * W + col;
         if (ncol == 0) continue;
-        UnitSums<kWide, kRows> U;
-        load_sums<kWide, kRows>(aw, aw_hi, t0, W, nrows, ncol, vec, U);
-        for (int l = 0; l < A.nl; ++l) {
-            if (A.dtype[l] == UVL_U8 && kNU8 > 0) {
-                const int row = A.row[l];
-                layer_unit<uint8_t, kWide, kRows>(static_cast<const uint8_t *>(A.data[l]), aw, aw_hi, t0, W, nrows,
-                                                  ncol, vec, U,
-                                                  [&](uint32_t lab, const Sum<kWide> &s) { bins.add_u8(row, lab, s); });
-            } else if (kU16) {
-                layer_unit<uint16_t, kWide, kRows>(static_cast<const uint16_t *>(A.data[l]), aw, aw_hi, t0, W, nrows,
-                                                   ncol, vec, U,
-                                                   [&](uint32_t lab, const Sum<kWide> &s) { bins.add_u16(l, lab, s); });
-            }
-        }
+        if (nrows == kRows && vec) area_unit<true, kNU8, kU16, kWide, kRows>(A, bins, aw, aw_hi, t0, W, nrows, ncol, vec);
+        else area_unit<false, kNU8, kU16, kWide, kRows>(A, bins, aw, aw_hi, t0, W, nrows, ncol, vec);
     }
     __syncthreads();
     if (kNU8 > 0)
-        for (int l = 0; l < A.nl; ++l) {
-            if (A.dtype[l] != UVL_U8) continue;
-            const int row = A.row[l];
+        for (int row = 0; row < A.nu8; ++row)
             for (int k = threadIdx.x; k < 256; k += kAreaBlock) {
                 const unsigned long long v = s_bins[row * 256 + k];
-                if (v) atomicAdd(A.bins[l] + k, v);
+                if (v) atomicAdd(A.bins[row] + k, v);
                 if constexpr (kWide) {
                     const unsigned long long h = s_bins[(kNU8 + row) * 256 + k];
-                    if (h) atomicAdd(A.bins_hi[l] + k, h);
+                    if (h) atomicAdd(A.bins_hi[row] + k, h);
                 }
             }
-        }
     if (kU16)
         for (int k = threadIdx.x; k < kHash; k += kAreaBlock) {
             const uint32_t key = s_key[k];
@@ -306,7 +338,7 @@ __global__ __launch_bounds__(kAreaBlock) void k_area(const uint32_t *__restrict_
 // Workgroups: one per CU at most, fewer when there are few units.
 template <int kNU8, bool kU16, bool kWide>
 void launch_area(hipStream_t s, const uint32_t *aw, const uint32_t *aw_hi, int W, int H, const AreaArgs &A) {
-    constexpr int kRows = 4;
+    constexpr int kRows = kWide ? 2 : 4;   // two-word weights: half the rows, the same registers
     const int64_t units = ceil_div(W, kChunk) * ceil_div(H, kRows);
     int64_t g = ceil_div(units, kAreaWaves * 2);
     if (g > 256) g = 256;
@@ -374,30 +406,33 @@ extern "C" int32_t uvl_area_query(const uvl_geom *geom, const uvl_layer *layers,
     const int W = geom->width, H = geom->height;
     // one launch for all layers (two-word weights: up to 16 u8 layers per
     // launch, to keep the bins within the workgroup's LDS)
-    int64_t off = 0;
-    for (int l0 = 0; l0 < nlayers;) {
+    // bins of layer l start at off[l]
+    std::vector<int64_t> off(nlayers);
+    for (int l = 0, o = 0; l < nlayers; ++l) {
+        off[l] = o;
+        o += layers[l].dtype == UVL_U8 ? 256 : 65536;
+    }
+    // one launch for all layers, u8 layers first (two-word weights: up to
+    // 16 u8 layers per launch, to keep the bins within the workgroup's LDS)
+    std::vector<int> u8s, u16s;
+    for (int l = 0; l < nlayers; ++l) (layers[l].dtype == UVL_U8 ? u8s : u16s).push_back(l);
+    const size_t max_u8 = wide ? 16 : kMaxLayers;
+    size_t i8 = 0, i16 = 0;
+    while (i8 < u8s.size() || i16 < u16s.size()) {
         AreaArgs A{};
-        int nu8 = 0;
-        bool u16 = false;
         int k = 0;
-        for (; l0 + k < nlayers && k < kMaxLayers; ++k) {
-            const uvl_layer &L = layers[l0 + k];
-            if (L.dtype == UVL_U8) {
-                if (wide && nu8 == 16) break;
-                A.row[k] = nu8++;
-            } else {
-                u16 = true;
-            }
-            A.data[k] = L.data;
-            A.dtype[k] = L.dtype;
-            A.bins[k] = lo + off;
-            A.bins_hi[k] = wide ? hi + off : nullptr;
-            off += L.dtype == UVL_U8 ? 256 : 65536;
-        }
+        auto put = [&](int l) {
+            A.data[k] = layers[l].data;
+            A.bins[k] = lo + off[l];
+            A.bins_hi[k] = wide ? hi + off[l] : nullptr;
+            ++k;
+        };
+        for (; i8 < u8s.size() && (size_t)k < max_u8; ++i8) put(u8s[i8]);
+        A.nu8 = k;
+        for (; i16 < u16s.size() && k < kMaxLayers; ++i16) put(u16s[i16]);
         A.nl = k;
-        if (wide) launch_by_layers<true>(s, geom->area_w, geom->area_w_hi, W, H, A, nu8, u16);
-        else launch_by_layers<false>(s, geom->area_w, nullptr, W, H, A, nu8, u16);
-        l0 += k;
+        if (wide) launch_by_layers<true>(s, geom->area_w, geom->area_w_hi, W, H, A, A.nu8, A.nl > A.nu8);
+        else launch_by_layers<false>(s, geom->area_w, nullptr, W, H, A, A.nu8, A.nl > A.nu8);
     }
     if (launch_status() != UVL_OK) return UVL_E_DEVICE;
     if (!areas_host) return UVL_OK;

@@ -202,9 +202,11 @@ class ModelSpec:
 class GpuExecutor(Executor):
     """The HIP library behind the server: resident models as Model objects
     with their layers in a layer pool, edits through waves (batched) or
-    single launches (plain).  keep_bins: the waves keep every layer's area
+    single launches (plain).  keep_bins: the waves keep each layer's area
     bins up to date and area requests copy them (batched serving); otherwise
-    an area request scans its layer."""
+    an area request scans its layer.  Kept bins are computed lazily: a layer
+    is stale from admission or from a layer operation writing it until an
+    area request scans it, and the waves update only fresh layers' bins."""
 
     def __init__(self, specs: Sequence[ModelSpec], cameras, max_wave_edits=4096, pad_k=None, keep_bins=True,
                  pool_slots=256):
@@ -218,6 +220,7 @@ class GpuExecutor(Executor):
         self.pool = uvl.LayerPool(pool_slots)
         self.models: Dict[int, object] = {}   # resident Model objects
         self.bins: Dict[int, list] = {}       # per resident model, one device bins tensor per layer
+        self.stale: set = set()               # (model, layer) whose kept bins are out of date
         self.depth: Dict[tuple, object] = {}  # (model, camera) -> depth map of a resident model
         self.outlines: Dict[int, object] = {}
         self.saved: Dict[int, list] = {}      # evicted models' layers (host)
@@ -249,8 +252,7 @@ class GpuExecutor(Executor):
         wide = 2 if m.geom.wide else 1
         self.bins[model] = [torch.empty(wide * (256 if l.dtype == uvl.U8 else 65536), dtype=torch.int64,
                                         device=m.device) for l in m.layers]
-        for l, b in zip(m.layers, self.bins[model]):
-            uvl.area_query(m.geom, [l], bins=b, sync=False)
+        self.stale.update((model, k) for k in range(len(m.layers)))
         for ci in range(len(self.cameras[model])):
             self._depth(model, ci)
         if self.pad_k is not None:
@@ -263,6 +265,7 @@ class GpuExecutor(Executor):
         self.saved[model] = [l.numpy().copy() for l in m.layers]
         m.release()                           # pool memory back (waits for the device)
         self.bins.pop(model, None)
+        self.stale.difference_update({k for k in self.stale if k[0] == model})
         self.outlines.pop(model, None)
         for key in [k for k in self.depth if k[0] == model]:
             del self.depth[key]
@@ -290,7 +293,7 @@ class GpuExecutor(Executor):
         for r in reqs:
             m, e = self.models[r.model], r.edit
             layer = m.layers[e.layer]
-            bins = self.bins[r.model][e.layer] if self.keep_bins else None
+            bins = self.bins[r.model][e.layer] if self.keep_bins and (r.model, e.layer) not in self.stale else None
             if r.kind == "brush":
                 batch.brush(m.geom, layer, e.centre, e.radius, e.label, bins=bins)
             else:
@@ -321,10 +324,13 @@ class GpuExecutor(Executor):
             b = None if op.op == self.uvl.REMAP else m.layers[op.b]
             self.uvl.layer_op(op.op, m.layers[op.dst], m.layers[op.a], b, op.sel_a, op.sel_b, op.out_label, op.lut)
             if self.keep_bins:
-                self.uvl.area_query(m.geom, [m.layers[op.dst]], bins=self.bins[r.model][op.dst], sync=False)
+                self.stale.add((r.model, op.dst))
         elif r.kind == "area":
             if self.keep_bins:
                 bins = self.bins[r.model][r.layer]
+                if (r.model, r.layer) in self.stale:
+                    self.uvl.area_query(m.geom, [m.layers[r.layer]], bins=bins, sync=False)
+                    self.stale.discard((r.model, r.layer))
             else:
                 bins = self.uvl.area_query(m.geom, [m.layers[r.layer]], sync=False)
             host = self.torch.empty(bins.shape, dtype=bins.dtype, pin_memory=True)
