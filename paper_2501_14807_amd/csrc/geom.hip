@@ -611,8 +611,18 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(GeomArgs a, GeomOut g) {
                 m[1] = u1[2] * u2[0] - u1[0] * u2[2];
                 m[2] = u1[0] * u2[1] - u1[1] * u2[0];
             }
-            const double len = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
-            const double inv = len > 0.0 ? 1.0 / len : 0.0;
+            const double len2 = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
+            double inv;
+            if (len2 >= 1e-30 && len2 <= 1e30) {
+                // 1 / sqrt(len2): the hardware fp32 estimate (about 1 ulp)
+                // and one Newton step in fp64 (relative error ~1e-14; the
+                // normal is not part of the bit-exact contract)
+                const double y = (double)__builtin_amdgcn_rsqf((float)len2);
+                inv = y * (1.5 - 0.5 * len2 * y * y);
+            } else {
+                const double len = sqrt(len2);
+                inv = len > 0.0 ? 1.0 / len : 0.0;
+            }
             g.nx[idx] = (float)(m[0] * inv);
             g.ny[idx] = (float)(m[1] * inv);
             g.nz[idx] = (float)(m[2] * inv);
