@@ -226,15 +226,105 @@ static int project(const float M[16], float x, float y, float z, float *xn, floa
 
 /* ------------------------------------------------------------------------
  * Depth texture (§4.3.1: the depth of the scene seen from the editing
- * camera, against which occluded fragments are discarded).  Rows [r0, r1) of a Wd x Hd map, initialised
- * to 1.0 (far).  Reading: GL window depth d = 0.5 z_ndc + 0.5; pixel (ix, iy)
- * samples its centre, row 0 at NDC y = -1.  A triangle is drawn only if all
- * three vertices have clip w > 0 and |x_ndc|, |y_ndc| <= 16 (a guard band in
- * place of clipping).  Screen position s = fmaf(ndc, .5, .5) * size in fp32,
- * then the shared fixed-point raster rule; depth is interpolated with the
- * screen-space barycentrics in fp64 (window depth is affine on screen),
- * samples outside [0, 1] are dropped, the nearest is kept, stored as fp32.
+ * camera, against which occluded fragments are discarded).  Rows [r0, r1) of
+ * a Wd x Hd map, initialised to 1.0 (far).  Reading: GL window depth
+ * d = 0.5 z_ndc + 0.5; pixel (ix, iy) samples its centre, row 0 at NDC
+ * y = -1.  A triangle whose three vertices lie in front of the near plane
+ * (z_clip + w_clip >= 0, w_clip > 0) and inside the guard band
+ * |x_clip|, |y_clip| <= 16 w_clip is drawn as it is; one with a vertex
+ * beyond any of these five planes is clipped against them (as the fixed-
+ * function pipeline clips primitives) and the remaining polygon drawn as a
+ * fan from its first vertex.  Clipping is in fp64 on the fp32 clip
+ * coordinates, one plane after the other; a cut edge is split at
+ * s + t (o - s), t = f(s) / (f(s) - f(o)), from its inside end s to its
+ * outside end o (f the plane's signed distance), so that the two triangles
+ * sharing an edge cut it at the same point.  A vertex of the triangle keeps
+ * its fp32 projection (x_clip / w_clip in fp32); a cut point's NDC is its
+ * fp64 quotient rounded to fp32, x and y clamped to [-16, 16].  Screen
+ * position s = fmaf(ndc, .5, .5) * size in fp32, then the shared fixed-point
+ * raster rule; depth is interpolated with the screen-space barycentrics in
+ * fp64 (window depth is affine on screen), samples outside [0, 1] are
+ * dropped, the nearest is kept, stored as fp32.
  * ------------------------------------------------------------------------ */
+static void depth_raster(const float xn[3], const float yn[3], const float zn[3], int Wd, int Hd, int r0, int r1,
+                         float *depth)
+{
+    int64_t X[3], Y[3];
+    double d[3];
+    for (int k = 0; k < 3; ++k) {
+        float sx = fmaf(xn[k], 0.5f, 0.5f) * (float)Wd;
+        float sy = fmaf(yn[k], 0.5f, 0.5f) * (float)Hd;
+        X[k] = snap256((double)sx);
+        Y[k] = snap256((double)sy);
+        d[k] = (double)fmaf(zn[k], 0.5f, 0.5f);
+    }
+    int64_t mnx = X[0], mxx = X[0], mny = Y[0], mxy = Y[0];
+    for (int k = 1; k < 3; ++k) {
+        if (X[k] < mnx) mnx = X[k];
+        if (X[k] > mxx) mxx = X[k];
+        if (Y[k] < mny) mny = Y[k];
+        if (Y[k] > mxy) mxy = Y[k];
+    }
+    int i_lo, i_hi, q_lo, q_hi;
+    cell_range(mnx, mxx, Wd, &i_lo, &i_hi);
+    cell_range(mny, mxy, Hd, &q_lo, &q_hi);
+    if (q_lo < r0) q_lo = r0;
+    if (q_hi > r1 - 1) q_hi = r1 - 1;
+    for (int iy = q_lo; iy <= q_hi; ++iy)
+        for (int ix = i_lo; ix <= i_hi; ++ix) {
+            int64_t e[3], E;
+            if (!tri_sample(X, Y, 256 * (int64_t)ix + 128, 256 * (int64_t)iy + 128, e, &E)) continue;
+            double z = ((double)e[0] / (double)E) * d[0] + ((double)e[1] / (double)E) * d[1] +
+                       ((double)e[2] / (double)E) * d[2];
+            if (!(z >= 0.0 && z <= 1.0)) continue;
+            float zf = (float)z;
+            int64_t idx = (int64_t)(iy - r0) * Wd + ix;
+            if (zf < depth[idx]) depth[idx] = zf;
+        }
+}
+
+/* signed distance to clipping plane p (>= 0 inside): the near plane, then
+ * the guard band's right, left, top and bottom sides */
+static double clip_dist(int p, const double c[4])
+{
+    switch (p) {
+    case 0: return c[2] + c[3];
+    case 1: return 16.0 * c[3] - c[0];
+    case 2: return 16.0 * c[3] + c[0];
+    case 3: return 16.0 * c[3] - c[1];
+    default: return 16.0 * c[3] + c[1];
+    }
+}
+
+typedef struct {
+    double c[4];
+    int orig;           /* the triangle's vertex it is, or -1 for a cut point */
+} clip_vert;
+
+/* Sutherland-Hodgman step: the part of polygon in[0..n) inside plane p */
+static int clip_plane(const clip_vert *in, int n, int p, clip_vert *out)
+{
+    int m = 0;
+    for (int i = 0; i < n; ++i) {
+        const clip_vert *a = &in[i], *b = &in[(i + 1) % n];
+        double fa = clip_dist(p, a->c), fb = clip_dist(p, b->c);
+        int ina = fa >= 0.0, inb = fb >= 0.0;
+        if (ina) out[m++] = *a;
+        if (ina != inb) {
+            const clip_vert *sv = ina ? a : b, *ov = ina ? b : a;
+            double fs = ina ? fa : fb, fo = ina ? fb : fa;
+            double t = fs / (fs - fo);
+            clip_vert q;
+            q.orig = -1;
+            for (int k = 0; k < 4; ++k) q.c[k] = sv->c[k] + t * (ov->c[k] - sv->c[k]);
+            out[m++] = q;
+        }
+    }
+    return m;
+}
+
+static float clamp16(float x) { return x < -16.0f ? -16.0f : (x > 16.0f ? 16.0f : x); }
+
 int orc_depth_map(const float *pos, const int32_t *tri, int64_t nv, int64_t nt, const float M[16],
                   int Wd, int Hd, int r0, int r1, float *depth)
 {
@@ -242,45 +332,67 @@ int orc_depth_map(const float *pos, const int32_t *tri, int64_t nv, int64_t nt, 
     const int64_t n = (int64_t)(r1 - r0) * Wd;
     for (int64_t k = 0; k < n; ++k) depth[k] = 1.0f;
     for (int64_t t = 0; t < nt; ++t) {
-        int64_t X[3], Y[3];
-        double d[3];
-        int ok = 1;
-        for (int k = 0; k < 3 && ok; ++k) {
+        float cf[3][4];
+        int finite = 1, inside = 1;
+        for (int k = 0; k < 3; ++k) {
             int64_t v = tri[3 * t + k];
             if (v < 0 || v >= nv) return -2;
-            float xn, yn, zn;
-            if (!project(M, pos[3 * v], pos[3 * v + 1], pos[3 * v + 2], &xn, &yn, &zn)) { ok = 0; break; }
-            if (!(fabsf(xn) <= 16.0f) || !(fabsf(yn) <= 16.0f)) { ok = 0; break; }
-            float sx = fmaf(xn, 0.5f, 0.5f) * (float)Wd;
-            float sy = fmaf(yn, 0.5f, 0.5f) * (float)Hd;
-            X[k] = snap256((double)sx);
-            Y[k] = snap256((double)sy);
-            d[k] = (double)fmaf(zn, 0.5f, 0.5f);
+            float x = pos[3 * v], y = pos[3 * v + 1], z = pos[3 * v + 2];
+            for (int q = 0; q < 4; ++q) {
+                cf[k][q] = fmaf(M[4 * q + 2], z, fmaf(M[4 * q + 1], y, fmaf(M[4 * q + 0], x, M[4 * q + 3])));
+                if (!isfinite(cf[k][q])) finite = 0;
+            }
+            double c[4] = {cf[k][0], cf[k][1], cf[k][2], cf[k][3]};
+            if (!(cf[k][3] > 0.0f)) inside = 0;
+            for (int p = 0; p < 5; ++p)
+                if (!(clip_dist(p, c) >= 0.0)) inside = 0;
+        }
+        if (!finite) continue;
+        float xn[3], yn[3], zn[3];
+        if (inside) {
+            for (int k = 0; k < 3; ++k) {
+                xn[k] = cf[k][0] / cf[k][3];
+                yn[k] = cf[k][1] / cf[k][3];
+                zn[k] = cf[k][2] / cf[k][3];
+            }
+            depth_raster(xn, yn, zn, Wd, Hd, r0, r1, depth);
+            continue;
+        }
+        clip_vert poly[2][9];
+        int m = 3;
+        for (int k = 0; k < 3; ++k) {
+            for (int q = 0; q < 4; ++q) poly[0][k].c[q] = (double)cf[k][q];
+            poly[0][k].orig = k;
+        }
+        int cur = 0;
+        for (int p = 0; p < 5 && m >= 3; ++p) {
+            m = clip_plane(poly[cur], m, p, poly[1 - cur]);
+            cur = 1 - cur;
+        }
+        if (m < 3) continue;
+        float px[9], py[9], pz[9];
+        int ok = 1;
+        for (int k = 0; k < m; ++k) {
+            const clip_vert *v = &poly[cur][k];
+            if (!(v->c[3] > 0.0)) { ok = 0; break; }
+            if (v->orig >= 0) {
+                const float *c = cf[v->orig];
+                px[k] = c[0] / c[3];
+                py[k] = c[1] / c[3];
+                pz[k] = c[2] / c[3];
+            } else {
+                px[k] = clamp16((float)(v->c[0] / v->c[3]));
+                py[k] = clamp16((float)(v->c[1] / v->c[3]));
+                pz[k] = (float)(v->c[2] / v->c[3]);
+            }
         }
         if (!ok) continue;
-        int64_t mnx = X[0], mxx = X[0], mny = Y[0], mxy = Y[0];
-        for (int k = 1; k < 3; ++k) {
-            if (X[k] < mnx) mnx = X[k];
-            if (X[k] > mxx) mxx = X[k];
-            if (Y[k] < mny) mny = Y[k];
-            if (Y[k] > mxy) mxy = Y[k];
+        for (int k = 1; k + 1 < m; ++k) {
+            xn[0] = px[0]; yn[0] = py[0]; zn[0] = pz[0];
+            xn[1] = px[k]; yn[1] = py[k]; zn[1] = pz[k];
+            xn[2] = px[k + 1]; yn[2] = py[k + 1]; zn[2] = pz[k + 1];
+            depth_raster(xn, yn, zn, Wd, Hd, r0, r1, depth);
         }
-        int i_lo, i_hi, q_lo, q_hi;
-        cell_range(mnx, mxx, Wd, &i_lo, &i_hi);
-        cell_range(mny, mxy, Hd, &q_lo, &q_hi);
-        if (q_lo < r0) q_lo = r0;
-        if (q_hi > r1 - 1) q_hi = r1 - 1;
-        for (int iy = q_lo; iy <= q_hi; ++iy)
-            for (int ix = i_lo; ix <= i_hi; ++ix) {
-                int64_t e[3], E;
-                if (!tri_sample(X, Y, 256 * (int64_t)ix + 128, 256 * (int64_t)iy + 128, e, &E)) continue;
-                double z = ((double)e[0] / (double)E) * d[0] + ((double)e[1] / (double)E) * d[1] +
-                           ((double)e[2] / (double)E) * d[2];
-                if (!(z >= 0.0 && z <= 1.0)) continue;
-                float zf = (float)z;
-                int64_t idx = (int64_t)(iy - r0) * Wd + ix;
-                if (zf < depth[idx]) depth[idx] = zf;
-            }
     }
     return 0;
 }

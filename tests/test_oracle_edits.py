@@ -1,7 +1,9 @@
 """Pins of the oracle's depth texture, brush and lasso selection (§4.3.1).
 
 Closed forms: window depth of a tilted plane and of a sphere by exact ray
-casting; Archimedes' cap (a ball of radius r centred on a sphere cuts a cap of
+casting, of a floor that reaches behind the eye (clipped at the near plane)
+and of a wall far beyond the guard band; a near occluder hiding a sphere;
+an eye inside a closed mesh seeing it everywhere; Archimedes' cap (a ball of radius r centred on a sphere cuts a cap of
 area pi r^2); the visible cap 2 pi R^2 (1 - R/d) seen from distance d; the
 world-space rectangle a square lasso cuts from a plane facing the camera.
 Brute force: even-odd crossing number against a winding-number angle sum.
@@ -97,12 +99,122 @@ def test_depth_of_sphere_and_background(orc):
     assert hit.sum() > 5000
 
 
-def test_depth_skips_triangles_behind_camera(orc):
+def test_depth_plane_seen_edge_on_is_not_drawn(orc):
     m = synth.plane_grid(3, 3, A=((8.0, 0.0), (0.0, 8.0), (0.0, 0.0)), b=(-4.0, -4.0, 0.0))
-    # the camera sits inside the plane's span looking along it: every
-    # triangle has a vertex behind the eye and is not drawn
+    # the eye lies in the plane, looking along it: the plane projects to a
+    # line (zero screen area), so nothing is drawn even though its triangles
+    # reach behind the eye and are clipped
     M = look_at_perspective((0.0, 0.0, 0.0), (1.0, 0.0, 0.0), (0.0, 0.0, 1.0))
     assert (orc.depth_map(m, M, 16, 16) == 1.0).all()
+
+
+def _floor(x0=-10.0, x1=50.0, half=30.0, z=-1.0, n=3):
+    return synth.plane_grid(n, n, A=((x1 - x0, 0.0), (0.0, 2 * half), (0.0, 0.0)), b=(x0, -half, z))
+
+
+def _ray_plane_depth(M64, Wd, Hd, z0):
+    """Window depth of the plane z = z0 along every pixel's ray (nan where
+    the ray does not meet it in front of the eye)."""
+    out = np.full((Hd, Wd), np.nan)
+    for iy in range(Hd):
+        for ix in range(Wd):
+            x = (2 * ix + 1) / Wd - 1
+            y = (2 * iy + 1) / Hd - 1
+            o, r = _pixel_ray(M64, x, y)
+            if abs(r[2]) < 1e-12:
+                continue
+            t = (z0 - o[2]) / r[2]
+            if t <= 0:
+                continue
+            out[iy, ix] = _window_depth(M64, o + t * r)
+    return out
+
+
+def test_depth_floor_through_the_near_plane(orc):
+    """A floor whose triangles reach behind the eye (every one crosses the
+    near plane): clipped, not dropped, so every pixel whose ray meets the
+    floor within the far plane holds the floor's exact window depth."""
+    m = _floor()
+    M = look_at_perspective((0.0, 0.0, 0.0), (1.0, 0.0, 0.0), (0.0, 0.0, 1.0))
+    M64 = M.reshape(4, 4).astype(np.float64)
+    Wd, Hd = 48, 32
+    D = orc.depth_map(m, M, Wd, Hd)
+    want = _ray_plane_depth(M64, Wd, Hd, -1.0)
+    # the floor spans x in [-10, 50], |y| <= 30: rays hitting it beyond
+    # x = 45 or |y| = 25 are left out (its far edge), as are grazing ones
+    ok = np.isfinite(want) & (want < 0.999)
+    # Window depth of a plane is affine on the screen, so its gradient per
+    # pixel g is one vector; each vertex snap moves a vertex by at most
+    # sqrt(2)/512 pixel, which moves the interpolated depth by at most
+    # |g| sqrt(2)/512 inside the triangle (the barycentrics sum to 1); the
+    # vertices' fp32 window depths add 2^-24 at most.
+    g = np.array([np.nanmedian(np.diff(want, axis=1)), np.nanmedian(np.diff(want, axis=0))])
+    tol = np.hypot(*g) * math.sqrt(2) / 512 * 1.01 + 2.0 ** -24 + 1e-7
+    checked = 0
+    for j, i in zip(*np.nonzero(ok)):
+        x = (2 * i + 1) / Wd - 1
+        y = (2 * j + 1) / Hd - 1
+        o, r = _pixel_ray(M64, x, y)
+        h = o + (-1.0 - o[2]) / r[2] * r
+        if h[0] > 45 or abs(h[1]) > 25:
+            continue
+        assert abs(D[j, i] - want[j, i]) < tol, (i, j, tol)
+        checked += 1
+    assert checked > 0.25 * Wd * Hd
+    # the upper half of the view sees nothing
+    assert (D[Hd // 2 + 1:] == 1.0).all()
+
+
+def test_depth_near_occluder_hides_what_is_behind(orc):
+    """A sphere below the floor of the previous case: the floor, clipped at
+    the near plane, stays in front of it wherever both are seen, so the depth
+    texture equals the floor's alone."""
+    floor = _floor()
+    ball = synth.sphere(radius=1.5, n_theta=65, n_phi=33)
+    ball = synth.Mesh(ball.pos + np.array([6.0, 0.0, -3.0], np.float32), ball.nrm, ball.uv, ball.tri)
+    both = synth.mesh.merge_meshes([floor, ball])
+    M = look_at_perspective((0.0, 0.0, 0.0), (1.0, 0.0, 0.0), (0.0, 0.0, 1.0))
+    Wd, Hd = 64, 64
+    D_floor = orc.depth_map(floor, M, Wd, Hd)
+    D_ball = orc.depth_map(ball, M, Wd, Hd)
+    D = orc.depth_map(both, M, Wd, Hd)
+    assert (D_ball < 1.0).sum() > 50                # the ball alone is in view
+    assert np.array_equal(D, D_floor)
+
+
+def test_depth_wall_beyond_the_guard_band(orc):
+    """A wall facing the eye at distance 2 whose corners project to |ndc| of
+    about 900: clipped to the guard band and drawn, every pixel at the
+    wall's window depth."""
+    m = synth.plane_grid(3, 3, A=((0.0, 0.0), (2000.0, 0.0), (0.0, 2000.0)), b=(2.0, -1000.0, -1000.0))
+    M = look_at_perspective((0.0, 0.0, 0.0), (1.0, 0.0, 0.0), (0.0, 0.0, 1.0))
+    M64 = M.reshape(4, 4).astype(np.float64)
+    D = orc.depth_map(m, M, 32, 32)
+    assert np.abs(D - _window_depth(M64, np.array([2.0, 0.0, 0.0]))).max() < 1e-6
+
+
+def test_depth_eye_inside_a_closed_mesh(orc):
+    """The eye at the centre of a sphere: triangles behind it and beside it
+    are clipped at the near plane and the guard band; every pixel is drawn
+    (no cracks where clipped triangles meet) at the depth of a point
+    between the inscribed polyhedron's faces and the sphere."""
+    R = 5.0
+    m = synth.sphere(radius=R, n_theta=65, n_phi=33)
+    M = look_at_perspective((0.0, 0.0, 0.0), (1.0, 0.3, 0.2), (0.0, 0.0, 1.0))
+    M64 = M.reshape(4, 4).astype(np.float64)
+    Wd = Hd = 64
+    D = orc.depth_map(m, M, Wd, Hd).astype(np.float64)
+    assert (D < 1.0).all()
+    # along each pixel's ray from the eye, the faces lie between R - sag and
+    # R (sag = R (1 - cos(pi / 32)) at these angular steps, generously);
+    # window depth grows with the distance along a ray
+    sag = R * (1 - math.cos(math.pi / 32))
+    for iy in range(0, Hd, 3):
+        for ix in range(0, Wd, 3):
+            a, _ = _pixel_ray(M64, (2 * ix + 1) / Wd - 1, (2 * iy + 1) / Hd - 1)
+            r = a / np.linalg.norm(a)
+            lo, hi = _window_depth(M64, (R - sag) * r), _window_depth(M64, R * r)
+            assert lo - 1e-5 <= D[iy, ix] <= hi + 1e-5, (ix, iy)
 
 
 def _sphere_geom(orc, W=1024):
