@@ -2,13 +2,20 @@
 // from the current viewpoint, for the depth test of the editing tools),
 // rasterised with the fixed-point rule of raster_rule.h on screen positions.
 //
+// A triangle reaching beyond the near plane (z_clip + w_clip >= 0) or the
+// guard band (|x_clip|, |y_clip| <= 16 w_clip) is clipped against those
+// planes, as the fixed-function pipeline clips primitives, and its polygon
+// drawn as a fan; one inside them is drawn as it is.
+//
 // Launch structure:
 //   1. one thread per triangle: set-up, and for bounding boxes of at most
 //      kSmallCells cells the whole raster, with an atomicMin per covered cell
 //      on the fp32 bits of the (non-negative) depth, order-independent;
-//      larger triangles go to a queue in the workspace;
+//      larger triangles and those to be clipped go to a queue in the
+//      workspace;
 //   2. a fixed grid of workgroups drains the queue, one triangle per
-//      workgroup, its 256 threads striding over the bounding box.
+//      workgroup, its 256 threads striding over the bounding box (of each
+//      fan triangle, for a clipped one).
 #include <math.h>
 
 #include <mutex>
@@ -35,33 +42,63 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Mat4 { float m[16]; };
 
-__device__ __forceinline__ bool project(const Mat4 &M, float x, float y, float z, float &xn, float &yn, float &zn) {
-    float c[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        c[k] = __builtin_fmaf(M.m[4 * k + 2], z, __builtin_fmaf(M.m[4 * k + 1], y, __builtin_fmaf(M.m[4 * k + 0], x, M.m[4 * k + 3])));
-    if (!(c[3] > 0.0f)) return false;
-    xn = c[0] / c[3];
-    yn = c[1] / c[3];
-    zn = c[2] / c[3];
-    return true;
+// A triangle's class for the depth raster: kDrop (a vertex index out of
+// range or a non-finite clip coordinate), kDirect (every vertex with w > 0,
+// in front of the near plane z + w >= 0 and inside the guard band
+// |x|, |y| <= 16 w: drawn as it is), kClip (the rest: clipped against those
+// five planes by k_depth_big, the remaining polygon drawn as a fan).
+enum { kDrop = 0, kDirect = 1, kClip = 2 };
+constexpr int kMaxPoly = 9;             // 3 vertices + one per clipping plane, + 1 spare
+
+// Signed distance to clipping plane p (>= 0 inside): the near plane, then
+// the guard band's right, left, top and bottom sides.
+__device__ __forceinline__ double clip_dist(int p, const double c[4]) {
+    switch (p) {
+    case 0: return c[2] + c[3];
+    case 1: return 16.0 * c[3] - c[0];
+    case 2: return 16.0 * c[3] + c[0];
+    case 3: return 16.0 * c[3] - c[1];
+    default: return 16.0 * c[3] + c[1];
+    }
 }
 
-__device__ __forceinline__ bool depth_tri(const Mat4 &M, const float *__restrict__ pos,
-                                          const int32_t *__restrict__ tri, int64_t nv, int64_t t, int Wd,
-                                          int Hd, Tri2 &T, double d[3]) {
+// Clip coordinates of triangle t's vertices (fp32 fma chains, as the
+// edit predicates project) and its class.
+__device__ __forceinline__ int depth_vertices(const Mat4 &M, const float *__restrict__ pos,
+                                              const int32_t *__restrict__ tri, int64_t nv, int64_t t,
+                                              float cf[3][4]) {
+    bool inside = true;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int32_t v = tri[3 * t + k];
-        if (v < 0 || v >= nv) return false;
-        float xn, yn, zn;
-        if (!project(M, pos[3 * (int64_t)v], pos[3 * (int64_t)v + 1], pos[3 * (int64_t)v + 2], xn, yn, zn)) return false;
-        if (!(fabsf(xn) <= 16.0f) || !(fabsf(yn) <= 16.0f)) return false;
-        const float sx = __builtin_fmaf(xn, 0.5f, 0.5f) * (float)Wd;
-        const float sy = __builtin_fmaf(yn, 0.5f, 0.5f) * (float)Hd;
+        if (v < 0 || v >= nv) return kDrop;
+        const float x = pos[3 * (int64_t)v], y = pos[3 * (int64_t)v + 1], z = pos[3 * (int64_t)v + 2];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            cf[k][q] = __builtin_fmaf(M.m[4 * q + 2], z,
+                                      __builtin_fmaf(M.m[4 * q + 1], y, __builtin_fmaf(M.m[4 * q + 0], x, M.m[4 * q + 3])));
+            if (!isfinite(cf[k][q])) return kDrop;
+        }
+        const double c[4] = {cf[k][0], cf[k][1], cf[k][2], cf[k][3]};
+        if (!(cf[k][3] > 0.0f)) inside = false;
+#pragma unroll
+        for (int p = 0; p < 5; ++p)
+            if (!(clip_dist(p, c) >= 0.0)) inside = false;
+    }
+    return inside ? kDirect : kClip;
+}
+
+// Screen set-up of a triangle from its vertices' NDC: window position
+// fmaf(ndc, .5, .5) * size in fp32, snapped; window depth fmaf(z, .5, .5).
+__device__ __forceinline__ bool depth_setup(const float xn[3], const float yn[3], const float zn[3], int Wd, int Hd,
+                                            Tri2 &T, double d[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float sx = __builtin_fmaf(xn[k], 0.5f, 0.5f) * (float)Wd;
+        const float sy = __builtin_fmaf(yn[k], 0.5f, 0.5f) * (float)Hd;
         T.X[k] = snap256((double)sx);
         T.Y[k] = snap256((double)sy);
-        d[k] = (double)__builtin_fmaf(zn, 0.5f, 0.5f);
+        d[k] = (double)__builtin_fmaf(zn[k], 0.5f, 0.5f);
     }
     return tri_setup(T);
 }
@@ -77,15 +114,110 @@ __device__ __forceinline__ void depth_sample(const Tri2 &T, const double d[3], l
     atomicMin(cell, __float_as_uint(zf));
 }
 
+// One triangle's raster by the whole workgroup, striding over its box.
+__device__ __forceinline__ void depth_block(const Tri2 &T, const double d[3], int Wd, int Hd,
+                                            unsigned *__restrict__ depth) {
+    int i0, i1, j0, j1;
+    bbox(T, Wd, Hd, i0, i1, j0, j1);
+    if (i1 < i0 || j1 < j0) return;
+    const unsigned bw = (unsigned)(i1 - i0 + 1);
+    const unsigned cells = bw * (unsigned)(j1 - j0 + 1);
+    for (unsigned c = threadIdx.x; c < cells; c += kBlock) {
+        const int i = i0 + (int)(c % bw), j = j0 + (int)(c / bw);
+        const long long px = 256LL * i + 128, py = 256LL * j + 128;
+        bool in = true;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) in &= T.A[k] * px + T.B[k] * py + T.C[k] >= T.bias[k];
+        if (in) depth_sample(T, d, px, py, depth + (int64_t)j * Wd + i);
+    }
+}
+
+// The clipped polygon of a kClip triangle as NDC vertices x, y, z (by one
+// thread, in LDS): fp64 Sutherland-Hodgman against the five planes in
+// order, each cut edge split at s + t (o - s), t = f(s) / (f(s) - f(o)),
+// from its inside end s to its outside end o, so that two triangles sharing
+// an edge cut it at the same point; a vertex of the triangle keeps its fp32
+// quotient, a cut point takes its fp64 quotient rounded to fp32, x and y
+// clamped to [-16, 16].  Returns the vertex count (0: nothing left).
+struct ClipPoly {
+    double c[2][kMaxPoly][4];
+    int orig[2][kMaxPoly];
+    float x[kMaxPoly], y[kMaxPoly], z[kMaxPoly];
+};
+
+__device__ __forceinline__ float clamp16(float v) { return v < -16.0f ? -16.0f : (v > 16.0f ? 16.0f : v); }
+
+__device__ int clip_polygon(const float cf[3][4], ClipPoly &P) {
+    int n = 3, cur = 0;
+    for (int k = 0; k < 3; ++k) {
+        for (int q = 0; q < 4; ++q) P.c[0][k][q] = (double)cf[k][q];
+        P.orig[0][k] = k;
+    }
+    for (int p = 0; p < 5 && n >= 3; ++p) {
+        const int nxt = 1 - cur;
+        int m = 0;
+        for (int i = 0; i < n; ++i) {
+            const int b = i + 1 < n ? i + 1 : 0;
+            const double fa = clip_dist(p, P.c[cur][i]), fb = clip_dist(p, P.c[cur][b]);
+            const bool ina = fa >= 0.0, inb = fb >= 0.0;
+            if (ina) {
+                for (int q = 0; q < 4; ++q) P.c[nxt][m][q] = P.c[cur][i][q];
+                P.orig[nxt][m] = P.orig[cur][i];
+                ++m;
+            }
+            if (ina != inb) {
+                const int sv = ina ? i : b, ov = ina ? b : i;
+                const double fs = ina ? fa : fb, fo = ina ? fb : fa;
+                const double t = fs / (fs - fo);
+                for (int q = 0; q < 4; ++q) P.c[nxt][m][q] = P.c[cur][sv][q] + t * (P.c[cur][ov][q] - P.c[cur][sv][q]);
+                P.orig[nxt][m] = -1;
+                ++m;
+            }
+        }
+        n = m;
+        cur = nxt;
+    }
+    if (n < 3) return 0;
+    for (int k = 0; k < n; ++k) {
+        const double *c = P.c[cur][k];
+        if (!(c[3] > 0.0)) return 0;
+        const int o = P.orig[cur][k];
+        if (o >= 0) {
+            P.x[k] = cf[o][0] / cf[o][3];
+            P.y[k] = cf[o][1] / cf[o][3];
+            P.z[k] = cf[o][2] / cf[o][3];
+        } else {
+            P.x[k] = clamp16((float)(c[0] / c[3]));
+            P.y[k] = clamp16((float)(c[1] / c[3]));
+            P.z[k] = (float)(c[2] / c[3]);
+        }
+    }
+    return n;
+}
+
 __global__ __launch_bounds__(kBlock) void k_depth_tri(Mat4 M, const float *__restrict__ pos,
                                                       const int32_t *__restrict__ tri, int64_t nv, int64_t nt,
                                                       int Wd, int Hd, unsigned *__restrict__ depth,
                                                       unsigned *__restrict__ queue, Counters *__restrict__ ctr) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= nt) return;
+    float cf[3][4];
+    const int cls = depth_vertices(M, pos, tri, nv, t, cf);
+    if (cls == kDrop) return;
+    if (cls == kClip) {
+        queue[atomicAdd(&ctr->queue_len, 1u)] = (unsigned)t;
+        return;
+    }
+    float xn[3], yn[3], zn[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        xn[k] = cf[k][0] / cf[k][3];
+        yn[k] = cf[k][1] / cf[k][3];
+        zn[k] = cf[k][2] / cf[k][3];
+    }
     Tri2 T;
     double d[3];
-    if (!depth_tri(M, pos, tri, nv, t, Wd, Hd, T, d)) return;
+    if (!depth_setup(xn, yn, zn, Wd, Hd, T, d)) return;
     int i0, i1, j0, j1;
     bbox(T, Wd, Hd, i0, i1, j0, j1);
     if (i1 < i0 || j1 < j0) return;
@@ -106,27 +238,45 @@ __global__ __launch_bounds__(kBlock) void k_depth_tri(Mat4 M, const float *__res
     }
 }
 
+// Queued triangles, one per workgroup: large ones drawn directly, clipped
+// ones as the fan of their polygon (the polygon built by thread 0 in LDS).
 __global__ __launch_bounds__(kBlock) void k_depth_big(Mat4 M, const float *__restrict__ pos,
                                                       const int32_t *__restrict__ tri, int64_t nv, int Wd, int Hd,
                                                       unsigned *__restrict__ depth,
                                                       const unsigned *__restrict__ queue,
                                                       const Counters *__restrict__ ctr) {
+    __shared__ ClipPoly s_poly;
+    __shared__ int s_n;
     const unsigned n = ctr->queue_len;
     for (unsigned q = blockIdx.x; q < n; q += gridDim.x) {
-        Tri2 T;
-        double d[3];
-        if (!depth_tri(M, pos, tri, nv, queue[q], Wd, Hd, T, d)) continue;
-        int i0, i1, j0, j1;
-        bbox(T, Wd, Hd, i0, i1, j0, j1);
-        const unsigned bw = (unsigned)(i1 - i0 + 1);
-        const unsigned cells = bw * (unsigned)(j1 - j0 + 1);
-        for (unsigned c = threadIdx.x; c < cells; c += kBlock) {
-            const int i = i0 + (int)(c % bw), j = j0 + (int)(c / bw);
-            const long long px = 256LL * i + 128, py = 256LL * j + 128;
-            bool in = true;
+        const unsigned t = queue[q];
+        float cf[3][4];
+        const int cls = depth_vertices(M, pos, tri, nv, t, cf);
+        if (cls == kDirect) {
+            float xn[3], yn[3], zn[3];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) in &= T.A[k] * px + T.B[k] * py + T.C[k] >= T.bias[k];
-            if (in) depth_sample(T, d, px, py, depth + (int64_t)j * Wd + i);
+            for (int k = 0; k < 3; ++k) {
+                xn[k] = cf[k][0] / cf[k][3];
+                yn[k] = cf[k][1] / cf[k][3];
+                zn[k] = cf[k][2] / cf[k][3];
+            }
+            Tri2 T;
+            double d[3];
+            if (depth_setup(xn, yn, zn, Wd, Hd, T, d)) depth_block(T, d, Wd, Hd, depth);
+        } else if (cls == kClip) {
+            // uniform over the workgroup (one triangle), so the barriers are too
+            if (threadIdx.x == 0) s_n = clip_polygon(cf, s_poly);
+            __syncthreads();
+            const int m = s_n;
+            for (int k = 1; k + 1 < m; ++k) {
+                const float xn[3] = {s_poly.x[0], s_poly.x[k], s_poly.x[k + 1]};
+                const float yn[3] = {s_poly.y[0], s_poly.y[k], s_poly.y[k + 1]};
+                const float zn[3] = {s_poly.z[0], s_poly.z[k], s_poly.z[k + 1]};
+                Tri2 T;
+                double d[3];
+                if (depth_setup(xn, yn, zn, Wd, Hd, T, d)) depth_block(T, d, Wd, Hd, depth);
+            }
+            __syncthreads();   // before the next triangle's polygon overwrites this one
         }
     }
 }

@@ -162,6 +162,41 @@ def test_depth_maps_bit_exact(gpu, orc):
     assert np.array_equal(d.cpu().numpy(), orc.depth_map(sph, M, 400, 300))
 
 
+def _clip_scenes():
+    """Cameras whose view reaches triangles beyond the near plane or the
+    guard band (clipped, drawn as fans): a floor reaching behind the eye, the
+    same floor over a sphere it hides, a wall far beyond the guard band, the
+    eye inside a closed sphere, and the vessel seen from inside its wall."""
+    look = synth.edits.look_at_perspective
+    floor = synth.plane_grid(3, 3, A=((60.0, 0.0), (0.0, 60.0), (0.0, 0.0)), b=(-10.0, -30.0, -1.0))
+    fine_floor = synth.plane_grid(41, 41, A=((60.0, 0.0), (0.0, 60.0), (0.0, 0.0)), b=(-10.0, -30.0, -1.0))
+    ball = synth.sphere(radius=1.5, n_theta=65, n_phi=33)
+    ball = synth.Mesh(ball.pos + np.array([6.0, 0.0, -3.0], np.float32), ball.nrm, ball.uv, ball.tri)
+    wall = synth.plane_grid(3, 3, A=((0.0, 0.0), (2000.0, 0.0), (0.0, 2000.0)), b=(2.0, -1000.0, -1000.0))
+    inside = synth.sphere(radius=5.0, n_theta=65, n_phi=33)
+    vessel = synth.tiny_workload().mesh
+    eye = look((0.0, 0.0, 0.0), (1.0, 0.0, 0.0), (0.0, 0.0, 1.0))
+    return [("floor", floor, eye), ("fine floor", fine_floor, eye),
+            ("floor over ball", synth.mesh.merge_meshes([floor, ball]), eye),
+            ("wall", wall, eye), ("inside sphere", inside, look((0.0, 0.0, 0.0), (1.0, 0.3, 0.2), (0.0, 0.0, 1.0))),
+            ("inside vessel wall", vessel, look((0.75, 0.0, 1.5), (-1.0, 0.2, 1.4), (0.0, 0.0, 1.0)))]
+
+
+def test_depth_maps_clipped_bit_exact(gpu, orc):
+    """Triangles clipped at the near plane and the guard band: depth maps
+    bit-exact against the oracle at two sizes."""
+    import torch
+    for name, mesh, M in _clip_scenes():
+        print(f"case: clipped depth, {name}", flush=True)
+        dm = gpu.DeviceMesh.from_mesh(mesh)
+        for dw, dh in ((64, 48), (257, 131)):
+            d = torch.empty((dh, dw), dtype=torch.float32, device="cuda")
+            gpu.render_depth(dm, M, d)
+            od = orc.depth_map(mesh, M, dw, dh)
+            assert (od < 1.0).any(), name
+            assert np.array_equal(d.cpu().numpy(), od), (name, dw, dh)
+
+
 # ---------------------------------------------------------------------------
 # edits
 
