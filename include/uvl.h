@@ -191,10 +191,15 @@ size_t uvl_depth_workspace_bytes(int64_t nt);
  * current viewpoint, rebuilt when the viewpoint changes).  view_proj: host
  * fp32 row-major 4x4 with clip = M [x y z 1]^T.  depth: device fp32 [dh][dw],
  * row 0 at NDC y = -1, window depth 0.5 z_ndc + 0.5, cleared to 1.0; each
- * pixel keeps the nearest sample of the triangles whose three vertices have
- * clip w > 0 and |x_ndc|, |y_ndc| <= 16, rasterised with the rule of
+ * pixel keeps the nearest sample of the mesh, rasterised with the rule of
  * uvl_build_geometry_image on screen positions fmaf(ndc, .5, .5) * size and
- * interpolated in fp64; samples outside [0, 1] are dropped.
+ * interpolated in fp64; samples outside [0, 1] are dropped.  A triangle
+ * whose vertices all have clip w > 0 and lie in front of the near plane
+ * (z + w >= 0) and inside the guard band |x|, |y| <= 16 w is drawn as it
+ * is; any other is clipped against those five planes (fp64 Sutherland-
+ * Hodgman on the fp32 clip coordinates, each cut edge split from its inside
+ * end) and the polygon drawn as a fan from its first vertex, so that
+ * occluders close to the camera stay in the depth texture.
  * Errors: UVL_E_INVAL for null pointers or dw/dh outside [1, 16384];
  * UVL_E_NOMEM if ws_bytes is too small. */
 int32_t uvl_render_depth(const uvl_mesh *mesh, const float view_proj[16], float *depth, int32_t dw,
