@@ -109,9 +109,15 @@ typedef struct {
  *                 stored row-major, ceil(W/32) per row), the bounds of its
  *                 covered positions as {min x, min y, min z, max x, max y,
  *                 max z}; a tile without covered texels holds min = +inf,
- *                 max = -inf.  ceil(W/32) * ceil(H/32) * 6 floats.  Batched
- *                 waves use it to skip tiles an edit provably cannot select. */
+ *                 max = -inf: ntiles = ceil(W/32) * ceil(H/32) boxes of 6
+ *                 floats, followed by the boxes of the blocks of
+ *                 UVL_TILE_BLOCK x UVL_TILE_BLOCK tiles (block (bx, by) holds
+ *                 tiles tx in [8 bx, 8 bx + 8), ty in [8 by, 8 by + 8);
+ *                 row-major, ceil(ceil(W/32) / 8) per row), each the union
+ *                 of its tiles' boxes.  Batched waves use them to skip tiles
+ *                 (and whole blocks) an edit provably cannot select. */
 #define UVL_TILE_SIDE 32
+#define UVL_TILE_BLOCK 8
 typedef struct {
     int32_t width, height;
     int32_t *tri_id;

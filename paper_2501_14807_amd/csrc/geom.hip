@@ -664,6 +664,31 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(GeomArgs a, GeomOut g) {
     }
 }
 
+// 5. the bounds of each block of 8 x 8 tiles (the union of its tiles'),
+// after the tile bounds: one wave per block.
+__global__ __launch_bounds__(kBlock) void k_block_box(float *__restrict__ box, int tiles_x, int tiles_y) {
+    const int nbx = (tiles_x + UVL_TILE_BLOCK - 1) / UVL_TILE_BLOCK;
+    const int nby = (tiles_y + UVL_TILE_BLOCK - 1) / UVL_TILE_BLOCK;
+    const int64_t nb = (int64_t)nbx * nby, ntiles = (int64_t)tiles_x * tiles_y;
+    const int lane = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (b >= nb) return;   // whole waves
+    const int tx = (int)(b % nbx) * UVL_TILE_BLOCK + (lane % UVL_TILE_BLOCK);
+    const int ty = (int)(b / nbx) * UVL_TILE_BLOCK + (lane / UVL_TILE_BLOCK);
+    const bool in = tx < tiles_x && ty < tiles_y;
+    float v[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) v[q] = in ? box[6 * ((int64_t)ty * tiles_x + tx) + q] : (q < 3 ? INFINITY : -INFINITY);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        v[q] = wave_minf(v[q]);
+        v[q + 3] = wave_maxf(v[q + 3]);
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        if (lane == q) box[6 * (ntiles + b) + q] = v[q];
+}
+
 __global__ void k_geom_counters(GCounters *ctr) {
     if (threadIdx.x == 0) {
         ctr->big_len = 0;
@@ -712,8 +737,11 @@ extern "C" size_t uvl_geom_bytes(int32_t width, int32_t height, uint32_t flags) 
     if (flags & UVL_GEOM_BARY) planes += 2;
     if (flags & UVL_GEOM_AREA_HI) planes += 1;
     size_t bytes = planes * plane;
-    if (flags & UVL_GEOM_TILE_BOX)
-        bytes += a256((size_t)ceil_div(width, UVL_TILE_SIDE) * ceil_div(height, UVL_TILE_SIDE) * 6 * sizeof(float));
+    if (flags & UVL_GEOM_TILE_BOX) {
+        const int64_t tx = ceil_div(width, UVL_TILE_SIDE), ty = ceil_div(height, UVL_TILE_SIDE);
+        const int64_t nb = ceil_div(tx, UVL_TILE_BLOCK) * ceil_div(ty, UVL_TILE_BLOCK);
+        bytes += a256((size_t)(tx * ty + nb) * 6 * sizeof(float));
+    }
     return bytes;
 }
 
@@ -781,6 +809,11 @@ extern "C" int32_t uvl_build_geometry_image(const uvl_mesh *mesh, uvl_geom *g, v
         fill_bytes(a.toff, ntiles * 4, s);
     }
     hipLaunchKernelGGL(k_tile, dim3((unsigned)ntiles), dim3(kTileThreads), 0, s, a, o);
+    if (g->tile_box) {
+        const int64_t nb = ceil_div(a.tiles_x, UVL_TILE_BLOCK) * ceil_div(a.tiles_y, UVL_TILE_BLOCK);
+        hipLaunchKernelGGL(k_block_box, dim3((unsigned)ceil_div(nb, kBlock / 64)), dim3(kBlock), 0, s, g->tile_box,
+                           a.tiles_x, a.tiles_y);
+    }
     if (launch_status() != UVL_OK) return UVL_E_DEVICE;
     GCounters host{};
     if (hipMemcpyAsync(&host, a.ctr, sizeof(GCounters), hipMemcpyDeviceToHost, s) != hipSuccess) return UVL_E_DEVICE;

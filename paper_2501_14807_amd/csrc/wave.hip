@@ -230,8 +230,9 @@ __device__ __forceinline__ int last_le(int n, int64_t v, F key) {
 // Cull pass: one wave per block of 8 x 8 tiles of a culling stream (lane l:
 // tile (l % 8, l / 8) of the block), grid-striding over the blocks.  Each
 // edit is first tested against the block's bounds (the union of its tiles'
-// bounds, contains every texel of the block); only edits that survive that
-// are tested per tile.  A lane's masks (one word per group of 64 edits) go
+// bounds, contains every texel of the block, stored by the geometry build
+// after the tile bounds); only edits that survive that are tested per tile,
+// and a block no edit survives reads no tile bounds at all.  A lane's masks (one word per group of 64 edits) go
 // to masks[mask0 + tile * groups + g] -- with one group, only for live tiles,
 // the only ones the wave kernel reads -- and the wave's tiles with a live
 // edit are appended to the stream's live list.
@@ -255,31 +256,44 @@ __global__ __launch_bounds__(kBlock) void k_wave_cull(char *__restrict__ ws, uin
         const int groups = (S.ne + 63) >> 6;
         const int tiles_y = S.ntiles / S.tiles_x;
         const int64_t blk = cw - S.cwave0;
-        const int nbx = (S.tiles_x + 7) >> 3;
-        const int tx = (int)(blk % nbx) * 8 + (lane & 7), ty = (int)(blk / nbx) * 8 + (lane >> 3);
+        const int nbx = (S.tiles_x + UVL_TILE_BLOCK - 1) / UVL_TILE_BLOCK;
+        const int tx = (int)(blk % nbx) * UVL_TILE_BLOCK + (lane % UVL_TILE_BLOCK);
+        const int ty = (int)(blk / nbx) * UVL_TILE_BLOCK + (lane / UVL_TILE_BLOCK);
         const bool in = tx < S.tiles_x && ty < tiles_y;
         const int64_t ti = (int64_t)ty * S.tiles_x + tx;
-        float box[6];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) box[q] = in ? S.box[6 * ti + q] : (q < 3 ? INFINITY : -INFINITY);
+        // the block's bounds, stored after the tiles' by the geometry build
+        // (wave-uniform: scalar loads)
         float bb[6];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            bb[q] = wave_min_f32(box[q]);
-            bb[q + 3] = -wave_min_f32(-box[q + 3]);
-        }
+        for (int q = 0; q < 6; ++q) bb[q] = S.box[6 * ((int64_t)S.ntiles + blk) + q];
+        // the lane's tile bounds, read once some edit survives the block test
+        float box[6];
+        bool have_box = false;
         bool any = false;
         for (int g = 0; g < groups; ++g) {
             uint64_t m = 0, im = 0;
             const int lim = S.ne - 64 * g < 64 ? S.ne - 64 * g : 64;
+            // block test (the same for every lane) ...
+            uint64_t alive = 0;
             for (int k = 0; k < lim; ++k) {
                 const UVL_CONST WaveEdit &E = edits[S.e0 + 64 * g + k];
                 const bool brush = E.kind == UVL_EDIT_BRUSH;
                 const BrushParams B{E.cx, E.cy, E.cz, E.r2};
-                // block test (the same for every lane), then the lane's tile
                 const bool block_dead = brush ? brush_culls(B, bb)
                                               : lasso_tile(lassos[E.lasso], bb, E.depth) == kTileCulled;
-                if (block_dead) continue;
+                alive |= (uint64_t)!block_dead << k;
+            }
+            // ... then the lane's tile, for the edits that survive it
+            if (alive && !have_box) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) box[q] = in ? S.box[6 * ti + q] : (q < 3 ? INFINITY : -INFINITY);
+                have_box = true;
+            }
+            for (uint64_t a = alive; a; a &= a - 1) {
+                const int k = __builtin_ctzll(a);
+                const UVL_CONST WaveEdit &E = edits[S.e0 + 64 * g + k];
+                const bool brush = E.kind == UVL_EDIT_BRUSH;
+                const BrushParams B{E.cx, E.cy, E.cz, E.r2};
                 const int cls = brush ? (brush_culls(B, box) ? kTileCulled : kTileLive)
                                       : lasso_tile(lassos[E.lasso], box, E.depth);
                 m |= (uint64_t)(cls != kTileCulled) << k;
@@ -923,7 +937,7 @@ int32_t pack(uvl_wave *w, const uvl_edit *edits, int32_t n, int32_t chunks_overr
         s.cwave0 = cwaves;
         if (s.cull) {
             words += nw;
-            cwaves += ceil_div(s.tiles_x, 8) * ceil_div(s.ntiles / s.tiles_x, 8);   // blocks of 8 x 8 tiles
+            cwaves += ceil_div(s.tiles_x, UVL_TILE_BLOCK) * ceil_div(s.ntiles / s.tiles_x, UVL_TILE_BLOCK);
         }
         live_n[k] = 0;
         // padding: the outline of this stream's geometry image, if listed

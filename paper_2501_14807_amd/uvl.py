@@ -49,6 +49,7 @@ class CGeom(ctypes.Structure):
                 ("tile_box", ctypes.c_void_p), ("area_w_hi", ctypes.c_void_p)]
 
 TILE_SIDE = 32
+TILE_BLOCK = 8
 
 
 class CLayer(ctypes.Structure):
@@ -241,7 +242,10 @@ class GeometryImage:
         self.tiles_x = (self.width + TILE_SIDE - 1) // TILE_SIDE
         self.tiles_y = (self.height + TILE_SIDE - 1) // TILE_SIDE
         self.ntiles = self.tiles_x * self.tiles_y
-        self.tile_box = torch.empty((self.ntiles, 6), dtype=torch.float32, device=device) if tile_box else None
+        # tile bounds, then the bounds of the blocks of TILE_BLOCK x TILE_BLOCK tiles
+        self.nblocks = (-(-self.tiles_x // TILE_BLOCK)) * (-(-self.tiles_y // TILE_BLOCK))
+        self.tile_box = (torch.empty((self.ntiles + self.nblocks, 6), dtype=torch.float32, device=device)
+                         if tile_box else None)
         self.c = CGeom()
         self.c.width, self.c.height = self.width, self.height
         self.c.tri_id = self.tri_id.data_ptr()

@@ -156,15 +156,17 @@ def test_remap_tables_are_checked_on_the_host(uvl):
 
 def test_geom_bytes(uvl):
     """uvl_geom_bytes: each 4-byte plane rounded to 256 bytes, optional
-    planes by flag, the tile bounds of ceil(W/32) x ceil(H/32) tiles."""
+    planes by flag, the tile bounds of ceil(W/32) x ceil(H/32) tiles and of
+    their blocks of 8 x 8 tiles."""
     L = uvl.lib()
 
     def plane(w, h):
         return -(-w * h * 4 // 256) * 256
 
     for w, h in ((1, 1), (37, 53), (512, 512), (8192, 8192), (32768, 3)):
-        tiles = -(-w // 32) * -(-h // 32)
-        box = -(-tiles * 24 // 256) * 256
+        tx, ty = -(-w // 32), -(-h // 32)
+        blocks = -(-tx // 8) * -(-ty // 8)
+        box = -(-(tx * ty + blocks) * 24 // 256) * 256
         assert L.uvl_geom_bytes(w, h, 0) == 5 * plane(w, h)
         assert L.uvl_geom_bytes(w, h, 1) == 8 * plane(w, h)
         assert L.uvl_geom_bytes(w, h, 2) == 7 * plane(w, h)

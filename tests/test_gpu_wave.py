@@ -151,14 +151,15 @@ def test_wave_errors(gpu):
 
 def test_tile_boxes(gpu):
     wl = synth.tiny_workload()
-    for (W, H) in ((512, 512), (37, 53), (1000, 3), (64, 96)):
+    for (W, H) in ((512, 512), (37, 53), (1000, 3), (64, 96), (2100, 300)):
         dm = gpu.DeviceMesh.from_mesh(wl.mesh)
         g = gpu.GeometryImage(W, H)
         gpu.build_geometry_image(dm, g)
         pos = g.host()["pos"].reshape(3, H, W)
         box = g.tile_box.cpu().numpy()
         tx, ty = (W + 31) // 32, (H + 31) // 32
-        assert box.shape == (tx * ty, 6)
+        bx, by = (tx + 7) // 8, (ty + 7) // 8
+        assert box.shape == (tx * ty + bx * by, 6)
         for b in range(ty):
             for a in range(tx):
                 p = pos[:, 32 * b:32 * b + 32, 32 * a:32 * a + 32].reshape(3, -1)
@@ -169,6 +170,14 @@ def test_tile_boxes(gpu):
                     assert np.array_equal(box[k, 3:], p[:, cov].max(axis=1))
                 else:
                     assert (box[k, :3] == np.inf).all() and (box[k, 3:] == -np.inf).all()
+        # blocks of 8 x 8 tiles: the union of their tiles' bounds
+        tiles = box[:tx * ty].reshape(ty, tx, 6)
+        for b in range(by):
+            for a in range(bx):
+                t = tiles[8 * b:8 * b + 8, 8 * a:8 * a + 8].reshape(-1, 6)
+                k = tx * ty + b * bx + a
+                assert np.array_equal(box[k, :3], t[:, :3].min(axis=0)), (W, H, a, b)
+                assert np.array_equal(box[k, 3:], t[:, 3:].max(axis=0)), (W, H, a, b)
 
 
 def _project(M, p):
