@@ -79,11 +79,14 @@ __device__ __forceinline__ int depth_vertices(const Mat4 &M, const float *__rest
                                       __builtin_fmaf(M.m[4 * q + 1], y, __builtin_fmaf(M.m[4 * q + 0], x, M.m[4 * q + 3])));
             if (!isfinite(cf[k][q])) return kDrop;
         }
-        const double c[4] = {cf[k][0], cf[k][1], cf[k][2], cf[k][3]};
-        if (!(cf[k][3] > 0.0f)) inside = false;
-#pragma unroll
-        for (int p = 0; p < 5; ++p)
-            if (!(clip_dist(p, c) >= 0.0)) inside = false;
+        // the five plane tests of clip_dist, exact: 16 w is exact in fp32
+        // (or +inf where the fp64 value exceeds every float, which compares
+        // the same), so |x| <= 16 w needs no rounding; z + w takes fp64,
+        // where the sum of two floats keeps its sign
+        const float g = 16.0f * cf[k][3];
+        if (!(cf[k][3] > 0.0f) || !(cf[k][0] <= g) || !(-cf[k][0] <= g) || !(cf[k][1] <= g) ||
+            !(-cf[k][1] <= g) || !((double)cf[k][2] + (double)cf[k][3] >= 0.0))
+            inside = false;
     }
     return inside ? kDirect : kClip;
 }
