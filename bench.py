@@ -156,6 +156,26 @@ def run_step(m, wl, uvl, T):
     return bins
 
 
+def area_needed_bytes(m, uvl, torch):
+    """Bytes a fused area query over all of m's layers must read: every
+    label and every texel's weight (4 B); a query of at most two layers on
+    a geometry image with per-block area sums (8 B per block of 4 rows x 8
+    columns) reads the weights only of the blocks whose labels differ within
+    the block in some layer, the sums of the others."""
+    W, H = m.geom.width, m.geom.height
+    N = W * H
+    labels = float(sum(N * (1 if l.dtype == uvl.U8 else 2) for l in m.layers))
+    if m.geom.area_blk is None or len(m.layers) > 2 or W % 8 or H % 4:
+        return labels + 4.0 * N
+    mixed = None
+    for l in m.layers:
+        a = l.data[:N].view(H // 4, 4, W // 8, 8)
+        u = (a == a[:, :1, :, :1]).all(dim=3).all(dim=1)
+        mixed = ~u if mixed is None else (mixed | ~u)
+    nmixed = int(mixed.sum().item())
+    return labels + 8.0 * (N // 32) + 4.0 * 32 * nmixed
+
+
 def bench_batched(n_models, reps, torch, uvl):
     """Batched waves against the plain path on many models of uneven size.
 
@@ -656,8 +676,9 @@ def main():
     # algorithmic bytes per launch (what the method must move):
     #   brush: 12 B of positions per texel; lasso: the same plus its depth
     #   map once; layer operation: the operands and the destination per
-    #   texel (REMAP: one operand); area: the texel weight and every layer's
-    #   label per texel; geometry image: 40 B of planes per texel (tri_id,
+    #   texel (REMAP: one operand); area: every layer's label per texel, the
+    #   per-block area sums and the 4 B weights of the blocks whose labels
+    #   are not all equal in some layer (area_needed_bytes); geometry image: 40 B of planes per texel (tri_id,
     #   position, normal, barycentrics, area), the tile bounds, and the mesh
     #   (positions, normals, uv per vertex, indices per triangle); depth map:
     #   4 B per pixel written and the mesh's positions and indices read
@@ -670,7 +691,7 @@ def main():
         "edit_brush": 12.0 * N,
         "edit_lasso": 12.0 * N + 4.0 * dw * dh,
         "layer_op": float(sum(op_bytes)) / max(1, len(op_bytes)),
-        "area_query": float(N * (4 + sum(lb))),
+        "area_query": area_needed_bytes(m, uvl, torch),
         "build_geometry_image": 40.0 * N + 24.0 * tiles + 32.0 * nv + 12.0 * nt,
         "render_depth": 4.0 * dw * dh + 12.0 * nv + 12.0 * nt,
     }

@@ -118,6 +118,17 @@ typedef struct {
  *                 (and whole blocks) an edit provably cannot select. */
 #define UVL_TILE_SIDE 32
 #define UVL_TILE_BLOCK 8
+/*   area_blk      optional (NULL: skipped), one-word weights only (ignored
+ *                 when area_w_hi is given): for each block of
+ *                 UVL_AREA_BLK_ROWS x UVL_AREA_BLK_COLS texels (block (bx,
+ *                 by) holds texels i in [8 bx, 8 bx + 8), j in [4 by,
+ *                 4 by + 4); row-major, ceil(W/8) per row), the exact sum of
+ *                 its area_w words: ceil(W/8) * ceil(H/4) uint64, 8-byte
+ *                 aligned.  uvl_area_query adds a block's sum for a layer
+ *                 whose labels are equal over it instead of reading its 32
+ *                 weights. */
+#define UVL_AREA_BLK_ROWS 4
+#define UVL_AREA_BLK_COLS 8
 typedef struct {
     int32_t width, height;
     int32_t *tri_id;
@@ -129,6 +140,7 @@ typedef struct {
     double area_abs_err;    /* out: bound on the rounding of one texel's area   */
     float *tile_box;        /* optional per-tile position bounds (see above)    */
     uint32_t *area_w_hi;    /* optional high words of the texel areas           */
+    uint64_t *area_blk;     /* optional per-block sums of area_w (see above)    */
 } uvl_geom;
 
 /* A layer's data texture: width*height values of `dtype`, device memory,
@@ -145,6 +157,7 @@ typedef struct {
 #define UVL_GEOM_BARY     2u   /* bary1, bary2 */
 #define UVL_GEOM_TILE_BOX 4u   /* tile_box */
 #define UVL_GEOM_AREA_HI  8u   /* area_w_hi */
+#define UVL_GEOM_AREA_BLK 16u  /* area_blk */
 
 /* Device bytes of the planes of a width x height geometry image: each plane
  * of N = width*height elements rounded up to a multiple of 256 bytes (so

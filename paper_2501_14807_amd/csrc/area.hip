@@ -21,7 +21,11 @@
 // ragged unit takes a path with per-row checks).  Per layer, runs of equal
 // labels go to the workgroup's bins; a row whose 8 labels are equal (the
 // common case: labelled regions are spatially coherent) is checked on the
-// packed words and adds its row sum.  u8 layers add into 256 LDS bins each
+// packed words and adds its row sum.  A query of one or two layers on a
+// geometry image with per-block area sums (one 64-bit sum per 4 x 8
+// texels, a lane's share of a unit) reads no weights where the lane's
+// labels are all equal: it adds the block's sum, and a lane whose labels
+// differ reads its weights then.  u8 layers add into 256 LDS bins each
 // (native 64-bit LDS atomics); u16 layers (65536 bins) add into an LDS hash
 // table keyed by (layer, label), open addressing with linear probing,
 // falling back to the global bin only if 16 probes find no slot.  The LDS
@@ -39,6 +43,8 @@ constexpr int kCols = 8;                  // columns per lane
 constexpr int kChunk = 64 * kCols;        // columns per wave unit
 constexpr int kMaxLayers = 32;
 constexpr int kU8Group = 4;               // u8 layers whose labels are loaded together
+constexpr int kBlkGroup = 1;              // the same with per-block area sums (weights held lazily)
+constexpr int kBlkMaxLayers = 2;          // queries of at most this many layers use the block sums
 constexpr int kHashBits = 11;
 constexpr int kHash = 1 << kHashBits;     // LDS hash slots for u16 labels
 constexpr uint32_t kEmptyKey = 0xffffffffu;
@@ -131,13 +137,16 @@ struct RowLabels {
         constexpr int kPerWord = 4 / sizeof(T);
         return (w[k / kPerWord] >> (8 * sizeof(T) * (k % kPerWord))) & (sizeof(T) == 1 ? 0xffu : 0xffffu);
     }
+    // a word made of the first label of w, repeated
+    static __device__ __forceinline__ uint32_t replicate(uint32_t w) {
+        return sizeof(T) == 1 ? (w & 0xffu) * 0x01010101u : (w & 0xffffu) * 0x00010001u;
+    }
     // all kCols labels equal: every word equal and made of one repeated label
     __device__ __forceinline__ bool uniform() const {
         bool eq = true;
 #pragma unroll
         for (int i = 1; i < kWords; ++i) eq = eq && w[i] == w[0];
-        const uint32_t rep = sizeof(T) == 1 ? (w[0] & 0xffu) * 0x01010101u : (w[0] & 0xffffu) * 0x00010001u;
-        return eq && w[0] == rep;
+        return eq && w[0] == replicate(w[0]);
     }
 };
 
@@ -255,6 +264,82 @@ __device__ __forceinline__ void u8_group(const AreaArgs &A, int l, const Bins<kW
     }
 }
 
+// All of a lane's labels equal (its whole block of kRows x kCols texels).
+template <typename T, int kRows>
+__device__ __forceinline__ bool unit_uniform(const RowLabels<T> lab[kRows]) {
+    const uint32_t rep = RowLabels<T>::replicate(lab[0].w[0]);
+    bool all = true;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r)
+#pragma unroll
+        for (int q = 0; q < RowLabels<T>::kWords; ++q) all = all && lab[r].w[q] == rep;
+    return all;
+}
+
+// One layer over a full unit with the block's area sum at hand: a lane
+// whose labels are all equal adds the sum; any other reads its weights
+// (once per unit, only that lane) and adds its runs.
+template <typename T, int kRows, typename Add>
+__device__ __forceinline__ void blk_layer(const RowLabels<T> lab[kRows], const Sum<false> &bs,
+                                          const uint32_t *__restrict__ aw, int64_t t0, int W,
+                                          UnitWeights<false, kRows> &U, bool &have_w, Add &&add) {
+    if (unit_uniform<T, kRows>(lab)) {
+        if (bs.nonzero()) add(lab[0].at(0), bs);
+        return;
+    }
+    if (!have_w) {
+        load_weights<true, false, kRows>(aw, nullptr, t0, W, kRows, kCols, true, U);
+        have_w = true;
+    }
+    unit_runs<true, T, false, kRows>(lab, kRows, U, add);
+}
+
+// A full unit of one-word weights with per-block area sums (area_blk):
+// u8 layers in groups of up to kU8Group (labels requested together), then
+// u16 layers; the weights are read only by lanes whose labels differ
+// within their block in some layer.
+template <int kNU8, bool kU16, int kRows>
+__device__ __forceinline__ void area_unit_blk(const AreaArgs &A, const Bins<false> &bins,
+                                              const uint32_t *__restrict__ aw,
+                                              const unsigned long long *__restrict__ blk, int64_t t0, int W,
+                                              int64_t bidx) {
+    Sum<false> bs;
+    bs.lo = blk[bidx];
+    UnitWeights<false, kRows> U;
+    bool have_w = false;
+    if constexpr (kNU8 > 0)
+        for (int l = 0; l < A.nu8;) {
+            const int g = A.nu8 - l >= kBlkGroup ? kBlkGroup : 1;
+            if (g == kBlkGroup) {
+                RowLabels<uint8_t> lab[kBlkGroup][kRows];
+#pragma unroll
+                for (int j = 0; j < kBlkGroup; ++j)
+                    load_rows<true, uint8_t, kRows>(static_cast<const uint8_t *>(A.data[l + j]), t0, W, kRows, kCols,
+                                                    true, lab[j]);
+#pragma unroll
+                for (int j = 0; j < kBlkGroup; ++j) {
+                    const int row = l + j;
+                    blk_layer<uint8_t, kRows>(lab[j], bs, aw, t0, W, U, have_w,
+                                              [&](uint32_t lb, const Sum<false> &v) { bins.add_u8(row, lb, v); });
+                }
+            } else {
+                RowLabels<uint8_t> lab[kRows];
+                load_rows<true, uint8_t, kRows>(static_cast<const uint8_t *>(A.data[l]), t0, W, kRows, kCols, true, lab);
+                const int row = l;
+                blk_layer<uint8_t, kRows>(lab, bs, aw, t0, W, U, have_w,
+                                          [&](uint32_t lb, const Sum<false> &v) { bins.add_u8(row, lb, v); });
+            }
+            l += g;
+        }
+    if constexpr (kU16)
+        for (int l = A.nu8; l < A.nl; ++l) {
+            RowLabels<uint16_t> lab[kRows];
+            load_rows<true, uint16_t, kRows>(static_cast<const uint16_t *>(A.data[l]), t0, W, kRows, kCols, true, lab);
+            blk_layer<uint16_t, kRows>(lab, bs, aw, t0, W, U, have_w,
+                                       [&](uint32_t lb, const Sum<false> &v) { bins.add_u16(l, lb, v); });
+        }
+}
+
 // One unit over every layer of the query: its weights, then the u8 layers
 // (first in A) in groups of up to kU8Group, then the u16 layers.
 template <bool kFull, int kNU8, bool kU16, bool kWide, int kRows>
@@ -282,9 +367,14 @@ __device__ __forceinline__ void area_unit(const AreaArgs &A, const Bins<kWide> &
 
 // kNU8: LDS bin rows for u8 layers (>= the query's u8 layer count);
 // kU16: the query has u16 layers; kWide: two-word weights.
-template <int kNU8, bool kU16, bool kWide, int kRows>
+// kBlk: one-word weights with per-block area sums (blk, ceil(W/8) per row).
+template <int kNU8, bool kU16, bool kWide, int kRows, bool kBlk>
 __global__ __launch_bounds__(kAreaBlock) void k_area(const uint32_t *__restrict__ aw,
-                                                      const uint32_t *__restrict__ aw_hi, int W, int H, AreaArgs A) {
+                                                      const uint32_t *__restrict__ aw_hi,
+                                                      const unsigned long long *__restrict__ blk, int W, int H,
+                                                      AreaArgs A) {
+    static_assert(!kBlk || (!kWide && kRows == UVL_AREA_BLK_ROWS && kCols == UVL_AREA_BLK_COLS),
+                  "a unit's lane covers one area block");
     constexpr int kBinRows = kNU8 > 0 ? (kWide ? 2 * kNU8 : kNU8) : 1;
     __shared__ unsigned long long s_bins[kBinRows * 256];
     __shared__ uint32_t s_key[kU16 ? kHash : 1];
@@ -310,7 +400,13 @@ __global__ __launch_bounds__(kAreaBlock) void k_area(const uint32_t *__restrict_
         const bool vec = (W % kCols) == 0 && ncol == kCols;
         const int64_t t0 = (int64_t)row0 * W + col;
         if (ncol == 0) continue;
-        if (nrows == kRows && vec) area_unit<true, kNU8, kU16, kWide, kRows>(A, bins, aw, aw_hi, t0, W, nrows, ncol, vec);
+        if (nrows == kRows && vec) {
+            if constexpr (kBlk)
+                area_unit_blk<kNU8, kU16, kRows>(A, bins, aw, blk, t0, W,
+                                                 (int64_t)rb * ((W + kCols - 1) / kCols) + col / kCols);
+            else
+                area_unit<true, kNU8, kU16, kWide, kRows>(A, bins, aw, aw_hi, t0, W, nrows, ncol, vec);
+        }
         else area_unit<false, kNU8, kU16, kWide, kRows>(A, bins, aw, aw_hi, t0, W, nrows, ncol, vec);
     }
     __syncthreads();
@@ -336,34 +432,43 @@ __global__ __launch_bounds__(kAreaBlock) void k_area(const uint32_t *__restrict_
 }
 
 // Workgroups: one per CU at most, fewer when there are few units.
+// blk: per-block area sums (one-word weights only), or null.
 template <int kNU8, bool kU16, bool kWide>
-void launch_area(hipStream_t s, const uint32_t *aw, const uint32_t *aw_hi, int W, int H, const AreaArgs &A) {
+void launch_area(hipStream_t s, const uint32_t *aw, const uint32_t *aw_hi, const unsigned long long *blk, int W,
+                 int H, const AreaArgs &A) {
     constexpr int kRows = kWide ? 2 : 4;   // two-word weights: half the rows, the same registers
     const int64_t units = ceil_div(W, kChunk) * ceil_div(H, kRows);
     int64_t g = ceil_div(units, kAreaWaves * 2);
     if (g > 256) g = 256;
     if (g < 1) g = 1;
-    hipLaunchKernelGGL((k_area<kNU8, kU16, kWide, kRows>), dim3((unsigned)g), dim3(kAreaBlock), 0, s, aw, aw_hi, W, H,
-                       A);
+    if constexpr (!kWide) {
+        if (blk) {
+            hipLaunchKernelGGL((k_area<kNU8, kU16, false, kRows, true>), dim3((unsigned)g), dim3(kAreaBlock), 0, s,
+                               aw, aw_hi, blk, W, H, A);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_area<kNU8, kU16, kWide, kRows, false>), dim3((unsigned)g), dim3(kAreaBlock), 0, s, aw, aw_hi,
+                       blk, W, H, A);
 }
 
 template <bool kWide>
-void launch_by_layers(hipStream_t s, const uint32_t *aw, const uint32_t *aw_hi, int W, int H, const AreaArgs &A,
-                      int nu8, bool u16) {
+void launch_by_layers(hipStream_t s, const uint32_t *aw, const uint32_t *aw_hi, const unsigned long long *blk, int W,
+                      int H, const AreaArgs &A, int nu8, bool u16) {
     // bin rows rounded up to a power of two: fewer kernel instances
     if (u16) {
-        if (nu8 == 0) launch_area<0, true, kWide>(s, aw, aw_hi, W, H, A);
-        else if (nu8 <= 1) launch_area<1, true, kWide>(s, aw, aw_hi, W, H, A);
-        else if (nu8 <= 4) launch_area<4, true, kWide>(s, aw, aw_hi, W, H, A);
-        else if (nu8 <= 8) launch_area<8, true, kWide>(s, aw, aw_hi, W, H, A);
-        else if (nu8 <= 16) launch_area<16, true, kWide>(s, aw, aw_hi, W, H, A);
-        else launch_area<(kWide ? 16 : 32), true, kWide>(s, aw, aw_hi, W, H, A);
+        if (nu8 == 0) launch_area<0, true, kWide>(s, aw, aw_hi, blk, W, H, A);
+        else if (nu8 <= 1) launch_area<1, true, kWide>(s, aw, aw_hi, blk, W, H, A);
+        else if (nu8 <= 4) launch_area<4, true, kWide>(s, aw, aw_hi, blk, W, H, A);
+        else if (nu8 <= 8) launch_area<8, true, kWide>(s, aw, aw_hi, blk, W, H, A);
+        else if (nu8 <= 16) launch_area<16, true, kWide>(s, aw, aw_hi, blk, W, H, A);
+        else launch_area<(kWide ? 16 : 32), true, kWide>(s, aw, aw_hi, blk, W, H, A);
     } else {
-        if (nu8 <= 1) launch_area<1, false, kWide>(s, aw, aw_hi, W, H, A);
-        else if (nu8 <= 4) launch_area<4, false, kWide>(s, aw, aw_hi, W, H, A);
-        else if (nu8 <= 8) launch_area<8, false, kWide>(s, aw, aw_hi, W, H, A);
-        else if (nu8 <= 16) launch_area<16, false, kWide>(s, aw, aw_hi, W, H, A);
-        else launch_area<(kWide ? 16 : 32), false, kWide>(s, aw, aw_hi, W, H, A);
+        if (nu8 <= 1) launch_area<1, false, kWide>(s, aw, aw_hi, blk, W, H, A);
+        else if (nu8 <= 4) launch_area<4, false, kWide>(s, aw, aw_hi, blk, W, H, A);
+        else if (nu8 <= 8) launch_area<8, false, kWide>(s, aw, aw_hi, blk, W, H, A);
+        else if (nu8 <= 16) launch_area<16, false, kWide>(s, aw, aw_hi, blk, W, H, A);
+        else launch_area<(kWide ? 16 : 32), false, kWide>(s, aw, aw_hi, blk, W, H, A);
     }
 }
 
@@ -390,6 +495,7 @@ extern "C" int32_t uvl_area_query(const uvl_geom *geom, const uvl_layer *layers,
     if (!geom || !layers || !bins_dev || nlayers < 1 || nlayers > kMaxLayers) return UVL_E_INVAL;
     if (!geom->area_w || !aligned16(geom->area_w) || geom->width < 1 || geom->height < 1) return UVL_E_INVAL;
     if (geom->area_w_hi && !aligned16(geom->area_w_hi)) return UVL_E_INVAL;
+    if (reinterpret_cast<uintptr_t>(geom->area_blk) & 7) return UVL_E_INVAL;
     if (reinterpret_cast<uintptr_t>(bins_dev) & 7) return UVL_E_INVAL;
     for (int l = 0; l < nlayers; ++l) {
         if (!layer_ok(&layers[l])) return UVL_E_INVAL;
@@ -431,8 +537,16 @@ extern "C" int32_t uvl_area_query(const uvl_geom *geom, const uvl_layer *layers,
         A.nu8 = k;
         for (; i16 < u16s.size() && k < kMaxLayers; ++i16) put(u16s[i16]);
         A.nl = k;
-        if (wide) launch_by_layers<true>(s, geom->area_w, geom->area_w_hi, W, H, A, A.nu8, A.nl > A.nu8);
-        else launch_by_layers<false>(s, geom->area_w, nullptr, W, H, A, A.nu8, A.nl > A.nu8);
+        // block sums pay for one or two layers (a refresh of one layer's
+        // bins reads a third of the bytes); with more, some layer is mixed
+        // in most blocks and the weights read in mid-unit cost more than
+        // reading them up front
+        const unsigned long long *blk =
+            A.nl <= kBlkMaxLayers ? reinterpret_cast<const unsigned long long *>(geom->area_blk) : nullptr;
+        if (wide)
+            launch_by_layers<true>(s, geom->area_w, geom->area_w_hi, nullptr, W, H, A, A.nu8, A.nl > A.nu8);
+        else
+            launch_by_layers<false>(s, geom->area_w, nullptr, blk, W, H, A, A.nu8, A.nl > A.nu8);
     }
     if (launch_status() != UVL_OK) return UVL_E_DEVICE;
     if (!areas_host) return UVL_OK;

@@ -135,6 +135,7 @@ struct GeomOut {
     float *px, *py, *pz, *nx, *ny, *nz, *b1, *b2;
     uint32_t *aw, *aw_hi;
     float *box;
+    unsigned long long *blk;   // per 4 x 8 block area sums (one-word weights), or null
 };
 
 __device__ __forceinline__ bool geom_tri(const GeomArgs &a, int64_t t, Tri2 &T, int v[3]) {
@@ -435,6 +436,9 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(GeomArgs a, GeomOut g) {
     __shared__ int s_coop[kMaxCoop];
     __shared__ int s_ncoop;
     __shared__ float s_red[7][kTileThreads / 64];
+    // area sums of the tile's 8 x 4 blocks of 4 rows x 8 columns (one-word weights)
+    constexpr int kBlkRows = kTile / UVL_AREA_BLK_ROWS, kBlkCols = kTile / UVL_AREA_BLK_COLS;
+    __shared__ unsigned long long s_blk[kBlkRows * kBlkCols];
     const int64_t tile = blockIdx.x;
     const int tx = (int)(tile % a.tiles_x), ty = (int)(tile / a.tiles_x);
     const int ti0 = tx * kTile, tj0 = ty * kTile;
@@ -446,6 +450,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(GeomArgs a, GeomOut g) {
         s_own[c] = marked && i < W && j < H ? g.tri_id[(int64_t)j * W + i] : kNoOwner;
     }
     for (int h = threadIdx.x; h < kHashSlots; h += kTileThreads) s_hkey[h] = -1;
+    if (threadIdx.x < kBlkRows * kBlkCols) s_blk[threadIdx.x] = 0ull;
     if (threadIdx.x == 0) s_ncoop = 0;
     __syncthreads();
     int ex;
@@ -629,6 +634,9 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(GeomArgs a, GeomOut g) {
         }
         g.aw[idx] = (uint32_t)qw;
         if (wide) g.aw_hi[idx] = (uint32_t)(qw >> 32);
+        if (g.blk && qw)
+            atomicAdd(&s_blk[((c / kTile) / UVL_AREA_BLK_ROWS) * kBlkCols + (c % kTile) / UVL_AREA_BLK_COLS],
+                      (unsigned long long)(uint32_t)qw);
         if (R.w >= wfloor) wmin = fmin(wmin, R.w);
     }
     // the tile's position bounds and the smallest owner weight
@@ -649,6 +657,12 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(GeomArgs a, GeomOut g) {
         s_wmin[wv] = wmin;
     }
     __syncthreads();
+    if (g.blk && threadIdx.x < kBlkRows * kBlkCols) {
+        const int bi = ti0 / UVL_AREA_BLK_COLS + (int)threadIdx.x % kBlkCols;
+        const int bj = tj0 / UVL_AREA_BLK_ROWS + (int)threadIdx.x / kBlkCols;
+        const int bw = (W + UVL_AREA_BLK_COLS - 1) / UVL_AREA_BLK_COLS, bh = (H + UVL_AREA_BLK_ROWS - 1) / UVL_AREA_BLK_ROWS;
+        if (bi < bw && bj < bh) g.blk[(int64_t)bj * bw + bi] = s_blk[threadIdx.x];
+    }
     if (threadIdx.x < 6 && g.box) {
         const int cc = threadIdx.x;
         float r = s_red[cc][0];
@@ -729,7 +743,8 @@ using namespace uvl;
 
 extern "C" size_t uvl_geom_bytes(int32_t width, int32_t height, uint32_t flags) {
     if (width < 1 || height < 1 || width > kMaxSide || height > kMaxSide) return 0;
-    if (flags & ~(uint32_t)(UVL_GEOM_NRM | UVL_GEOM_BARY | UVL_GEOM_TILE_BOX | UVL_GEOM_AREA_HI)) return 0;
+    if (flags & ~(uint32_t)(UVL_GEOM_NRM | UVL_GEOM_BARY | UVL_GEOM_TILE_BOX | UVL_GEOM_AREA_HI | UVL_GEOM_AREA_BLK))
+        return 0;
     const size_t n = (size_t)width * height;
     const size_t plane = a256(n * 4);        // every plane holds 4-byte elements
     size_t planes = 5;                        // tri_id, pos x/y/z, area_w
@@ -742,6 +757,8 @@ extern "C" size_t uvl_geom_bytes(int32_t width, int32_t height, uint32_t flags) 
         const int64_t nb = ceil_div(tx, UVL_TILE_BLOCK) * ceil_div(ty, UVL_TILE_BLOCK);
         bytes += a256((size_t)(tx * ty + nb) * 6 * sizeof(float));
     }
+    if (flags & UVL_GEOM_AREA_BLK)
+        bytes += a256((size_t)ceil_div(width, UVL_AREA_BLK_COLS) * ceil_div(height, UVL_AREA_BLK_ROWS) * 8);
     return bytes;
 }
 
@@ -761,6 +778,7 @@ extern "C" int32_t uvl_build_geometry_image(const uvl_mesh *mesh, uvl_geom *g, v
     const bool has_n = g->nrm_x || g->nrm_y || g->nrm_z, has_b = g->bary1 || g->bary2;
     if (has_n && !(g->nrm_x && g->nrm_y && g->nrm_z)) return UVL_E_INVAL;
     if (has_b && !(g->bary1 && g->bary2)) return UVL_E_INVAL;
+    if (reinterpret_cast<uintptr_t>(g->area_blk) & 7) return UVL_E_INVAL;
     if (ws_bytes < uvl_build_workspace_bytes(mesh->nt, g->width, g->height)) return UVL_E_NOMEM;
     if (int32_t s = device_ok()) return s;
 
@@ -790,7 +808,8 @@ extern "C" int32_t uvl_build_geometry_image(const uvl_mesh *mesh, uvl_geom *g, v
     a.tflag = reinterpret_cast<unsigned *>(w + L.tflag);
     a.blk = reinterpret_cast<unsigned *>(w + L.blk);
     GeomOut o{g->tri_id, g->pos_x, g->pos_y, g->pos_z, has_n ? g->nrm_x : nullptr, g->nrm_y, g->nrm_z,
-              has_b ? g->bary1 : nullptr, g->bary2, g->area_w, g->area_w_hi, g->tile_box};
+              has_b ? g->bary1 : nullptr, g->bary2, g->area_w, g->area_w_hi, g->tile_box,
+              g->area_w_hi ? nullptr : reinterpret_cast<unsigned long long *>(g->area_blk)};
 
     hipLaunchKernelGGL(k_geom_counters, dim3(1), dim3(64), 0, s, a.ctr);
     fill_bytes(a.tcount, ntiles * 4, s);

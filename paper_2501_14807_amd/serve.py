@@ -232,7 +232,7 @@ class GpuExecutor(Executor):
     def footprint(self, model):
         sp, uvl = self.specs[model], self.uvl
         n = sp.width * sp.height
-        geom = uvl.lib().uvl_geom_bytes(sp.width, sp.height, 7)
+        geom = uvl.lib().uvl_geom_bytes(sp.width, sp.height, 7 | 16)
         layers = sum(n * (1 if dt == uvl.U8 else 2) for dt in sp.layer_dtypes)
         bins = sum(8 * (256 if dt == uvl.U8 else 65536) for dt in sp.layer_dtypes)
         depth = len(self.cameras[model]) * sp.depth * sp.depth * 4

@@ -46,10 +46,11 @@ class CGeom(ctypes.Structure):
                 ("bary1", ctypes.c_void_p), ("bary2", ctypes.c_void_p),
                 ("area_w", ctypes.c_void_p),
                 ("area_scale", ctypes.c_double), ("area_abs_err", ctypes.c_double),
-                ("tile_box", ctypes.c_void_p), ("area_w_hi", ctypes.c_void_p)]
+                ("tile_box", ctypes.c_void_p), ("area_w_hi", ctypes.c_void_p), ("area_blk", ctypes.c_void_p)]
 
 TILE_SIDE = 32
 TILE_BLOCK = 8
+AREA_BLK_ROWS, AREA_BLK_COLS = 4, 8
 
 
 class CLayer(ctypes.Structure):
@@ -227,7 +228,7 @@ class GeometryImage:
     """
 
     def __init__(self, width: int, height: int, normals: bool = True, bary: bool = True,
-                 device="cuda", tile_box: bool = True, wide: bool = False):
+                 device="cuda", tile_box: bool = True, wide: bool = False, area_blk: bool = True):
         self.width, self.height = int(width), int(height)
         n = self.width * self.height
         self.n = n
@@ -256,6 +257,12 @@ class GeometryImage:
             self.c.bary1, self.c.bary2 = self.bary[0].data_ptr(), self.bary[1].data_ptr()
         self.c.area_w = self.area_w.data_ptr()
         self.c.tile_box = None if self.tile_box is None else self.tile_box.data_ptr()
+        # per-block sums of the one-word texel areas (4 rows x 8 columns)
+        self.area_blk = None
+        if area_blk and not wide:
+            nb = (-(-self.width // AREA_BLK_COLS)) * (-(-self.height // AREA_BLK_ROWS))
+            self.area_blk = torch.empty(nb, dtype=torch.int64, device=device)
+            self.c.area_blk = self.area_blk.data_ptr()
         if wide:
             self.make_wide()
         self.c.area_scale = 0.0
@@ -268,6 +275,8 @@ class GeometryImage:
         if self.area_w_hi is None:
             self.area_w_hi = torch.empty(self.area_w.numel(), dtype=torch.int32, device=self._device)
             self.c.area_w_hi = self.area_w_hi.data_ptr()
+            self.area_blk = None                  # block sums are for one-word areas only
+            self.c.area_blk = None
 
     @property
     def wide(self) -> bool:
@@ -282,7 +291,7 @@ class GeometryImage:
         return float(self.c.area_abs_err)
 
     def nbytes(self) -> int:
-        ts = [self.tri_id, self.pos, self.nrm, self.bary, self.area_w, self.tile_box, self.area_w_hi]
+        ts = [self.tri_id, self.pos, self.nrm, self.bary, self.area_w, self.tile_box, self.area_w_hi, self.area_blk]
         return sum(t.numel() * t.element_size() for t in ts if t is not None)
 
     # host copies of the first n elements of each plane
@@ -292,6 +301,8 @@ class GeometryImage:
                "area_w": self.area_w[:n].cpu().numpy().view(np.uint32)}
         if self.area_w_hi is not None:
             out["area_w_hi"] = self.area_w_hi[:n].cpu().numpy().view(np.uint32)
+        if self.area_blk is not None:
+            out["area_blk"] = self.area_blk.cpu().numpy().view(np.uint64)
         if self.nrm is not None:
             out["nrm"] = self.nrm[:, :n].cpu().numpy()
         if self.bary is not None:

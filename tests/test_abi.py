@@ -157,7 +157,7 @@ def test_remap_tables_are_checked_on_the_host(uvl):
 def test_geom_bytes(uvl):
     """uvl_geom_bytes: each 4-byte plane rounded to 256 bytes, optional
     planes by flag, the tile bounds of ceil(W/32) x ceil(H/32) tiles and of
-    their blocks of 8 x 8 tiles."""
+    their blocks of 8 x 8 tiles, the area sums of 4 x 8 texel blocks."""
     L = uvl.lib()
 
     def plane(w, h):
@@ -171,12 +171,14 @@ def test_geom_bytes(uvl):
         assert L.uvl_geom_bytes(w, h, 1) == 8 * plane(w, h)
         assert L.uvl_geom_bytes(w, h, 2) == 7 * plane(w, h)
         assert L.uvl_geom_bytes(w, h, 7) == 10 * plane(w, h) + box
+        blk = -(-(-(-w // 8) * -(-h // 4) * 8) // 256) * 256
+        assert L.uvl_geom_bytes(w, h, 16) == 5 * plane(w, h) + blk
     assert L.uvl_geom_bytes(0, 5, 0) == 0
     assert L.uvl_geom_bytes(5, 32769, 0) == 0
     assert L.uvl_geom_bytes(5, 5, 64) == 0
     # the binding's geometry image allocates what the library states (CPU tensors)
     g = uvl.GeometryImage(300, 173, device="cpu")
-    assert g.nbytes() <= L.uvl_geom_bytes(300, 173, 7) < g.nbytes() + 256
+    assert g.nbytes() <= L.uvl_geom_bytes(300, 173, 7 | 16) < g.nbytes() + 2 * 256
 
 
 def test_build_and_depth_validation(uvl):

@@ -2,7 +2,7 @@
 one texel stands for, summed over a label's texels).
 
 Bars: every non-zero bin within 1e-6 relative of the oracle's fp64 area,
-empty bins exactly zero.  Cases: atlas widths above one 1024-column wave unit
+empty bins exactly zero; the per-block area sums exact.  Cases: atlas widths above one 1024-column wave unit
 and above 4096 columns, widths that are not multiples of 16 (the lanes' scalar
 path), u8 and u16 layers in one fused query and one by one; a mesh whose
 texel areas span a factor 1.6e5, which one 32-bit word per texel cannot hold
@@ -75,6 +75,25 @@ def test_area_wide_and_ragged_atlases(gpu, orc, W, H):
         assert np.array_equal(single, got), (W, H, k)
 
 
+@pytest.mark.parametrize("W,H", [(512, 512), (4100, 257), (1030, 19), (17, 300)])
+def test_area_block_sums(gpu, W, H):
+    """The geometry image's per-block area sums (blocks of 4 rows x 8
+    columns, ragged at the right and bottom edges) equal the sums of the
+    blocks' area words, exactly."""
+    wl = synth.tiny_workload()
+    dm = gpu.DeviceMesh.from_mesh(wl.mesh)
+    g = gpu.GeometryImage(W, H)
+    gpu.build_geometry_image(dm, g)
+    h = g.host()
+    aw = h["area_w"].astype(np.uint64).reshape(H, W)
+    bw, bh = -(-W // 8), -(-H // 4)
+    pad = np.zeros((bh * 4, bw * 8), np.uint64)
+    pad[:H, :W] = aw
+    want = pad.reshape(bh, 4, bw, 8).sum(axis=(1, 3)).reshape(-1)
+    assert np.array_equal(h["area_blk"], want)
+    assert want.sum() == aw.sum() > 0
+
+
 def _two_scale_mesh():
     """Two planar charts side by side in texture space with equal UV areas:
     one a unit square in 3D, the other a 400 x 400 square, so texel areas
@@ -105,7 +124,7 @@ def test_two_word_texel_areas(gpu, orc):
     # the binding rebuilds with two words
     g = gpu.GeometryImage(W, H)
     gpu.build_geometry_image(dm, g)
-    assert g.wide
+    assert g.wide and g.area_blk is None and g.c.area_blk is None
     h = g.host()
     assert np.array_equal(h["tri_id"], og.tri_id)
     a = (h["area_w_hi"].astype(np.float64) * 2.0 ** 32 + h["area_w"].astype(np.float64)) * g.area_scale
