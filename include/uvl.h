@@ -124,9 +124,11 @@ typedef struct {
  *                 by) holds texels i in [8 bx, 8 bx + 8), j in [4 by,
  *                 4 by + 4); row-major, ceil(W/8) per row), the exact sum of
  *                 its area_w words: ceil(W/8) * ceil(H/4) uint64, 8-byte
- *                 aligned.  uvl_area_query adds a block's sum for a layer
- *                 whose labels are equal over it instead of reading its 32
- *                 weights. */
+ *                 aligned, written by uvl_build_geometry_image (a caller
+ *                 that sets it afterwards must fill it the same way or
+ *                 leave it NULL).  uvl_area_query, for one or two layers,
+ *                 adds a block's sum for a layer whose labels are equal over
+ *                 it instead of reading its 32 weights. */
 #define UVL_AREA_BLK_ROWS 4
 #define UVL_AREA_BLK_COLS 8
 typedef struct {
