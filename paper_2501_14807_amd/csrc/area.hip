@@ -43,7 +43,6 @@ constexpr int kCols = 8;                  // columns per lane
 constexpr int kChunk = 64 * kCols;        // columns per wave unit
 constexpr int kMaxLayers = 32;
 constexpr int kU8Group = 4;               // u8 layers whose labels are loaded together
-constexpr int kBlkGroup = 1;              // the same with per-block area sums (weights held lazily)
 constexpr int kBlkMaxLayers = 2;          // queries of at most this many layers use the block sums
 constexpr int kHashBits = 11;
 constexpr int kHash = 1 << kHashBits;     // LDS hash slots for u16 labels
@@ -295,9 +294,8 @@ __device__ __forceinline__ void blk_layer(const RowLabels<T> lab[kRows], const S
 }
 
 // A full unit of one-word weights with per-block area sums (area_blk):
-// u8 layers in groups of up to kU8Group (labels requested together), then
-// u16 layers; the weights are read only by lanes whose labels differ
-// within their block in some layer.
+// layer by layer, u8 layers first; the weights are read only by lanes whose
+// labels differ within their block in some layer.
 template <int kNU8, bool kU16, int kRows>
 __device__ __forceinline__ void area_unit_blk(const AreaArgs &A, const Bins<false> &bins,
                                               const uint32_t *__restrict__ aw,
@@ -308,28 +306,11 @@ __device__ __forceinline__ void area_unit_blk(const AreaArgs &A, const Bins<fals
     UnitWeights<false, kRows> U;
     bool have_w = false;
     if constexpr (kNU8 > 0)
-        for (int l = 0; l < A.nu8;) {
-            const int g = A.nu8 - l >= kBlkGroup ? kBlkGroup : 1;
-            if (g == kBlkGroup) {
-                RowLabels<uint8_t> lab[kBlkGroup][kRows];
-#pragma unroll
-                for (int j = 0; j < kBlkGroup; ++j)
-                    load_rows<true, uint8_t, kRows>(static_cast<const uint8_t *>(A.data[l + j]), t0, W, kRows, kCols,
-                                                    true, lab[j]);
-#pragma unroll
-                for (int j = 0; j < kBlkGroup; ++j) {
-                    const int row = l + j;
-                    blk_layer<uint8_t, kRows>(lab[j], bs, aw, t0, W, U, have_w,
-                                              [&](uint32_t lb, const Sum<false> &v) { bins.add_u8(row, lb, v); });
-                }
-            } else {
-                RowLabels<uint8_t> lab[kRows];
-                load_rows<true, uint8_t, kRows>(static_cast<const uint8_t *>(A.data[l]), t0, W, kRows, kCols, true, lab);
-                const int row = l;
-                blk_layer<uint8_t, kRows>(lab, bs, aw, t0, W, U, have_w,
-                                          [&](uint32_t lb, const Sum<false> &v) { bins.add_u8(row, lb, v); });
-            }
-            l += g;
+        for (int l = 0; l < A.nu8; ++l) {
+            RowLabels<uint8_t> lab[kRows];
+            load_rows<true, uint8_t, kRows>(static_cast<const uint8_t *>(A.data[l]), t0, W, kRows, kCols, true, lab);
+            blk_layer<uint8_t, kRows>(lab, bs, aw, t0, W, U, have_w,
+                                      [&](uint32_t lb, const Sum<false> &v) { bins.add_u8(l, lb, v); });
         }
     if constexpr (kU16)
         for (int l = A.nu8; l < A.nl; ++l) {
