@@ -259,7 +259,7 @@ def bench_batched(n_models, reps, torch, uvl):
 # offered request rates of the serving sweep (requests/s); a mode's sweep
 # stops once its p99 passes SERVE_SATURATED_MS (higher rates only queue more)
 SERVE_RATES = (12000.0, 13000.0, 14000.0, 15000.0, 16000.0, 24000.0, 40000.0, 48000.0, 52000.0, 56000.0, 60000.0,
-               64000.0, 68000.0, 72000.0, 76000.0, 80000.0)
+               64000.0, 66000.0, 68000.0, 70000.0, 72000.0, 76000.0, 80000.0)
 SERVE_SATURATED_MS = 200.0
 SERVE_SLOS_MS = (5.0, 10.0, 20.0)
 
