@@ -16,9 +16,9 @@
 // two-word weights); a wave takes units in turn, each lane holding 8
 // consecutive columns: it loads the unit's weights into registers, where
 // they stay while the wave walks the layers, u8 layers first, requesting
-// the labels of up to four u8 layers before it sums any (a unit whose rows
-// and columns all exist has every load issued ahead of the first wait; a
-// ragged unit takes a path with per-row checks).  Per layer, runs of equal
+// the labels of two u8 layers (four with 1024-thread workgroups) before it
+// sums any (a unit whose rows and columns all exist has every load issued
+// ahead of the first wait; a ragged unit takes a path with per-row checks).  Per layer, runs of equal
 // labels go to the workgroup's bins; a row whose 8 labels are equal (the
 // common case: labelled regions are spatially coherent) is checked on the
 // packed words and adds its row sum.  A query of one or two layers on a
@@ -29,24 +29,37 @@
 // (native 64-bit LDS atomics); u16 layers (65536 bins) add into an LDS hash
 // table keyed by (layer, label), open addressing with linear probing,
 // falling back to the global bin only if 16 probes find no slot.  The LDS
-// bins go to the global bins once per workgroup.  A workgroup is 16 waves
-// with up to 88 KiB of LDS (gfx950 has 160 KiB per CU), one workgroup per
-// CU stride over the units.
+// bins go to the global bins once per workgroup.  A workgroup (8 waves for
+// queries of up to 8 u8 layers, else 16, with up to 88 KiB of LDS of the
+// CU's 160 KiB) strides over the units with the others.
 #include "uvl_internal.h"
 
 namespace uvl {
 namespace {
 
-constexpr int kAreaBlock = 1024;          // 16 waves
-constexpr int kAreaWaves = kAreaBlock / 64;
 constexpr int kCols = 8;                  // columns per lane
 constexpr int kChunk = 64 * kCols;        // columns per wave unit
 constexpr int kMaxLayers = 32;
-constexpr int kU8Group = 4;               // u8 layers whose labels are loaded together
 constexpr int kBlkMaxLayers = 2;          // queries of at most this many layers use the block sums
 constexpr int kHashBits = 11;
 constexpr int kHash = 1 << kHashBits;     // LDS hash slots for u16 labels
 constexpr uint32_t kEmptyKey = 0xffffffffu;
+
+// LDS of one workgroup: the u8 bins (two rows per layer with two-word
+// weights) and the u16 hash.
+constexpr int area_lds_bytes(int nu8, bool u16, bool wide) {
+    return (nu8 > 0 ? (wide ? 2 : 1) * nu8 * 256 * 8 : 0) + (u16 ? kHash * 4 + (wide ? 2 : 1) * kHash * 8 : 0);
+}
+
+// Threads per workgroup of the one-pass query: 512 for up to 8 u8 bin rows
+// where two workgroups fit the CU's 160 KiB of LDS, else 1024 (one
+// workgroup of 16 waves per CU).  Measured at 8192^2: 8 u8 + 1 u16 layers
+// 166-170 us with 512 threads (groups of two u8 layers, three workgroups
+// per CU at most) against 190 us with 1024 (groups of four, one per CU);
+// 32 u8 layers 1.70 ms with 1024 against 1.88-1.93 ms with 512.
+constexpr int area_threads(int nu8, bool u16, bool wide) {
+    return nu8 <= 8 && area_lds_bytes(nu8, u16, wide) <= 80 * 1024 ? 512 : 1024;
+}
 constexpr uint32_t kNoLabel = 0xffffffffu;
 
 struct AreaArgs {
@@ -322,8 +335,9 @@ __device__ __forceinline__ void area_unit_blk(const AreaArgs &A, const Bins<fals
 }
 
 // One unit over every layer of the query: its weights, then the u8 layers
-// (first in A) in groups of up to kU8Group, then the u16 layers.
-template <bool kFull, int kNU8, bool kU16, bool kWide, int kRows>
+// (first in A) in groups of up to kG, then the u16 layers.
+// kG: u8 layers whose labels are requested together.
+template <bool kFull, int kNU8, bool kU16, bool kWide, int kRows, int kG>
 __device__ __forceinline__ void area_unit(const AreaArgs &A, const Bins<kWide> &bins, const uint32_t *__restrict__ aw,
                                           const uint32_t *__restrict__ aw_hi, int64_t t0, int W, int nrows, int ncol,
                                           bool vec) {
@@ -331,8 +345,8 @@ __device__ __forceinline__ void area_unit(const AreaArgs &A, const Bins<kWide> &
     load_weights<kFull, kWide, kRows>(aw, aw_hi, t0, W, nrows, ncol, vec, U);
     if constexpr (kNU8 > 0)
         for (int l = 0; l < A.nu8;) {
-            const int g = A.nu8 - l >= kU8Group ? kU8Group : (A.nu8 - l >= 2 ? 2 : 1);
-            if (g == kU8Group) u8_group<kFull, kU8Group, kWide, kRows>(A, l, bins, t0, W, nrows, ncol, vec, U);
+            const int g = A.nu8 - l >= kG ? kG : (A.nu8 - l >= 2 ? 2 : 1);
+            if (g == kG) u8_group<kFull, kG, kWide, kRows>(A, l, bins, t0, W, nrows, ncol, vec, U);
             else if (g == 2) u8_group<kFull, 2, kWide, kRows>(A, l, bins, t0, W, nrows, ncol, vec, U);
             else u8_group<kFull, 1, kWide, kRows>(A, l, bins, t0, W, nrows, ncol, vec, U);
             l += g;
@@ -349,8 +363,8 @@ __device__ __forceinline__ void area_unit(const AreaArgs &A, const Bins<kWide> &
 // kNU8: LDS bin rows for u8 layers (>= the query's u8 layer count);
 // kU16: the query has u16 layers; kWide: two-word weights.
 // kBlk: one-word weights with per-block area sums (blk, ceil(W/8) per row).
-template <int kNU8, bool kU16, bool kWide, int kRows, bool kBlk>
-__global__ __launch_bounds__(kAreaBlock) void k_area(const uint32_t *__restrict__ aw,
+template <int kNU8, bool kU16, bool kWide, int kRows, bool kBlk, int kT>
+__global__ __launch_bounds__(kT) void k_area(const uint32_t *__restrict__ aw,
                                                       const uint32_t *__restrict__ aw_hi,
                                                       const unsigned long long *__restrict__ blk, int W, int H,
                                                       AreaArgs A) {
@@ -361,18 +375,22 @@ __global__ __launch_bounds__(kAreaBlock) void k_area(const uint32_t *__restrict_
     __shared__ uint32_t s_key[kU16 ? kHash : 1];
     __shared__ unsigned long long s_val[kU16 ? (kWide ? 2 * kHash : kHash) : 1];
     if (kNU8 > 0)
-        for (int k = threadIdx.x; k < kBinRows * 256; k += kAreaBlock) s_bins[k] = 0ull;
+        for (int k = threadIdx.x; k < kBinRows * 256; k += kT) s_bins[k] = 0ull;
     if (kU16) {
-        for (int k = threadIdx.x; k < kHash; k += kAreaBlock) s_key[k] = kEmptyKey;
-        for (int k = threadIdx.x; k < (kWide ? 2 * kHash : kHash); k += kAreaBlock) s_val[k] = 0ull;
+        for (int k = threadIdx.x; k < kHash; k += kT) s_key[k] = kEmptyKey;
+        for (int k = threadIdx.x; k < (kWide ? 2 * kHash : kHash); k += kT) s_val[k] = 0ull;
     }
     __syncthreads();
     const Bins<kWide> bins{s_bins, kNU8, s_key, s_val, &A};
     const int lane = threadIdx.x & 63;
     const int chunks = (int)ceil_div(W, kChunk), rblocks = (int)ceil_div(H, kRows);
     const int64_t units = (int64_t)chunks * rblocks;
-    for (int64_t u = (int64_t)blockIdx.x * kAreaWaves + (threadIdx.x >> 6); u < units;
-         u += (int64_t)gridDim.x * kAreaWaves) {
+    constexpr int kWaves = kT / 64;
+    // two u8 layers per request group at 8 waves per workgroup (several
+    // workgroups per CU), four at 16 (one per CU)
+    constexpr int kG = kT == 512 ? 2 : 4;
+    for (int64_t u = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); u < units;
+         u += (int64_t)gridDim.x * kWaves) {
         const int c = (int)(u % chunks), rb = (int)(u / chunks);
         const int col = c * kChunk + lane * kCols;
         const int ncol = W - col < kCols ? (W - col > 0 ? W - col : 0) : kCols;
@@ -386,14 +404,14 @@ __global__ __launch_bounds__(kAreaBlock) void k_area(const uint32_t *__restrict_
                 area_unit_blk<kNU8, kU16, kRows>(A, bins, aw, blk, t0, W,
                                                  (int64_t)rb * ((W + kCols - 1) / kCols) + col / kCols);
             else
-                area_unit<true, kNU8, kU16, kWide, kRows>(A, bins, aw, aw_hi, t0, W, nrows, ncol, vec);
+                area_unit<true, kNU8, kU16, kWide, kRows, kG>(A, bins, aw, aw_hi, t0, W, nrows, ncol, vec);
         }
-        else area_unit<false, kNU8, kU16, kWide, kRows>(A, bins, aw, aw_hi, t0, W, nrows, ncol, vec);
+        else area_unit<false, kNU8, kU16, kWide, kRows, kG>(A, bins, aw, aw_hi, t0, W, nrows, ncol, vec);
     }
     __syncthreads();
     if (kNU8 > 0)
         for (int row = 0; row < A.nu8; ++row)
-            for (int k = threadIdx.x; k < 256; k += kAreaBlock) {
+            for (int k = threadIdx.x; k < 256; k += kT) {
                 const unsigned long long v = s_bins[row * 256 + k];
                 if (v) atomicAdd(A.bins[row] + k, v);
                 if constexpr (kWide) {
@@ -402,7 +420,7 @@ __global__ __launch_bounds__(kAreaBlock) void k_area(const uint32_t *__restrict_
                 }
             }
     if (kU16)
-        for (int k = threadIdx.x; k < kHash; k += kAreaBlock) {
+        for (int k = threadIdx.x; k < kHash; k += kT) {
             const uint32_t key = s_key[k];
             if (key == kEmptyKey) continue;
             const int l = (int)(key >> 16);
@@ -412,24 +430,31 @@ __global__ __launch_bounds__(kAreaBlock) void k_area(const uint32_t *__restrict_
         }
 }
 
-// Workgroups: one per CU at most, fewer when there are few units.
+// Workgroups (area_threads): of 512 threads, three per CU at most (two are
+// resident at the kernel's register use, the third takes up the slack of
+// uneven units), or of 1024 threads, one per CU; fewer when there are few
+// units.  The block-sum path keeps 1024 threads.
 // blk: per-block area sums (one-word weights only), or null.
 template <int kNU8, bool kU16, bool kWide>
 void launch_area(hipStream_t s, const uint32_t *aw, const uint32_t *aw_hi, const unsigned long long *blk, int W,
                  int H, const AreaArgs &A) {
     constexpr int kRows = kWide ? 2 : 4;   // two-word weights: half the rows, the same registers
     const int64_t units = ceil_div(W, kChunk) * ceil_div(H, kRows);
-    int64_t g = ceil_div(units, kAreaWaves * 2);
-    if (g > 256) g = 256;
-    if (g < 1) g = 1;
+    constexpr int kT = area_threads(kNU8, kU16, kWide);
+    auto grid = [&](int threads) {
+        int64_t g = ceil_div(units, (threads / 64) * 2);
+        const int64_t cap = threads == 512 ? 768 : 256;
+        g = g > cap ? cap : g;
+        return (unsigned)(g < 1 ? 1 : g);
+    };
     if constexpr (!kWide) {
         if (blk) {
-            hipLaunchKernelGGL((k_area<kNU8, kU16, false, kRows, true>), dim3((unsigned)g), dim3(kAreaBlock), 0, s,
+            hipLaunchKernelGGL((k_area<kNU8, kU16, false, kRows, true, 1024>), dim3(grid(1024)), dim3(1024), 0, s,
                                aw, aw_hi, blk, W, H, A);
             return;
         }
     }
-    hipLaunchKernelGGL((k_area<kNU8, kU16, kWide, kRows, false>), dim3((unsigned)g), dim3(kAreaBlock), 0, s, aw, aw_hi,
+    hipLaunchKernelGGL((k_area<kNU8, kU16, kWide, kRows, false, kT>), dim3(grid(kT)), dim3(kT), 0, s, aw, aw_hi,
                        blk, W, H, A);
 }
 
