@@ -239,6 +239,32 @@ __device__ __forceinline__ void unit_runs(const RowLabels<T> lab[kRows], int nro
                 run = Sum<kWide>();
             }
             run.add(U.tot[r]);
+        } else if constexpr (sizeof(T) == 2) {
+            // u16: a loop, so that the hash insert is inlined once per row
+            // (each inlined insert holds its probe loop's exec masks)
+#pragma unroll 1
+            for (int k = 0; k < kCols; ++k) {
+                uint32_t word = lab[r].w[0], lo = U.lo[r][0];
+#pragma unroll
+                for (int q = 1; q < kCols; ++q) {
+                    if (q / 2 != 0 && k / 2 == q / 2) word = lab[r].w[q / 2];
+                    if (k == q) lo = U.lo[r][q];
+                }
+                const uint32_t lk = (word >> (16 * (k & 1))) & 0xffffu;
+                if (lk != cur) {
+                    if (run.nonzero()) add(cur, run);
+                    cur = lk;
+                    run = Sum<kWide>();
+                }
+                run.lo += lo;
+                if constexpr (kWide) {
+                    uint32_t hi = U.hi[r][0];
+#pragma unroll
+                    for (int q = 1; q < kCols; ++q)
+                        if (k == q) hi = U.hi[r][q];
+                    run.hi += hi;
+                }
+            }
         } else {
 #pragma unroll
             for (int k = 0; k < kCols; ++k) {
